@@ -1,0 +1,415 @@
+/*
+ * lp_oracle.c -- plain FP64 reference for Lagrangian RK4 advection on rectilinear
+ * grids.  TEST INFRASTRUCTURE ONLY: it is built and called by the tests, the smoke
+ * check and the CPU-baseline leg of the benchmark, never by the product library.
+ * It shares no source with the HIP path.  Compiled with -O2 -ffp-contract=off so
+ * every product and sum is rounded exactly where it is written.
+ *
+ * What it follows (Lange & van Sebille, Parcels v0.9):
+ *   - the trajectory equation, Eq. (1), integrated with the classical fourth-order
+ *     Runge-Kutta scheme (Sect. 2.1.1, the default integrator);
+ *   - field sampling fieldset.F[time, lon, lat, depth] (Sect. 2.1.2) done as linear
+ *     interpolation in space and linear interpolation in time, on grids whose axes
+ *     depend on lon only, lat only or depth only (Sect. 2.3, Sect. 2.4);
+ *   - conversion of m/s to degrees/s on a spherical mesh (Sect. 4.2.2);
+ *   - per-particle error states handled by recovery (delete on leaving the
+ *     domain, Sect. 2.1.2 and Sect. 3.3);
+ *   - a Brownian displacement with uniform Kh (the behaviour term of Eq. (1),
+ *     Sect. 2.1.2 and Sect. 4.2.7), drawn with Philox4x32-10 (Salmon et al.,
+ *     "Parallel random numbers: as easy as 1, 2, 3", SC'11).
+ *
+ * Readings where the paper is silent (each one is listed with its reason in the
+ * design notes): classical RK4 tableau; lower-cell rule at a node with the last
+ * node in the last cell; space first, then time; metres per degree 1852*60;
+ * cos(lat) taken at each stage point; a step is rejected whole if any stage
+ * point or the end point leaves the domain; a land cell has four land corners.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stddef.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OR_ST_OOB 1u
+#define OR_ST_LAND 2u
+#define OR_ST_DELETED 4u
+
+#define OR_OK 0
+#define OR_EINVAL (-1)
+#define OR_ETIME (-4)
+
+/* metres per degree (one nautical mile per arc minute) and degrees to radians */
+static const double OR_M = 111120.0;
+static const double OR_D = 0.017453292519943295;
+
+typedef struct {
+    int nx, ny, nz;          /* nz = 0: two-dimensional field set */
+    const double *X, *Y, *Z; /* strictly increasing axes */
+    int spherical;
+    int nt;
+    const double *T;         /* snapshot times, strictly increasing */
+    double period;           /* > 0: the snapshots repeat with this period */
+    int stored_f32;          /* 1: U, V, W hold float; 0: double */
+    const void *U, *V, *W;   /* [nt][max(nz,1)][ny][nx], i fastest */
+    const unsigned char *land; /* [ny][nx] node mask (1 = land) or NULL */
+} or_fieldset;
+
+typedef struct {
+    int policy;              /* 0: delete on error, 1: freeze on error */
+    double Kh;               /* horizontal diffusivity, 0 = no Brownian term */
+    uint32_t run_id, seed;   /* Philox key */
+} or_options;
+
+/* ---------------------------------------------------------------- cell search */
+/* Locate x on axis X[0..n-1]: returns 1 if x is NaN or outside [X0, X(n-1)];
+ * otherwise idx = the largest i in [0, n-2] with X[i] <= x and
+ * frac = (x - X[i]) / (X[i+1] - X[i]).  A point on the last node is in the last
+ * cell with frac = 1. */
+int or_locate(double x, const double *X, int n, int *idx, double *frac)
+{
+    if (x != x || x < X[0] || x > X[n - 1])
+        return 1;
+    int lo = 0, hi = n - 2;
+    while (lo < hi) {
+        int mid = lo + (hi - lo + 1) / 2;
+        if (X[mid] <= x)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    *idx = lo;
+    *frac = (x - X[lo]) / (X[lo + 1] - X[lo]);
+    return 0;
+}
+
+static double rd(const or_fieldset *fs, const void *F, size_t off)
+{
+    if (fs->stored_f32)
+        return (double)((const float *)F)[off];
+    return ((const double *)F)[off];
+}
+
+/* bilinear interpolation on level k of snapshot s: the four corner weights times
+ * the corner values, products evaluated first, then summed left to right */
+static double bilinear(const or_fieldset *fs, const void *F, int s, int k,
+                       int i, int j, double xi, double eta)
+{
+    size_t nx = (size_t)fs->nx, ny = (size_t)fs->ny;
+    size_t nzl = fs->nz > 0 ? (size_t)fs->nz : 1;
+    size_t base = (((size_t)s * nzl) + (size_t)k) * ny * nx;
+    double f00 = rd(fs, F, base + (size_t)j * nx + (size_t)i);
+    double f10 = rd(fs, F, base + (size_t)j * nx + (size_t)i + 1);
+    double f11 = rd(fs, F, base + ((size_t)j + 1) * nx + (size_t)i + 1);
+    double f01 = rd(fs, F, base + ((size_t)j + 1) * nx + (size_t)i);
+    double p0 = ((1.0 - xi) * (1.0 - eta)) * f00;
+    double p1 = (xi * (1.0 - eta)) * f10;
+    double p2 = (xi * eta) * f11;
+    double p3 = ((1.0 - xi) * eta) * f01;
+    return ((p0 + p1) + p2) + p3;
+}
+
+typedef struct {
+    int i, j, k;
+    double xi, eta, zeta;
+} or_cell;
+
+static double spatial(const or_fieldset *fs, const void *F, int s, const or_cell *c)
+{
+    if (fs->nz <= 0)
+        return bilinear(fs, F, s, 0, c->i, c->j, c->xi, c->eta);
+    double lo = bilinear(fs, F, s, c->k, c->i, c->j, c->xi, c->eta);
+    double hi = bilinear(fs, F, s, c->k + 1, c->i, c->j, c->xi, c->eta);
+    return (1.0 - c->zeta) * lo + c->zeta * hi;
+}
+
+/* ---------------------------------------------------------------- time bracket */
+/* Bracketing snapshots for time t.  nt == 1: steady (s0 = s1 = 0, tau = 0).
+ * Periodic: t is first mapped into [T0, T0 + period) and the snapshot after the
+ * last one is the first one again, at T0 + period.  Otherwise t must lie in
+ * [T0, T(nt-1)]. */
+int or_time_bracket(const or_fieldset *fs, double t, int *s0, int *s1, double *tau)
+{
+    const double *T = fs->T;
+    int nt = fs->nt;
+    if (nt == 1) {
+        *s0 = 0;
+        *s1 = 0;
+        *tau = 0.0;
+        return OR_OK;
+    }
+    if (fs->period > 0.0) {
+        double r = fmod(t - T[0], fs->period);
+        if (r < 0.0)
+            r += fs->period;
+        double tp = T[0] + r;
+        int s = 0;
+        for (int q = 0; q < nt; q++)
+            if (T[q] <= tp)
+                s = q;
+        double tnext = (s + 1 < nt) ? T[s + 1] : T[0] + fs->period;
+        *s0 = s;
+        *s1 = (s + 1 < nt) ? s + 1 : 0;
+        *tau = (tp - T[s]) / (tnext - T[s]);
+        return OR_OK;
+    }
+    if (t != t || t < T[0] || t > T[nt - 1])
+        return OR_ETIME;
+    int s = 0;
+    for (int q = 0; q <= nt - 2; q++)
+        if (T[q] <= t)
+            s = q;
+    *s0 = s;
+    *s1 = s + 1;
+    *tau = (t - T[s]) / (T[s + 1] - T[s]);
+    return OR_OK;
+}
+
+/* ---------------------------------------------------------------- sampling */
+/* Velocity at (x, y, z, t) in coordinate units per second.  Returns 1 if the
+ * point is outside the grid (the caller has checked t). */
+int or_sample(const or_fieldset *fs, double x, double y, double z, double t, double out[3])
+{
+    or_cell c = {0, 0, 0, 0.0, 0.0, 0.0};
+    if (or_locate(x, fs->X, fs->nx, &c.i, &c.xi))
+        return 1;
+    if (or_locate(y, fs->Y, fs->ny, &c.j, &c.eta))
+        return 1;
+    if (fs->nz > 0 && or_locate(z, fs->Z, fs->nz, &c.k, &c.zeta))
+        return 1;
+    int s0, s1;
+    double tau;
+    if (or_time_bracket(fs, t, &s0, &s1, &tau) != OR_OK)
+        return 2;
+    double u, v, w = 0.0;
+    if (fs->nt == 1) {
+        u = spatial(fs, fs->U, 0, &c);
+        v = spatial(fs, fs->V, 0, &c);
+        if (fs->nz > 0)
+            w = spatial(fs, fs->W, 0, &c);
+    } else {
+        u = (1.0 - tau) * spatial(fs, fs->U, s0, &c) + tau * spatial(fs, fs->U, s1, &c);
+        v = (1.0 - tau) * spatial(fs, fs->V, s0, &c) + tau * spatial(fs, fs->V, s1, &c);
+        if (fs->nz > 0)
+            w = (1.0 - tau) * spatial(fs, fs->W, s0, &c) + tau * spatial(fs, fs->W, s1, &c);
+    }
+    if (fs->spherical) {
+        out[0] = u / (OR_M * cos(y * OR_D));
+        out[1] = v / OR_M;
+    } else {
+        out[0] = u;
+        out[1] = v;
+    }
+    out[2] = w;
+    return 0;
+}
+
+/* ---------------------------------------------------------------- Philox4x32-10 */
+/* Counter-based generator of Salmon et al. (SC'11): ten rounds of the four-word
+ * Philox round, each multiplying words 0 and 2 by the two round multipliers and
+ * xoring the high halves into the other words together with the key; the key is
+ * bumped by the two Weyl constants between rounds. */
+void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; r++) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+    }
+    out[0] = c0;
+    out[1] = c1;
+    out[2] = c2;
+    out[3] = c3;
+}
+
+/* Uniform in (0, 1) from two words: the top 53 bits of (a:b) scaled by 2^-53,
+ * plus 2^-54 so that neither end is reached. */
+static double or_unit(uint32_t a, uint32_t b)
+{
+    uint64_t m = (((uint64_t)a << 32) | (uint64_t)b) >> 11;
+    return (double)m * 1.1102230246251565e-16 + 5.551115123125783e-17;
+}
+
+/* Two standard normals for (run, seed, particle, step) by Box-Muller. */
+void or_normals(uint32_t run_id, uint32_t seed, uint32_t pid, uint32_t step, double n[2])
+{
+    uint32_t ctr[4] = {pid, step, 0u, 0u};
+    uint32_t key[2] = {run_id, seed};
+    uint32_t w[4];
+    or_philox4x32_10(ctr, key, w);
+    double u1 = or_unit(w[0], w[1]);
+    double u2 = or_unit(w[2], w[3]);
+    double r = sqrt(-2.0 * log(u1));
+    double a = (2.0 * 3.141592653589793) * u2;
+    n[0] = r * cos(a);
+    n[1] = r * sin(a);
+}
+
+/* ---------------------------------------------------------------- one RK4 step */
+static int in_domain(const or_fieldset *fs, double x, double y, double z, or_cell *c)
+{
+    if (or_locate(x, fs->X, fs->nx, &c->i, &c->xi))
+        return 0;
+    if (or_locate(y, fs->Y, fs->ny, &c->j, &c->eta))
+        return 0;
+    if (fs->nz > 0 && or_locate(z, fs->Z, fs->nz, &c->k, &c->zeta))
+        return 0;
+    return 1;
+}
+
+static int land_cell(const or_fieldset *fs, int i, int j)
+{
+    const unsigned char *L = fs->land;
+    size_t nx = (size_t)fs->nx;
+    return L[(size_t)j * nx + i] && L[(size_t)j * nx + i + 1] &&
+           L[((size_t)j + 1) * nx + i] && L[((size_t)j + 1) * nx + i + 1];
+}
+
+/* Advance one particle by step n (time t_org + n dt to t_org + (n+1) dt). */
+static void rk4_step(const or_fieldset *fs, const or_options *opt, double t_org, double dt,
+                     int64_t n, uint32_t pid, double *px, double *py, double *pz,
+                     unsigned char *st)
+{
+    const int is3d = fs->nz > 0;
+    const unsigned char err_extra = opt->policy == 0 ? OR_ST_DELETED : 0;
+    double tn = t_org + (double)n * dt;
+    double th = t_org + ((double)n + 0.5) * dt;
+    double te = t_org + ((double)n + 1.0) * dt;
+    double x = *px, y = *py, z = is3d ? *pz : 0.0;
+    double hd = 0.5 * dt;
+    double k1[3], k2[3], k3[3], k4[3];
+
+    if (or_sample(fs, x, y, z, tn, k1))
+        goto out_of_bounds;
+    double x2 = x + k1[0] * hd, y2 = y + k1[1] * hd, z2 = z + k1[2] * hd;
+    if (or_sample(fs, x2, y2, z2, th, k2))
+        goto out_of_bounds;
+    double x3 = x + k2[0] * hd, y3 = y + k2[1] * hd, z3 = z + k2[2] * hd;
+    if (or_sample(fs, x3, y3, z3, th, k3))
+        goto out_of_bounds;
+    double x4 = x + k3[0] * dt, y4 = y + k3[1] * dt, z4 = z + k3[2] * dt;
+    if (or_sample(fs, x4, y4, z4, te, k4))
+        goto out_of_bounds;
+    double xs = x + ((((k1[0] + 2.0 * k2[0]) + 2.0 * k3[0]) + k4[0]) * dt) / 6.0;
+    double ys = y + ((((k1[1] + 2.0 * k2[1]) + 2.0 * k3[1]) + k4[1]) * dt) / 6.0;
+    double zs = z + ((((k1[2] + 2.0 * k2[2]) + 2.0 * k3[2]) + k4[2]) * dt) / 6.0;
+
+    if (opt->Kh > 0.0) {
+        double nn[2];
+        or_normals(opt->run_id, opt->seed, pid, (uint32_t)n, nn);
+        double sig = sqrt(2.0 * opt->Kh * dt);
+        double dx = sig * nn[0], dy = sig * nn[1];
+        if (fs->spherical) {
+            dx = dx / (OR_M * cos(ys * OR_D));
+            dy = dy / OR_M;
+        }
+        xs = xs + dx;
+        ys = ys + dy;
+    }
+
+    or_cell c;
+    if (!in_domain(fs, xs, ys, zs, &c))
+        goto out_of_bounds;
+    if (fs->land && land_cell(fs, c.i, c.j)) {
+        *st = (unsigned char)(OR_ST_LAND | err_extra);
+        return;
+    }
+    *px = xs;
+    *py = ys;
+    if (is3d)
+        *pz = zs;
+    return;
+
+out_of_bounds:
+    *st = (unsigned char)(OR_ST_OOB | err_extra);
+}
+
+/* Check that every stage time of steps step0 .. step0+nsteps-1 has snapshots. */
+static int check_time(const or_fieldset *fs, double t_org, double dt, int64_t step0, int64_t nsteps)
+{
+    if (fs->nt == 1 || fs->period > 0.0)
+        return OR_OK;
+    double ta = t_org + (double)step0 * dt;
+    double tb = t_org + (double)(step0 + nsteps) * dt;
+    double lo = ta < tb ? ta : tb, hi = ta < tb ? tb : ta;
+    if (lo < fs->T[0] || hi > fs->T[fs->nt - 1])
+        return OR_ETIME;
+    return OR_OK;
+}
+
+/* Advance n particles through steps step0 .. step0+nsteps-1.  Particles with a
+ * nonzero status are not advanced.  *psteps is increased by the number of
+ * (particle, step) pairs that started active.  Returns OR_ETIME if the run needs
+ * a time outside the snapshots (nothing is changed then). */
+int or_advance(const or_fieldset *fs, int64_t n, double *x, double *y, double *z,
+               unsigned char *status, const uint32_t *pid, double t_org, double dt,
+               int64_t step0, int64_t nsteps, const or_options *opt, int64_t *psteps,
+               int nthreads)
+{
+    if (dt == 0.0 || nsteps < 0 || n < 0)
+        return OR_EINVAL;
+    if (check_time(fs, t_org, dt, step0, nsteps) != OR_OK)
+        return OR_ETIME;
+    int64_t total = 0;
+#ifdef _OPENMP
+    if (nthreads <= 0)
+        nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(static) num_threads(nthreads) reduction(+ : total)
+#endif
+    for (int64_t p = 0; p < n; p++) {
+        int64_t active = 0;
+        for (int64_t q = 0; q < nsteps; q++) {
+            if (status[p])
+                break;
+            active++;
+            rk4_step(fs, opt, t_org, dt, step0 + q, pid[p], &x[p], &y[p],
+                     z ? &z[p] : NULL, &status[p]);
+        }
+        total += active;
+    }
+    if (psteps)
+        *psteps += total;
+    return OR_OK;
+}
+
+/* Cell indices (O1 rule) of n positions; -1 on every axis for a point outside. */
+void or_cell_indices(const or_fieldset *fs, int64_t n, const double *x, const double *y,
+                     const double *z, int32_t *ci, int32_t *cj, int32_t *ck)
+{
+    for (int64_t p = 0; p < n; p++) {
+        or_cell c = {0, 0, 0, 0.0, 0.0, 0.0};
+        if (in_domain(fs, x[p], y[p], z ? z[p] : 0.0, &c)) {
+            ci[p] = c.i;
+            cj[p] = c.j;
+            if (ck)
+                ck[p] = fs->nz > 0 ? c.k : 0;
+        } else {
+            ci[p] = -1;
+            cj[p] = -1;
+            if (ck)
+                ck[p] = -1;
+        }
+    }
+}
+
+int or_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
