@@ -1,0 +1,161 @@
+#!/usr/bin/env python3
+"""Benchmark of the RK4 advection hot path on one MI355X.
+
+Workload (default): 2D time-varying eddy field on the global 0.25 degree grid
+(1440 x 720), 30 daily float32 U, V snapshots (periodic, 30% land), 1,000,000
+particles seeded in ocean cells, RK4 with dt = 300 s for 30 days (8640 steps),
+daily output records of every particle, delete on leaving the grid or landing.
+One benchmark step is that whole 30-day run (sort, advection, compaction and
+records), with the field snapshots and start positions already in HBM.
+
+Prints one JSON line: particle-steps/s, the roofline of the dominant kernel
+(measured with HIP events on the launch stream) and the FP64 oracle timed on the
+host cores on a bounded sample of the same workload.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector (FMA = 2 flops)
+
+# Algorithmic cost of one 2D spherical RK4 particle-step with linear time
+# interpolation (see the design notes): bytes of the four-corner stencil of U, V
+# at two snapshots in float32, and FP64 flops of the method (cos excluded,
+# a division counted as one flop).
+STENCIL_BYTES_2D_F32 = 4 * 2 * 2 * 4     # 64 B
+STATE_BYTES_2D = 8 + 8 + 8 + 8 + 4 + 1 + 1  # lon, lat read + write, order id, status r/w
+FLOPS_2D_STEP = 234
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=3)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--particles", type=int, default=1_000_000)
+    p.add_argument("--days", type=int, default=30)
+    p.add_argument("--dtype", default="f32", choices=["f32", "bf16", "f16s"])
+    p.add_argument("--output-stride", type=int, default=1)
+    p.add_argument("--sort-every", type=int, default=1)
+    p.add_argument("--cpu-baseline", type=int, default=1)
+    p.add_argument("--cpu-sample-stride", type=int, default=100)
+    return p.parse_args()
+
+
+def cpu_baseline(w, stride: int):
+    """The FP64 oracle, as it stands, on every `stride`-th particle of the same
+    workload for the full run, on all host cores."""
+    from oracle import oracle as O
+    ids = np.arange(0, w.n, stride)
+    ofs = O.OracleFieldSet.from_workload(w)
+    st = O.make_state(w.lon0[ids], w.lat0[ids], pid=ids.astype(np.uint32))
+    threads = O.max_threads()
+    t = time.perf_counter()
+    rc = O.advance(ofs, st, w.dt, w.nsteps, nthreads=threads)
+    el = time.perf_counter() - t
+    assert rc == 0
+    return dict(value=st.psteps / el, unit="particle-steps/s", cores=threads, kind="oracle",
+                sample=f"every {stride}th particle ({ids.size}) for the full {w.nsteps} steps, "
+                       f"{st.psteps} particle-steps in {el:.2f} s")
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": a.gpus}))
+        sys.exit(2)
+    import torch
+    from paper_1707_05163_amd import FieldSet, ParticleSet
+    from synthetic import configs as SC
+
+    torch.cuda.set_device(0)
+    nsteps = a.days * 288
+    w = SC.cfg1_global_eddies(n_particles=a.particles, nsteps=nsteps)
+    print(f"[bench] workload {w.name}: {w.n} particles x {w.nsteps} steps, "
+          f"{w.fields.nt} snapshots {w.grid.nx}x{w.grid.ny}", file=sys.stderr, flush=True)
+    fs = FieldSet.from_workload(w, dtype=a.dtype)
+    lon0 = torch.from_numpy(w.lon0).cuda()
+    lat0 = torch.from_numpy(w.lat0).cuda()
+    stream = torch.cuda.current_stream()
+    psets = [ParticleSet(fs, lon0, lat0, stream=stream) for _ in range(a.warmup + a.steps)]
+    torch.cuda.synchronize()
+    runtime = w.nsteps * w.dt
+
+    def step(ps, profile):
+        ps.execute(runtime, w.dt, w.outputdt, output_stride=a.output_stride,
+                   sort_every=a.sort_every, profile=profile, stream=stream)
+
+    for i in range(a.warmup):
+        step(psets[i], False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(a.steps):
+        step(psets[a.warmup + i], True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+
+    psteps = 0
+    kms = 0.0
+    launches = 0
+    for ps in psets[a.warmup:]:
+        c, _ = ps.status()
+        psteps += c["particle_steps"]
+        ms, k = ps.timing()
+        kms += ms
+        launches += k
+    rate = psteps / el
+    avg_launch_s = kms / 1e3 / launches
+    steps_per_launch = psteps / launches
+    S = w.outputdt / w.dt
+    bytes_per_step = STENCIL_BYTES_2D_F32 * (0.5 if a.dtype != "f32" else 1.0) + STATE_BYTES_2D / S
+    hbm_ach = steps_per_launch * bytes_per_step / avg_launch_s / 1e9
+    alu_ach = steps_per_launch * FLOPS_2D_STEP / avg_launch_s / 1e12
+    hbm = {"bound": "hbm", "achieved": round(hbm_ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(hbm_ach / HBM_PEAK_GBS, 4), "traffic": None}
+    alu = {"bound": "alu", "achieved": round(alu_ach, 3), "peak": FP64_VECTOR_PEAK_TFLOPS,
+           "unit": "TFLOP/s", "frac": round(alu_ach / FP64_VECTOR_PEAK_TFLOPS, 4), "traffic": None}
+    roof, other = (hbm, alu) if hbm["frac"] >= alu["frac"] else (alu, hbm)
+    out = {
+        "metric": "RK4 particle-steps/s",
+        "value": rate,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": el / a.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if a.dtype == "f32" else "f64+" + a.dtype,
+        "data": "synthetic",
+        "config": {"workload": w.name, "grid": f"{w.grid.nx}x{w.grid.ny}", "snapshots": w.fields.nt,
+                   "particles": w.n, "rk4_steps": w.nsteps, "dt_s": w.dt,
+                   "field_dtype": a.dtype, "output_stride": a.output_stride,
+                   "sort_every": a.sort_every},
+        "roofline": roof,
+        "roofline_other": other,
+        "kernel": {"name": "k_advect", "launches": launches,
+                   "avg_launch_ms": round(avg_launch_s * 1e3, 4),
+                   "particle_steps_per_launch": steps_per_launch,
+                   "kernel_share_of_step": round(kms / 1e3 / el, 4)},
+    }
+    if a.cpu_baseline:
+        print("[bench] timing the FP64 oracle on the host", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(w, a.cpu_sample_stride)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

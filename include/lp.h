@@ -1,0 +1,179 @@
+/*
+ * lp.h -- C ABI of the MI355X Lagrangian particle advection library.
+ *
+ * The interface follows the statement of the problem in Lange & van Sebille,
+ * "Parcels v0.9" (GMD 2017):
+ *   - a FieldSet of gridded Fields with time snapshots on a rectilinear grid
+ *     (Sect. 2.4; read three time slices at a time and advanced, Sect. 3.1 and
+ *     Sect. 3.4);
+ *   - a ParticleSet created from longitude / latitude (/ depth) arrays
+ *     (Sect. 2.1, Sect. 3.2);
+ *   - pset.execute(kernel, runtime, dt, output interval, recovery), the dynamic
+ *     update loop of Sect. 2.2 and Sect. 3.4, with per-particle error states
+ *     mapped to a recovery action (Sect. 2.1.2);
+ *   - the AdvectionRK4 / AdvectionRK4_3D kernels (Sect. 2.1.1, Sect. 3.3), with
+ *     linear interpolation in space and time (Sect. 2.3, Sect. 2.4) and the
+ *     m/s -> degree/s conversion on spherical meshes (Sect. 4.2.2).
+ *
+ * Conventions for every call:
+ *   - return value: LP_OK (0) or a negative LP_E* code; lp_last_error() then
+ *     returns a message (thread-local, valid until the next failing call on the
+ *     same thread).  Per-particle problems are never return codes: they are
+ *     status bits (LP_ST_*), as the paper maps particle errors to recovery
+ *     kernels.
+ *   - host arrays are owned by the caller and only read (or written) during the
+ *     call; "_device" variants take device pointers on the library's GPU, which
+ *     the caller keeps valid until the stream reaches the copy.
+ *   - the library owns every device buffer it allocates; *_destroy frees them.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Calls that return data to the host synchronise that stream.
+ *   - all positions are FP64; longitudes/latitudes in degrees on a spherical
+ *     mesh, metres on a flat mesh; depth in metres, positive downward.
+ */
+#ifndef LP_H
+#define LP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define LP_OK 0
+#define LP_EINVAL (-1)  /* bad argument: sizes, non-monotone axes, dt not dividing */
+#define LP_ENOMEM (-2)  /* device or pinned host allocation failed */
+#define LP_EDEVICE (-3) /* a HIP runtime call failed */
+#define LP_ETIME (-4)   /* a needed time is not covered by the resident snapshots */
+#define LP_ESTATE (-5)  /* call not allowed in the current state */
+
+/* mesh */
+#define LP_MESH_FLAT 0
+#define LP_MESH_SPHERICAL 1
+
+/* device storage type of the field snapshots */
+#define LP_F64 0        /* double values, FP64 interpolation */
+#define LP_F32 1        /* float values, FP64 interpolation */
+#define LP_BF16 2       /* bfloat16 (round-to-nearest-even), FP32 interpolation */
+#define LP_F16_SCALED 3 /* float16 times a power-of-two scale per (variable,
+                           level, snapshot), FP32 interpolation */
+
+/* recovery policy on a particle error */
+#define LP_DELETE 0 /* error bit plus LP_ST_DELETED; the particle is removed */
+#define LP_FREEZE 1 /* error bit only; the particle stays where it was */
+
+/* particle status bits */
+#define LP_ST_OOB 1u     /* a stage point or the end point left the grid */
+#define LP_ST_LAND 2u    /* the end point fell in a cell with four land corners */
+#define LP_ST_DELETED 4u /* removed by the DELETE policy */
+
+/* integrators */
+#define LP_KERNEL_RK4 0 /* classical fourth-order Runge-Kutta (Sect. 2.1.1) */
+
+/* ------------------------------------------------------------------ FieldSet */
+typedef struct lp_fieldset lp_fieldset;
+
+typedef struct {
+    int32_t nx, ny;     /* horizontal nodes (>= 2 each) */
+    int32_t nz;         /* 0: two-dimensional (U, V); >= 2: levels (U, V, W) */
+    const double *lon;  /* nx strictly increasing (degrees or metres) */
+    const double *lat;  /* ny strictly increasing */
+    const double *depth;/* nz strictly increasing, NULL when nz == 0 */
+    int32_t mesh;       /* LP_MESH_FLAT or LP_MESH_SPHERICAL */
+    int32_t dtype;      /* LP_F64, LP_F32, LP_BF16 or LP_F16_SCALED */
+    int32_t capacity;   /* device snapshot slots (>= 1); 3 keeps two resident
+                           snapshots plus one being uploaded (Sect. 3.1) */
+    double time_period; /* > 0: snapshots repeat with this period; every snapshot
+                           of the period must then stay resident */
+    const uint8_t *land;/* ny*nx node mask (1 = land), or NULL */
+} lp_grid_desc;
+
+/* Create a field set on the current device.  Copies the axes and the mask. */
+int fieldset_create(const lp_grid_desc *g, lp_fieldset **out);
+
+/* Push the snapshot at time t (advancetime, Sect. 3.4): U, V (and W when
+ * nz >= 2) are host float arrays [max(nz,1)][ny][nx], i fastest, in m/s (W
+ * positive downward).  Times must increase from push to push.  When all slots
+ * are full the oldest snapshot is replaced, after the kernels that read it have
+ * finished.  The upload and the conversion to the storage type run on the
+ * field set's own upload stream; a later pset_execute waits for them.  The
+ * host arrays may be reused when the call returns. */
+int fieldset_push_snapshot(lp_fieldset *fs, double t, const float *U, const float *V,
+                           const float *W, void *stream);
+/* Same with double host arrays (LP_F64 storage keeps them exact). */
+int fieldset_push_snapshot_f64(lp_fieldset *fs, double t, const double *U, const double *V,
+                               const double *W, void *stream);
+/* Same with float arrays already in device memory (no host copy). */
+int fieldset_push_snapshot_device(lp_fieldset *fs, double t, const float *dU, const float *dV,
+                                  const float *dW, void *stream);
+/* Number of snapshots currently resident and their times (times may be NULL). */
+int fieldset_resident(const lp_fieldset *fs, int32_t *count, double *times);
+void fieldset_destroy(lp_fieldset *fs);
+
+/* ---------------------------------------------------------------- ParticleSet */
+typedef struct lp_pset lp_pset;
+
+/* Create n particles from host arrays (depth NULL in 2D).  Particle p has id p.
+ * Time is t0 + k*dt after k steps; step0 is the number of steps already taken
+ * from t0 (so a set can be resumed exactly from pset_get output) and is also
+ * the step index that keys the Brownian random numbers. */
+int pset_create(lp_fieldset *fs, int64_t n, const double *lon, const double *lat,
+                const double *depth, double t0, int64_t step0, lp_pset **out);
+/* Same with device arrays (copied into the set's own buffers on `stream`). */
+int pset_create_device(lp_fieldset *fs, int64_t n, const double *dlon, const double *dlat,
+                       const double *ddepth, double t0, int64_t step0, void *stream,
+                       lp_pset **out);
+
+typedef struct {
+    int32_t kernel;       /* LP_KERNEL_RK4 */
+    int32_t recovery;     /* LP_DELETE or LP_FREEZE */
+    double Kh;            /* > 0: add a Brownian displacement sqrt(2 Kh dt) N(0,1)
+                             per horizontal component after each step (Sect. 4.2.7) */
+    uint32_t run_id, seed;/* Philox4x32-10 key (run_id, seed); counter (id, step) */
+    int32_t output_stride;/* record every k-th particle id at each output time;
+                             0 = no records */
+    int32_t sort_every;   /* re-sort particles by grid tile every k output
+                             segments (0 = never) */
+    int32_t profile;      /* 1: time each advection launch with HIP events */
+} lp_exec_opts;
+
+/* Advance every active particle by runtime/dt steps of dt (dt > 0), taking an
+ * output record every outputdt (0 = only at the end).  dt must divide runtime
+ * and outputdt.  The first execute of a set also records the start time.
+ * Asynchronous on `stream`; returns LP_ETIME before launching anything if a
+ * stage time is not covered by the resident snapshots. */
+int pset_execute(lp_pset *ps, double runtime, double dt, double outputdt,
+                 const lp_exec_opts *opts, void *stream);
+
+typedef struct {
+    int64_t n, active, oob, land, deleted;
+    int64_t particle_steps; /* (particle, step) pairs that started active */
+    double time;            /* current time */
+    int64_t step;           /* steps taken since t0 */
+} lp_counts;
+
+/* Counts (and, if status != NULL, the n status bytes in id order).  Syncs. */
+int pset_status(lp_pset *ps, lp_counts *c, uint8_t *status);
+/* Positions and cell indices (-1 outside the grid) in id order; any output
+ * pointer may be NULL.  Synchronises. */
+int pset_get(lp_pset *ps, double *lon, double *lat, double *depth, int32_t *ci, int32_t *cj,
+             int32_t *ck);
+/* Output records: *nrec records of *nper = ceil(n / output_stride) particles
+ * (ids 0, k, 2k, ...), record-major.  Call with NULL arrays to get the sizes.
+ * Synchronises. */
+int pset_records(lp_pset *ps, int64_t *nrec, int64_t *nper, double *lon, double *lat,
+                 double *depth, uint8_t *status, int32_t *ci, int32_t *cj, int32_t *ck);
+/* Sum and count of the timed advection launches since the last call (needs
+ * opts.profile = 1).  Synchronises. */
+int pset_timing(lp_pset *ps, double *kernel_ms, int64_t *launches);
+void pset_destroy(lp_pset *ps);
+
+const char *lp_last_error(void);
+/* Library version string. */
+const char *lp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LP_H */

@@ -1,0 +1,14 @@
+"""MI355X-native Lagrangian particle advection (HIP kernels for gfx950 behind a C ABI).
+
+``FieldSet`` and ``ParticleSet`` load the in-tree HIP library on first use and raise
+ImportError if it has not been built; nothing here computes on the CPU.
+"""
+
+__all__ = ["FieldSet", "ParticleSet", "SEED"]
+
+
+def __getattr__(name):
+    if name in __all__:
+        from . import core
+        return getattr(core, name)
+    raise AttributeError(name)

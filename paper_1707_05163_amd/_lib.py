@@ -1,0 +1,98 @@
+"""ctypes declarations of the C ABI in include/lp.h (argument marshalling only).
+
+Importing this module loads the in-tree HIP library ``_lp_hip.so``; it raises
+ImportError if the library has not been built.  There is no CPU fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "_lp_hip.so")
+
+LP_OK, LP_EINVAL, LP_ENOMEM, LP_EDEVICE, LP_ETIME, LP_ESTATE = 0, -1, -2, -3, -4, -5
+LP_MESH_FLAT, LP_MESH_SPHERICAL = 0, 1
+LP_F64, LP_F32, LP_BF16, LP_F16_SCALED = 0, 1, 2, 3
+LP_DELETE, LP_FREEZE = 0, 1
+LP_ST_OOB, LP_ST_LAND, LP_ST_DELETED = 1, 2, 4
+LP_KERNEL_RK4 = 0
+
+# every function declared in include/lp.h
+EXPORTS = (
+    "fieldset_create", "fieldset_push_snapshot", "fieldset_push_snapshot_f64",
+    "fieldset_push_snapshot_device", "fieldset_resident", "fieldset_destroy",
+    "pset_create", "pset_create_device", "pset_execute", "pset_status", "pset_get",
+    "pset_records", "pset_timing", "pset_destroy", "lp_last_error", "lp_version",
+)
+
+
+class lp_grid_desc(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("lon", C.c_void_p), ("lat", C.c_void_p), ("depth", C.c_void_p),
+                ("mesh", C.c_int32), ("dtype", C.c_int32), ("capacity", C.c_int32),
+                ("time_period", C.c_double), ("land", C.c_void_p)]
+
+
+class lp_exec_opts(C.Structure):
+    _fields_ = [("kernel", C.c_int32), ("recovery", C.c_int32), ("Kh", C.c_double),
+                ("run_id", C.c_uint32), ("seed", C.c_uint32), ("output_stride", C.c_int32),
+                ("sort_every", C.c_int32), ("profile", C.c_int32)]
+
+
+class lp_counts(C.Structure):
+    _fields_ = [("n", C.c_int64), ("active", C.c_int64), ("oob", C.c_int64),
+                ("land", C.c_int64), ("deleted", C.c_int64), ("particle_steps", C.c_int64),
+                ("time", C.c_double), ("step", C.c_int64)]
+
+
+class LPError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"lp error {code}: {msg}")
+        self.code = code
+
+
+def _declare(L):
+    P = C.c_void_p
+    I = C.c_int
+    pp = C.POINTER(C.c_void_p)
+    sig = {
+        "fieldset_create": ([C.POINTER(lp_grid_desc), pp], I),
+        "fieldset_push_snapshot": ([P, C.c_double, P, P, P, P], I),
+        "fieldset_push_snapshot_f64": ([P, C.c_double, P, P, P, P], I),
+        "fieldset_push_snapshot_device": ([P, C.c_double, P, P, P, P], I),
+        "fieldset_resident": ([P, C.POINTER(C.c_int32), P], I),
+        "fieldset_destroy": ([P], None),
+        "pset_create": ([P, C.c_int64, P, P, P, C.c_double, C.c_int64, pp], I),
+        "pset_create_device": ([P, C.c_int64, P, P, P, C.c_double, C.c_int64, P, pp], I),
+        "pset_execute": ([P, C.c_double, C.c_double, C.c_double, C.POINTER(lp_exec_opts), P], I),
+        "pset_status": ([P, C.POINTER(lp_counts), P], I),
+        "pset_get": ([P, P, P, P, P, P, P], I),
+        "pset_records": ([P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), P, P, P, P, P, P, P], I),
+        "pset_timing": ([P, C.POINTER(C.c_double), C.POINTER(C.c_int64)], I),
+        "pset_destroy": ([P], None),
+        "lp_last_error": ([], C.c_char_p),
+        "lp_version": ([], C.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    return L
+
+
+def load():
+    if not os.path.exists(LIBPATH):
+        raise ImportError(f"HIP library not built: {LIBPATH} is missing "
+                          "(run __graft_entry__.build())")
+    return _declare(C.CDLL(LIBPATH))
+
+
+lib = load()
+
+
+def check(rc: int):
+    if rc != LP_OK:
+        raise LPError(rc, lib.lp_last_error().decode())
+    return rc

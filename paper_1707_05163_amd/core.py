@@ -1,0 +1,202 @@
+"""FieldSet / ParticleSet wrappers over the C ABI, named after the paper's API
+(Sect. 2.1, Sect. 3).  Argument marshalling only: every step of the advection
+runs in the HIP library.  Host arrays are numpy; device arrays are torch CUDA
+tensors (torch provides device memory and the stream handle)."""
+
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional
+
+import numpy as np
+
+from . import _lib as L
+
+SEED = 0x17070516
+_DTYPES = {"f64": L.LP_F64, "f32": L.LP_F32, "bf16": L.LP_BF16, "f16s": L.LP_F16_SCALED}
+_MESH = {"flat": L.LP_MESH_FLAT, "spherical": L.LP_MESH_SPHERICAL}
+_RECOVERY = {"delete": L.LP_DELETE, "freeze": L.LP_FREEZE}
+
+
+def _is_torch(a) -> bool:
+    return type(a).__module__.startswith("torch")
+
+
+def _stream(stream):
+    if stream is None:
+        try:
+            import torch
+            if torch.cuda.is_available():
+                return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+        except ImportError:
+            pass
+        return None
+    if hasattr(stream, "cuda_stream"):
+        return C.c_void_p(stream.cuda_stream)
+    return C.c_void_p(int(stream))
+
+
+def _host(a, dtype):
+    return None if a is None else np.ascontiguousarray(a, dtype=dtype)
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if _is_torch(a):
+        return C.c_void_p(a.data_ptr())
+    return C.c_void_p(a.ctypes.data)
+
+
+class FieldSet:
+    """Velocity snapshots on a rectilinear lon/lat(/depth) grid held in a ring of
+    ``capacity`` device slots."""
+
+    def __init__(self, lon, lat, depth=None, mesh: str = "flat", dtype: str = "f32",
+                 capacity: int = 3, time_period: float = 0.0, land=None):
+        self._keep = [_host(lon, np.float64), _host(lat, np.float64), _host(depth, np.float64),
+                      _host(land, np.uint8)]
+        lo, la, de, ld = self._keep
+        self.nx, self.ny = lo.size, la.size
+        self.nz = 0 if de is None else de.size
+        self.dtype = dtype
+        g = L.lp_grid_desc(self.nx, self.ny, self.nz, lo.ctypes.data, la.ctypes.data,
+                           None if de is None else de.ctypes.data, _MESH[mesh], _DTYPES[dtype],
+                           int(capacity), float(time_period),
+                           None if ld is None else ld.ctypes.data)
+        h = C.c_void_p()
+        L.check(L.lib.fieldset_create(C.byref(g), C.byref(h)))
+        self._h = h
+
+    @classmethod
+    def from_workload(cls, w, dtype: str = "f32", capacity: Optional[int] = None,
+                      push: bool = True, time_period: Optional[float] = None):
+        g = w.grid
+        cap = w.fields.nt if capacity is None else capacity
+        period = w.fields.period if time_period is None else time_period
+        fs = cls(g.lon, g.lat, g.depth, "spherical" if g.spherical else "flat", dtype, cap,
+                 period, g.land)
+        if push:
+            for s in range(min(cap, w.fields.nt)):
+                fs.push_snapshot(w.fields.times[s], *w.fields.snapshot(s))
+        return fs
+
+    @property
+    def handle(self):
+        return self._h
+
+    def push_snapshot(self, t: float, U, V, W=None, stream=None):
+        """advancetime: upload the snapshot at time t into the next ring slot."""
+        if _is_torch(U):
+            L.check(L.lib.fieldset_push_snapshot_device(self._h, float(t), _ptr(U), _ptr(V),
+                                                        _ptr(W), _stream(stream)))
+            return
+        if self.dtype == "f64" and np.asarray(U).dtype == np.float64:
+            u, v, w = _host(U, np.float64), _host(V, np.float64), _host(W, np.float64)
+            L.check(L.lib.fieldset_push_snapshot_f64(self._h, float(t), _ptr(u), _ptr(v),
+                                                     _ptr(w), _stream(stream)))
+            return
+        u, v, w = _host(U, np.float32), _host(V, np.float32), _host(W, np.float32)
+        L.check(L.lib.fieldset_push_snapshot(self._h, float(t), _ptr(u), _ptr(v), _ptr(w),
+                                             _stream(stream)))
+
+    advancetime = push_snapshot
+
+    def resident(self):
+        n = C.c_int32()
+        t = np.zeros(1024)
+        L.check(L.lib.fieldset_resident(self._h, C.byref(n), t.ctypes.data))
+        return t[: n.value].copy()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            L.lib.fieldset_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class ParticleSet:
+    """Particles with FP64 positions; particle p has id p."""
+
+    def __init__(self, fieldset: FieldSet, lon, lat, depth=None, t0: float = 0.0,
+                 step0: int = 0, stream=None):
+        self.fieldset = fieldset
+        h = C.c_void_p()
+        if _is_torch(lon):
+            self.n = int(lon.numel())
+            L.check(L.lib.pset_create_device(fieldset.handle, self.n, _ptr(lon), _ptr(lat),
+                                             _ptr(depth), float(t0), int(step0),
+                                             _stream(stream), C.byref(h)))
+        else:
+            lo, la, de = _host(lon, np.float64), _host(lat, np.float64), _host(depth, np.float64)
+            self.n = int(lo.size)
+            L.check(L.lib.pset_create(fieldset.handle, self.n, _ptr(lo), _ptr(la), _ptr(de),
+                                      float(t0), int(step0), C.byref(h)))
+        self._h = h
+        self.is3d = fieldset.nz > 0
+
+    def execute(self, runtime: float, dt: float, outputdt: float = 0.0,
+                recovery: str = "delete", Kh: float = 0.0, run_id: int = 0, seed: int = SEED,
+                output_stride: int = 0, sort_every: int = 1, profile: bool = False,
+                stream=None):
+        o = L.lp_exec_opts(L.LP_KERNEL_RK4, _RECOVERY[recovery], float(Kh), int(run_id),
+                           int(seed) & 0xFFFFFFFF, int(output_stride), int(sort_every),
+                           int(bool(profile)))
+        L.check(L.lib.pset_execute(self._h, float(runtime), float(dt), float(outputdt),
+                                   C.byref(o), _stream(stream)))
+
+    def status(self):
+        c = L.lp_counts()
+        st = np.empty(self.n, np.uint8)
+        L.check(L.lib.pset_status(self._h, C.byref(c), st.ctypes.data))
+        counts = {k: getattr(c, k) for k, _ in L.lp_counts._fields_}
+        return counts, st
+
+    def get(self):
+        n = self.n
+        out = dict(lon=np.empty(n), lat=np.empty(n), ci=np.empty(n, np.int32),
+                   cj=np.empty(n, np.int32))
+        if self.is3d:
+            out["depth"] = np.empty(n)
+            out["ck"] = np.empty(n, np.int32)
+        L.check(L.lib.pset_get(self._h, _ptr(out["lon"]), _ptr(out["lat"]),
+                               _ptr(out.get("depth")), _ptr(out["ci"]), _ptr(out["cj"]),
+                               _ptr(out.get("ck"))))
+        return out
+
+    def records(self):
+        nrec, nper = C.c_int64(), C.c_int64()
+        L.check(L.lib.pset_records(self._h, C.byref(nrec), C.byref(nper), None, None, None,
+                                   None, None, None, None))
+        shape = (nrec.value, nper.value)
+        out = dict(lon=np.empty(shape), lat=np.empty(shape), status=np.empty(shape, np.uint8),
+                   ci=np.empty(shape, np.int32), cj=np.empty(shape, np.int32))
+        if self.is3d:
+            out["depth"] = np.empty(shape)
+            out["ck"] = np.empty(shape, np.int32)
+        L.check(L.lib.pset_records(self._h, C.byref(nrec), C.byref(nper), _ptr(out["lon"]),
+                                   _ptr(out["lat"]), _ptr(out.get("depth")),
+                                   _ptr(out["status"]), _ptr(out["ci"]), _ptr(out["cj"]),
+                                   _ptr(out.get("ck"))))
+        return out
+
+    def timing(self):
+        ms, k = C.c_double(), C.c_int64()
+        L.check(L.lib.pset_timing(self._h, C.byref(ms), C.byref(k)))
+        return ms.value, k.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            L.lib.pset_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

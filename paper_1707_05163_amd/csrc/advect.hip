@@ -1,0 +1,396 @@
+// advect.hip -- per-particle RK4 advection through gridded velocity snapshots.
+//
+// One particle per lane; each lane keeps its position in registers for all the
+// steps of a launch.  Every RK stage samples the velocity as in the paper's field
+// access fieldset.F[time, lon, lat, depth] (Sect. 2.1.2): find the cell on the
+// rectilinear grid (Sect. 2.4), interpolate linearly in space (bilinear in 2D,
+// trilinear in 3D; Sect. 2.3), then linearly between the two bracketing
+// snapshots (Sect. 2.4), and on a spherical mesh convert m/s to degrees/s
+// (Sect. 4.2.2).  The stages combine with the classical RK4 weights (Sect. 2.1.1,
+// Eq. 1); the Brownian term of Eq. (1) is the optional Philox kick (Sect. 4.2.7).
+// Particles that leave the grid or end in a land cell get status bits instead of
+// moving (the recovery kernels of Sect. 2.1.2).
+//
+// Storage types: LP_F64 / LP_F32 snapshots are interpolated in FP64; LP_BF16 and
+// LP_F16_SCALED snapshots are interpolated in FP32 and only the position update
+// runs in FP64.
+#include "lp_internal.h"
+
+namespace lp {
+
+namespace {
+
+constexpr uint8_t ST_OOB = 1, ST_LAND = 2, ST_DELETED = 4;
+
+// Blocks are dispatched round-robin over the 8 XCDs (block b -> XCD b % 8).  Map
+// the hardware block id so that each XCD works on one contiguous range of the
+// (tile-sorted) particle order and keeps that region's stencils in its own L2.
+__device__ inline uint32_t xcd_block(uint32_t b, uint32_t nb)
+{
+    const uint32_t q = nb >> 3, r = nb & 7u;
+    const uint32_t x = b & 7u, local = b >> 3;
+    return x * q + (x < r ? x : r) + local;
+}
+
+// Cell search on one axis: the largest i in [0, n-2] with c[i] <= x, or false if x
+// is NaN or outside [c0, c(n-1)].  The guess (closed form for a uniform axis, a
+// bin table otherwise) is corrected against the stored coordinates, so the index
+// follows the stored grid exactly.
+__device__ inline bool locate(const AxisDev &a, double x, int &i, double &f)
+{
+    if (!(x >= a.lo && x <= a.hi))
+        return false;
+    int g;
+    if (a.uniform) {
+        g = (int)((x - a.lo) * a.ginv);
+    } else {
+        int b = (int)((x - a.lo) * a.ginv);
+        b = b < kGuessBins - 1 ? b : kGuessBins - 1;
+        g = a.guess[b];
+    }
+    g = g < 0 ? 0 : (g > a.n - 2 ? a.n - 2 : g);
+    while (g > 0 && a.c[g] > x)
+        --g;
+    while (g < a.n - 2 && a.c[g + 1] <= x)
+        ++g;
+    i = g;
+    f = (x - a.c[g]) * a.rw[g];
+    return true;
+}
+
+template <int ST> struct Real { using T = double; };
+template <> struct Real<kBF16> { using T = float; };
+template <> struct Real<kF16S> { using T = float; };
+
+__device__ inline float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ inline float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xFFFF0000u); }
+__device__ inline float f16_lo(uint32_t w)
+{
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)(w & 0xFFFFu));
+}
+__device__ inline float f16_hi(uint32_t w)
+{
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)(w >> 16));
+}
+
+// Load (U, V[, W]) of one node of one snapshot slot.
+template <int ST, bool IS3D>
+__device__ inline void load_node(const char *slot, size_t node, const float *sc,
+                                 typename Real<ST>::T v[3])
+{
+    if constexpr (ST == kF64) {
+        if constexpr (IS3D) {
+            const double4 q = reinterpret_cast<const double4 *>(slot)[node];
+            v[0] = q.x; v[1] = q.y; v[2] = q.z;
+        } else {
+            const double2 q = reinterpret_cast<const double2 *>(slot)[node];
+            v[0] = q.x; v[1] = q.y; v[2] = 0.0;
+        }
+    } else if constexpr (ST == kF32) {
+        if constexpr (IS3D) {
+            const float4 q = reinterpret_cast<const float4 *>(slot)[node];
+            v[0] = q.x; v[1] = q.y; v[2] = q.z;
+        } else {
+            const float2 q = reinterpret_cast<const float2 *>(slot)[node];
+            v[0] = q.x; v[1] = q.y; v[2] = 0.0;
+        }
+    } else if constexpr (ST == kBF16) {
+        if constexpr (IS3D) {
+            const uint2 q = reinterpret_cast<const uint2 *>(slot)[node];
+            v[0] = bf16_lo(q.x); v[1] = bf16_hi(q.x); v[2] = bf16_lo(q.y);
+        } else {
+            const uint32_t q = reinterpret_cast<const uint32_t *>(slot)[node];
+            v[0] = bf16_lo(q); v[1] = bf16_hi(q); v[2] = 0.f;
+        }
+    } else {
+        if constexpr (IS3D) {
+            const uint2 q = reinterpret_cast<const uint2 *>(slot)[node];
+            v[0] = f16_lo(q.x) * sc[0]; v[1] = f16_hi(q.x) * sc[1]; v[2] = f16_lo(q.y) * sc[2];
+        } else {
+            const uint32_t q = reinterpret_cast<const uint32_t *>(slot)[node];
+            v[0] = f16_lo(q) * sc[0]; v[1] = f16_hi(q) * sc[1]; v[2] = 0.f;
+        }
+    }
+}
+
+struct Cell {
+    int i, j, k;
+    double xi, eta, zeta;
+};
+
+// Bilinear interpolation of level k in one slot: the four corner weights times the
+// corner values, summed in the order (0,0), (1,0), (1,1), (0,1).
+template <int ST, bool IS3D>
+__device__ inline void bilinear(const AdvectParams &P, const char *slot, int sidx, int k,
+                                const Cell &c, typename Real<ST>::T out[3])
+{
+    using R = typename Real<ST>::T;
+    const size_t nx = (size_t)P.g.ax.n;
+    const size_t plane = nx * (size_t)P.g.ay.n;
+    const size_t n00 = (size_t)k * plane + (size_t)c.j * nx + (size_t)c.i;
+    const float *sc = nullptr;
+    if constexpr (ST == kF16S)
+        sc = P.f.scales + ((size_t)sidx * P.f.nzl + k) * 3;
+    R f00[3], f10[3], f11[3], f01[3];
+    load_node<ST, IS3D>(slot, n00, sc, f00);
+    load_node<ST, IS3D>(slot, n00 + 1, sc, f10);
+    load_node<ST, IS3D>(slot, n00 + nx + 1, sc, f11);
+    load_node<ST, IS3D>(slot, n00 + nx, sc, f01);
+    const R xi = (R)c.xi, eta = (R)c.eta;
+    const R w00 = ((R)1 - xi) * ((R)1 - eta), w10 = xi * ((R)1 - eta);
+    const R w11 = xi * eta, w01 = ((R)1 - xi) * eta;
+#pragma unroll
+    for (int q = 0; q < (IS3D ? 3 : 2); ++q)
+        out[q] = ((w00 * f00[q] + w10 * f10[q]) + w11 * f11[q]) + w01 * f01[q];
+}
+
+template <int ST, bool IS3D>
+__device__ inline void spatial(const AdvectParams &P, int sidx, const Cell &c,
+                               typename Real<ST>::T out[3])
+{
+    using R = typename Real<ST>::T;
+    const char *slot = static_cast<const char *>(P.f.slots) + (size_t)sidx * P.f.slot_bytes;
+    if constexpr (!IS3D) {
+        bilinear<ST, false>(P, slot, sidx, 0, c, out);
+        out[2] = (R)0;
+    } else {
+        R lo[3], hi[3];
+        bilinear<ST, true>(P, slot, sidx, c.k, c, lo);
+        bilinear<ST, true>(P, slot, sidx, c.k + 1, c, hi);
+        const R z = (R)c.zeta;
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+            out[q] = ((R)1 - z) * lo[q] + z * hi[q];
+    }
+}
+
+// Velocity at a stage point in coordinate units per second; false if outside.
+template <int ST, bool IS3D, bool STEADY>
+__device__ inline bool sample(const AdvectParams &P, const TimeEntry &te, double x, double y,
+                              double z, double k[3])
+{
+    using R = typename Real<ST>::T;
+    Cell c;
+    if (!locate(P.g.ax, x, c.i, c.xi) || !locate(P.g.ay, y, c.j, c.eta))
+        return false;
+    c.k = 0;
+    c.zeta = 0.0;
+    if constexpr (IS3D) {
+        if (!locate(P.g.az, z, c.k, c.zeta))
+            return false;
+    }
+    R v[3];
+    if constexpr (STEADY) {
+        spatial<ST, IS3D>(P, te.sa, c, v);
+    } else {
+        R a[3], b[3];
+        spatial<ST, IS3D>(P, te.sa, c, a);
+        spatial<ST, IS3D>(P, te.sb, c, b);
+        const R tau = (R)te.tau;
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+            v[q] = ((R)1 - tau) * a[q] + tau * b[q];
+    }
+    if (P.g.spherical) {
+        if constexpr (sizeof(R) == 8) {
+            k[0] = v[0] / (kMetresPerDegree * cos(y * kDegToRad));
+            k[1] = v[1] / kMetresPerDegree;
+        } else {
+            const float cl = cosf((float)(y * kDegToRad));
+            k[0] = (double)(v[0] / ((float)kMetresPerDegree * cl));
+            k[1] = (double)(v[1] / (float)kMetresPerDegree);
+        }
+    } else {
+        k[0] = (double)v[0];
+        k[1] = (double)v[1];
+    }
+    k[2] = (double)v[2];
+    return true;
+}
+
+// Philox4x32-10 (Salmon et al., SC'11): ten Philox-4x32 rounds, key bumped by the
+// Weyl constants between rounds.
+__device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1)
+{
+    constexpr uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    constexpr uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += W0;
+            k1 += W1;
+        }
+        const uint32_t lo0 = M0 * c[0], hi0 = __umulhi(M0, c[0]);
+        const uint32_t lo1 = M1 * c[2], hi1 = __umulhi(M1, c[2]);
+        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+    }
+}
+
+__device__ inline double unit53(uint32_t a, uint32_t b)
+{
+    const uint64_t m = (((uint64_t)a << 32) | (uint64_t)b) >> 11;
+    return (double)m * 0x1p-53 + 0x1p-54;
+}
+
+template <int ST, bool IS3D, bool STEADY>
+__device__ inline uint8_t rk4_step(const AdvectParams &P, int s, uint32_t id, double &x,
+                                   double &y, double &z)
+{
+    const TimeEntry e0 = P.tab[2 * s], e1 = P.tab[2 * s + 1], e2 = P.tab[2 * s + 2];
+    const double dt = P.dt, hd = 0.5 * dt;
+    double k1[3], k2[3], k3[3], k4[3];
+    if (!sample<ST, IS3D, STEADY>(P, e0, x, y, z, k1))
+        return ST_OOB;
+    if (!sample<ST, IS3D, STEADY>(P, e1, x + k1[0] * hd, y + k1[1] * hd, z + k1[2] * hd, k2))
+        return ST_OOB;
+    if (!sample<ST, IS3D, STEADY>(P, e1, x + k2[0] * hd, y + k2[1] * hd, z + k2[2] * hd, k3))
+        return ST_OOB;
+    if (!sample<ST, IS3D, STEADY>(P, e2, x + k3[0] * dt, y + k3[1] * dt, z + k3[2] * dt, k4))
+        return ST_OOB;
+    double xs = x + ((((k1[0] + 2.0 * k2[0]) + 2.0 * k3[0]) + k4[0]) * dt) / 6.0;
+    double ys = y + ((((k1[1] + 2.0 * k2[1]) + 2.0 * k3[1]) + k4[1]) * dt) / 6.0;
+    double zs = z;
+    if constexpr (IS3D)
+        zs = z + ((((k1[2] + 2.0 * k2[2]) + 2.0 * k3[2]) + k4[2]) * dt) / 6.0;
+    if (P.Kh > 0.0) {
+        uint32_t c[4] = {id, (uint32_t)(P.step0 + s), 0u, 0u};
+        philox4x32_10(c, P.run_id, P.seed);
+        const double u1 = unit53(c[0], c[1]), u2 = unit53(c[2], c[3]);
+        const double r = sqrt(-2.0 * log(u1));
+        double sn, cs;
+        sincos((2.0 * 3.141592653589793) * u2, &sn, &cs);
+        const double sig = sqrt(2.0 * P.Kh * dt);
+        double dx = sig * (r * cs), dy = sig * (r * sn);
+        if (P.g.spherical) {
+            dx = dx / (kMetresPerDegree * cos(ys * kDegToRad));
+            dy = dy / kMetresPerDegree;
+        }
+        xs = xs + dx;
+        ys = ys + dy;
+    }
+    int ci, cj, ck;
+    double f;
+    if (!locate(P.g.ax, xs, ci, f) || !locate(P.g.ay, ys, cj, f))
+        return ST_OOB;
+    if constexpr (IS3D) {
+        if (!locate(P.g.az, zs, ck, f))
+            return ST_OOB;
+    }
+    if (P.g.landcell && P.g.landcell[(size_t)cj * (size_t)(P.g.ax.n - 1) + (size_t)ci])
+        return ST_LAND;
+    x = xs;
+    y = ys;
+    z = zs;
+    return 0;
+}
+
+template <int ST, bool IS3D, bool STEADY>
+__global__ __launch_bounds__(kBlock) void k_advect(AdvectParams P)
+{
+    const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const uint32_t k = blk * kBlock + threadIdx.x;
+    const uint32_t nact = *P.n_active;
+    long long steps = 0;
+    if (k < nact) {
+        const uint32_t id = P.order[k];
+        uint8_t st = P.status[id];
+        if (st == 0) {
+            double x = P.x[id], y = P.y[id], z = IS3D ? P.z[id] : 0.0;
+            for (int s = 0; s < P.nsteps; ++s) {
+                ++steps;
+                const uint8_t e = rk4_step<ST, IS3D, STEADY>(P, s, id, x, y, z);
+                if (e) {
+                    st = (uint8_t)(e | (P.policy == 0 ? ST_DELETED : 0));
+                    break;
+                }
+            }
+            P.x[id] = x;
+            P.y[id] = y;
+            if constexpr (IS3D)
+                P.z[id] = z;
+            if (st)
+                P.status[id] = st;
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1)
+        steps += __shfl_xor(steps, off, 64);
+    if ((threadIdx.x & 63) == 0 && steps)
+        atomicAdd(P.psteps, (unsigned long long)steps);
+}
+
+// Output record (or cell-index query) of the particles with id = r * stride.
+__global__ void k_record(RecordParams R)
+{
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < R.nper;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t id = r * R.stride;
+        const double x = R.x[id], y = R.y[id];
+        const double z = R.z ? R.z[id] : 0.0;
+        int i = -1, j = -1, k = R.g.az.n ? -1 : 0;
+        double f;
+        bool in = locate(R.g.ax, x, i, f) && locate(R.g.ay, y, j, f);
+        if (in && R.g.az.n)
+            in = locate(R.g.az, z, k, f);
+        if (!in) {
+            i = -1;
+            j = -1;
+            k = -1;
+        }
+        if (R.rx) R.rx[r] = x;
+        if (R.ry) R.ry[r] = y;
+        if (R.rz) R.rz[r] = z;
+        if (R.rst) R.rst[r] = R.status[id];
+        if (R.ci) R.ci[r] = i;
+        if (R.cj) R.cj[r] = j;
+        if (R.ck) R.ck[r] = k;
+    }
+}
+
+template <int ST, bool IS3D>
+hipError_t launch3(const AdvectParams &p, bool steady, uint32_t n_launch, hipStream_t s)
+{
+    const uint32_t blocks = (n_launch + kBlock - 1) / kBlock;
+    if (blocks == 0)
+        return hipSuccess;
+    if (steady)
+        hipLaunchKernelGGL((k_advect<ST, IS3D, true>), dim3(blocks), dim3(kBlock), 0, s, p);
+    else
+        hipLaunchKernelGGL((k_advect<ST, IS3D, false>), dim3(blocks), dim3(kBlock), 0, s, p);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_advect(int store, bool is3d, const AdvectParams &p, uint32_t n_launch,
+                         hipStream_t s)
+{
+    const bool steady = p.f.steady != 0;
+    switch (store) {
+    case kF64: return is3d ? launch3<kF64, true>(p, steady, n_launch, s)
+                           : launch3<kF64, false>(p, steady, n_launch, s);
+    case kF32: return is3d ? launch3<kF32, true>(p, steady, n_launch, s)
+                           : launch3<kF32, false>(p, steady, n_launch, s);
+    case kBF16: return is3d ? launch3<kBF16, true>(p, steady, n_launch, s)
+                            : launch3<kBF16, false>(p, steady, n_launch, s);
+    case kF16S: return is3d ? launch3<kF16S, true>(p, steady, n_launch, s)
+                            : launch3<kF16S, false>(p, steady, n_launch, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_record(const RecordParams &p, hipStream_t s)
+{
+    if (p.nper <= 0)
+        return hipSuccess;
+    int64_t blocks = (p.nper + 255) / 256;
+    if (blocks > 65536)
+        blocks = 65536;
+    hipLaunchKernelGGL(k_record, dim3((uint32_t)blocks), dim3(256), 0, s, p);
+    return hipGetLastError();
+}
+
+}  // namespace lp

@@ -1,0 +1,951 @@
+// capi.hip -- host side of the library: field sets with a ring of device snapshot
+// slots, particle sets, and the execute loop that drives the kernels.
+//
+// The execute loop follows the paper's dynamic update loop (Sect. 2.2): advance
+// every particle in steps of dt, write output at every output interval, and turn
+// particle errors into recovery actions.  Field snapshots enter through a ring of
+// device slots fed on the field set's own stream, the device counterpart of
+// keeping three consecutive time slices and calling advancetime (Sect. 3.1,
+// Sect. 3.4).
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/lp.h"
+#include "lp_internal.h"
+
+using lp::AxisDev;
+using lp::GridDev;
+using lp::TimeEntry;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHECK(expr)                                                                        \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(e_ == hipErrorOutOfMemory ? LP_ENOMEM : LP_EDEVICE, "%s: %s (%s:%d)", \
+                        #expr, hipGetErrorString(e_), __FILE__, __LINE__);                    \
+    } while (0)
+
+template <class T>
+int dalloc(T **p, size_t count)
+{
+    *p = nullptr;
+    if (count == 0)
+        return LP_OK;
+    hipError_t e = hipMalloc((void **)p, count * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(LP_ENOMEM, "hipMalloc of %zu bytes failed: %s", count * sizeof(T),
+                    hipGetErrorString(e));
+    }
+    return LP_OK;
+}
+
+template <class T>
+void dfree(T *&p)
+{
+    if (p)
+        (void)hipFree((void *)p);
+    p = nullptr;
+}
+
+struct HostAxis {
+    std::vector<double> c, rw;
+    std::vector<int32_t> guess;
+    bool uniform = true;
+};
+
+int build_axis(const double *src, int n, const char *name, HostAxis &h)
+{
+    if (!src || n < 2)
+        return fail(LP_EINVAL, "axis %s needs at least 2 coordinates", name);
+    h.c.assign(src, src + n);
+    for (int i = 0; i + 1 < n; ++i)
+        if (!(h.c[i + 1] > h.c[i]))
+            return fail(LP_EINVAL, "axis %s is not strictly increasing at %d", name, i);
+    h.rw.resize(n - 1);
+    for (int i = 0; i + 1 < n; ++i)
+        h.rw[i] = 1.0 / (h.c[i + 1] - h.c[i]);
+    const double lo = h.c[0], hi = h.c[n - 1], dx = (hi - lo) / (n - 1);
+    h.uniform = true;
+    for (int i = 0; i < n; ++i)
+        if (std::fabs(h.c[i] - (lo + i * dx)) > 0.25 * dx)
+            h.uniform = false;
+    if (!h.uniform) {
+        h.guess.resize(lp::kGuessBins);
+        int i = 0;
+        for (int b = 0; b < lp::kGuessBins; ++b) {
+            const double xb = lo + (hi - lo) * ((double)b / lp::kGuessBins);
+            while (i < n - 2 && h.c[i + 1] <= xb)
+                ++i;
+            h.guess[b] = i;
+        }
+    }
+    return LP_OK;
+}
+
+struct DevAxis {
+    double *c = nullptr, *rw = nullptr;
+    int32_t *guess = nullptr;
+};
+
+int upload_axis(const HostAxis &h, DevAxis &d, AxisDev &a)
+{
+    int rc;
+    if ((rc = dalloc(&d.c, h.c.size())) || (rc = dalloc(&d.rw, h.rw.size())))
+        return rc;
+    HIPCHECK(hipMemcpy(d.c, h.c.data(), h.c.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(d.rw, h.rw.data(), h.rw.size() * sizeof(double), hipMemcpyHostToDevice));
+    if (!h.uniform) {
+        if ((rc = dalloc(&d.guess, h.guess.size())))
+            return rc;
+        HIPCHECK(hipMemcpy(d.guess, h.guess.data(), h.guess.size() * sizeof(int32_t),
+                           hipMemcpyHostToDevice));
+    }
+    a.c = d.c;
+    a.rw = d.rw;
+    a.guess = d.guess;
+    a.n = (int32_t)h.c.size();
+    a.lo = h.c.front();
+    a.hi = h.c.back();
+    a.uniform = h.uniform ? 1 : 0;
+    a.ginv = h.uniform ? (double)(a.n - 1) / (a.hi - a.lo) : (double)lp::kGuessBins / (a.hi - a.lo);
+    return LP_OK;
+}
+
+void free_axis(DevAxis &d)
+{
+    dfree(d.c);
+    dfree(d.rw);
+    dfree(d.guess);
+}
+
+size_t node_bytes(int dtype, bool is3d)
+{
+    switch (dtype) {
+    case LP_F64: return is3d ? 32 : 16;
+    case LP_F32: return is3d ? 16 : 8;
+    default: return is3d ? 8 : 4;
+    }
+}
+
+}  // namespace
+
+struct lp_fieldset {
+    int device = 0;
+    int nx = 0, ny = 0, nz = 0, nzl = 1;
+    bool is3d = false;
+    int mesh = 0, dtype = 0, capacity = 0;
+    double period = 0.0;
+    DevAxis dx_, dy_, dz_;
+    GridDev g{};
+    uint8_t *dland = nullptr;
+    char *dslots = nullptr;
+    size_t slot_bytes = 0;
+    float *dscales = nullptr;
+    float *dtmp = nullptr;
+    float *dstage = nullptr;
+    double *dstage64 = nullptr;
+    hipStream_t up = nullptr;
+    std::vector<hipEvent_t> ready, release;
+    std::vector<double> slot_t;
+    std::vector<int64_t> slot_seq;  // push index held by each slot, -1 = empty
+    int64_t npushed = 0;
+    double first_t = 0.0, last_t = 0.0;
+
+    size_t plane() const { return (size_t)nx * (size_t)ny; }
+};
+
+struct lp_pset {
+    lp_fieldset *fs = nullptr;
+    int64_t n = 0;
+    double *dx = nullptr, *dy = nullptr, *dz = nullptr;
+    uint8_t *dst = nullptr;
+    uint32_t *dorder[2] = {nullptr, nullptr};
+    uint32_t *dcount = nullptr;  // [2]
+    int cur = 0;
+    uint32_t n_launch = 0;       // host upper bound of the active count
+    uint32_t *hcount = nullptr;  // pinned copy of the device count
+    hipEvent_t count_ev = nullptr;
+    bool count_pending = false;
+    uint32_t *dkeys = nullptr, *dhist = nullptr, *dblk = nullptr;
+    uint32_t nbins = 0;
+    unsigned long long *dpsteps = nullptr;
+    double t0 = 0.0, dt = 0.0;
+    int64_t step = 0;
+    // output records (record-major)
+    int64_t stride = 0, nper = 0, nrec = 0, rec_cap = 0;
+    double *rx = nullptr, *ry = nullptr, *rz = nullptr;
+    uint8_t *rst = nullptr;
+    int32_t *rci = nullptr, *rcj = nullptr, *rck = nullptr;
+    // time table
+    TimeEntry *dtab = nullptr, *htab = nullptr;
+    size_t tab_cap = 0;
+    hipEvent_t tab_ev = nullptr;
+    bool tab_pending = false;
+    // profiling
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof;
+    int segs_since_sort = 1 << 30;
+    hipStream_t last_stream = nullptr;
+};
+
+// ---------------------------------------------------------------- field sets
+extern "C" int fieldset_create(const lp_grid_desc *g, lp_fieldset **out)
+{
+    if (!g || !out)
+        return fail(LP_EINVAL, "null argument");
+    *out = nullptr;
+    if (g->nx < 2 || g->ny < 2 || (g->nz != 0 && g->nz < 2))
+        return fail(LP_EINVAL, "grid needs nx, ny >= 2 and nz == 0 or >= 2");
+    if (g->dtype < LP_F64 || g->dtype > LP_F16_SCALED)
+        return fail(LP_EINVAL, "unknown dtype %d", g->dtype);
+    if (g->mesh != LP_MESH_FLAT && g->mesh != LP_MESH_SPHERICAL)
+        return fail(LP_EINVAL, "unknown mesh %d", g->mesh);
+    if (g->capacity < 1)
+        return fail(LP_EINVAL, "capacity must be >= 1");
+    if (!(g->time_period >= 0.0))
+        return fail(LP_EINVAL, "time_period must be >= 0");
+    if (g->nz >= 2 && !g->depth)
+        return fail(LP_EINVAL, "3D grid needs depth levels");
+    if ((size_t)g->nx * g->ny > 0x7FFFFFFFull)
+        return fail(LP_EINVAL, "too many horizontal nodes");
+    HostAxis hx, hy, hz;
+    int rc;
+    if ((rc = build_axis(g->lon, g->nx, "lon", hx)) || (rc = build_axis(g->lat, g->ny, "lat", hy)))
+        return rc;
+    if (g->nz >= 2 && (rc = build_axis(g->depth, g->nz, "depth", hz)))
+        return rc;
+
+    lp_fieldset *fs = new lp_fieldset();
+    auto bail = [&](int code) {
+        fieldset_destroy(fs);
+        return code;
+    };
+    (void)hipGetDevice(&fs->device);
+    fs->nx = g->nx;
+    fs->ny = g->ny;
+    fs->nz = g->nz;
+    fs->is3d = g->nz >= 2;
+    fs->nzl = fs->is3d ? g->nz : 1;
+    fs->mesh = g->mesh;
+    fs->dtype = g->dtype;
+    fs->capacity = g->capacity;
+    fs->period = g->time_period;
+    if ((rc = upload_axis(hx, fs->dx_, fs->g.ax)) || (rc = upload_axis(hy, fs->dy_, fs->g.ay)))
+        return bail(rc);
+    if (fs->is3d && (rc = upload_axis(hz, fs->dz_, fs->g.az)))
+        return bail(rc);
+    fs->g.spherical = g->mesh == LP_MESH_SPHERICAL;
+    if (g->land) {
+        std::vector<uint8_t> cell((size_t)(g->ny - 1) * (g->nx - 1));
+        const size_t nx = g->nx;
+        for (int j = 0; j + 1 < g->ny; ++j)
+            for (int i = 0; i + 1 < g->nx; ++i)
+                cell[(size_t)j * (nx - 1) + i] =
+                    (g->land[j * nx + i] && g->land[j * nx + i + 1] && g->land[(j + 1) * nx + i] &&
+                     g->land[(j + 1) * nx + i + 1])
+                        ? 1
+                        : 0;
+        if ((rc = dalloc(&fs->dland, cell.size())))
+            return bail(rc);
+        if (hipMemcpy(fs->dland, cell.data(), cell.size(), hipMemcpyHostToDevice) != hipSuccess)
+            return bail(fail(LP_EDEVICE, "land mask upload failed"));
+        fs->g.landcell = fs->dland;
+    }
+    fs->slot_bytes = node_bytes(fs->dtype, fs->is3d) * fs->plane() * fs->nzl;
+    fs->slot_bytes = (fs->slot_bytes + 255) & ~(size_t)255;
+    if ((rc = dalloc(&fs->dslots, fs->slot_bytes * fs->capacity)))
+        return bail(rc);
+    if ((rc = dalloc(&fs->dscales, (size_t)fs->capacity * fs->nzl * 3)) ||
+        (rc = dalloc(&fs->dtmp, (size_t)fs->nzl * 3)))
+        return bail(rc);
+    if (hipStreamCreateWithFlags(&fs->up, hipStreamNonBlocking) != hipSuccess)
+        return bail(fail(LP_EDEVICE, "stream creation failed"));
+    fs->ready.resize(fs->capacity);
+    fs->release.resize(fs->capacity);
+    for (int s = 0; s < fs->capacity; ++s) {
+        if (hipEventCreateWithFlags(&fs->ready[s], hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&fs->release[s], hipEventDisableTiming) != hipSuccess)
+            return bail(fail(LP_EDEVICE, "event creation failed"));
+    }
+    fs->slot_t.assign(fs->capacity, 0.0);
+    fs->slot_seq.assign(fs->capacity, -1);
+    *out = fs;
+    return LP_OK;
+}
+
+extern "C" void fieldset_destroy(lp_fieldset *fs)
+{
+    if (!fs)
+        return;
+    if (fs->up)
+        (void)hipStreamSynchronize(fs->up);
+    free_axis(fs->dx_);
+    free_axis(fs->dy_);
+    free_axis(fs->dz_);
+    dfree(fs->dland);
+    dfree(fs->dslots);
+    dfree(fs->dscales);
+    dfree(fs->dtmp);
+    dfree(fs->dstage);
+    dfree(fs->dstage64);
+    for (auto e : fs->ready)
+        if (e) (void)hipEventDestroy(e);
+    for (auto e : fs->release)
+        if (e) (void)hipEventDestroy(e);
+    if (fs->up)
+        (void)hipStreamDestroy(fs->up);
+    delete fs;
+}
+
+static int push_common(lp_fieldset *fs, double t, const void *U, const void *V, const void *W,
+                       bool device_src, bool f64, void *stream)
+{
+    if (!fs || !U || !V || (fs->is3d && !W))
+        return fail(LP_EINVAL, "null field pointer");
+    if (f64 && fs->dtype != LP_F64)
+        return fail(LP_EINVAL, "double snapshots need LP_F64 storage");
+    if (!std::isfinite(t))
+        return fail(LP_EINVAL, "snapshot time is not finite");
+    if (fs->npushed > 0 && !(t > fs->last_t))
+        return fail(LP_EINVAL, "snapshot times must increase (%g after %g)", t, fs->last_t);
+    if (fs->period > 0.0) {
+        if (fs->npushed >= fs->capacity)
+            return fail(LP_ESTATE, "a periodic field set keeps every snapshot resident: "
+                                   "capacity %d is full", fs->capacity);
+        if (fs->npushed > 0 && !(t < fs->first_t + fs->period))
+            return fail(LP_EINVAL, "snapshot time beyond one period");
+    }
+    const int slot = (int)(fs->npushed % fs->capacity);
+    const size_t nvals = fs->plane() * fs->nzl;
+    const int nvar = fs->is3d ? 3 : 2;
+    int rc;
+    if (f64) {
+        if (!fs->dstage64 && (rc = dalloc(&fs->dstage64, nvals * 3)))
+            return rc;
+    } else if (!fs->dstage && (rc = dalloc(&fs->dstage, nvals * 3))) {
+        return rc;
+    }
+    if (stream) {
+        hipEvent_t ev;
+        HIPCHECK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        HIPCHECK(hipEventRecord(ev, (hipStream_t)stream));
+        HIPCHECK(hipStreamWaitEvent(fs->up, ev, 0));
+        HIPCHECK(hipEventDestroy(ev));
+    }
+    // kernels that still read the slot must finish before it is overwritten
+    HIPCHECK(hipStreamWaitEvent(fs->up, fs->release[slot], 0));
+    const void *src[3] = {U, V, W};
+    const size_t esz = f64 ? sizeof(double) : sizeof(float);
+    const hipMemcpyKind kind = device_src ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    for (int q = 0; q < nvar; ++q) {
+        void *dst = f64 ? (void *)(fs->dstage64 + q * nvals) : (void *)(fs->dstage + q * nvals);
+        HIPCHECK(hipMemcpyAsync(dst, src[q], nvals * esz, kind, fs->up));
+    }
+    char *slotp = fs->dslots + (size_t)slot * fs->slot_bytes;
+    float *scales = fs->dscales + (size_t)slot * fs->nzl * 3;
+    hipError_t e;
+    if (f64)
+        e = lp::launch_convert_snapshot(fs->dtype, fs->is3d, nullptr, nullptr, nullptr,
+                                        fs->dstage64, fs->dstage64 + nvals,
+                                        fs->is3d ? fs->dstage64 + 2 * nvals : nullptr,
+                                        fs->plane(), fs->nzl, slotp, scales, fs->dtmp, fs->up);
+    else
+        e = lp::launch_convert_snapshot(fs->dtype, fs->is3d, fs->dstage, fs->dstage + nvals,
+                                        fs->is3d ? fs->dstage + 2 * nvals : nullptr, nullptr,
+                                        nullptr, nullptr, fs->plane(), fs->nzl, slotp, scales,
+                                        fs->dtmp, fs->up);
+    HIPCHECK(e);
+    HIPCHECK(hipEventRecord(fs->ready[slot], fs->up));
+    if (!device_src)
+        HIPCHECK(hipStreamSynchronize(fs->up));  // the host arrays may be reused now
+    if (fs->npushed == 0)
+        fs->first_t = t;
+    fs->slot_t[slot] = t;
+    fs->slot_seq[slot] = fs->npushed;
+    fs->npushed++;
+    fs->last_t = t;
+    return LP_OK;
+}
+
+extern "C" int fieldset_push_snapshot(lp_fieldset *fs, double t, const float *U, const float *V,
+                                      const float *W, void *stream)
+{
+    return push_common(fs, t, U, V, W, false, false, stream);
+}
+
+extern "C" int fieldset_push_snapshot_f64(lp_fieldset *fs, double t, const double *U,
+                                          const double *V, const double *W, void *stream)
+{
+    return push_common(fs, t, U, V, W, false, true, stream);
+}
+
+extern "C" int fieldset_push_snapshot_device(lp_fieldset *fs, double t, const float *dU,
+                                             const float *dV, const float *dW, void *stream)
+{
+    return push_common(fs, t, dU, dV, dW, true, false, stream);
+}
+
+namespace {
+
+struct Resident {
+    double t;
+    int slot;
+};
+
+std::vector<Resident> resident(const lp_fieldset *fs)
+{
+    std::vector<Resident> r;
+    for (int s = 0; s < fs->capacity; ++s)
+        if (fs->slot_seq[s] >= 0)
+            r.push_back({fs->slot_t[s], s});
+    std::sort(r.begin(), r.end(), [](const Resident &a, const Resident &b) { return a.t < b.t; });
+    return r;
+}
+
+// Bracket of time t among the resident snapshots: linear weight tau between
+// slot sa (earlier) and sb (later).
+int bracket(const lp_fieldset *fs, const std::vector<Resident> &r, double t, TimeEntry &e)
+{
+    const int m = (int)r.size();
+    if (m == 0)
+        return fail(LP_ETIME, "no snapshot has been pushed");
+    if (m == 1 && fs->npushed == 1) {  // steady field
+        e.tau = 0.0;
+        e.sa = e.sb = r[0].slot;
+        return LP_OK;
+    }
+    if (fs->period > 0.0) {
+        const double T0 = r[0].t;
+        double q = std::fmod(t - T0, fs->period);
+        if (q < 0.0)
+            q += fs->period;
+        const double tp = T0 + q;
+        int s = 0;
+        for (int k = 0; k < m; ++k)
+            if (r[k].t <= tp)
+                s = k;
+        const double tn = (s + 1 < m) ? r[s + 1].t : T0 + fs->period;
+        e.sa = r[s].slot;
+        e.sb = (s + 1 < m) ? r[s + 1].slot : r[0].slot;
+        e.tau = (tp - r[s].t) / (tn - r[s].t);
+        return LP_OK;
+    }
+    if (!(t >= r[0].t && t <= r[m - 1].t) || m < 2)
+        return fail(LP_ETIME, "time %.17g is not covered by the resident snapshots [%.17g, %.17g]",
+                    t, r[0].t, r[m - 1].t);
+    int s = 0;
+    for (int k = 0; k + 1 < m; ++k)
+        if (r[k].t <= t)
+            s = k;
+    e.sa = r[s].slot;
+    e.sb = r[s + 1].slot;
+    e.tau = (t - r[s].t) / (r[s + 1].t - r[s].t);
+    return LP_OK;
+}
+
+}  // namespace
+
+extern "C" int fieldset_resident(const lp_fieldset *fs, int32_t *count, double *times)
+{
+    if (!fs || !count)
+        return fail(LP_EINVAL, "null argument");
+    auto r = resident(fs);
+    *count = (int32_t)r.size();
+    if (times)
+        for (size_t k = 0; k < r.size(); ++k)
+            times[k] = r[k].t;
+    return LP_OK;
+}
+
+// ---------------------------------------------------------------- particle sets
+extern "C" void pset_destroy(lp_pset *ps)
+{
+    if (!ps)
+        return;
+    (void)hipDeviceSynchronize();
+    dfree(ps->dx);
+    dfree(ps->dy);
+    dfree(ps->dz);
+    dfree(ps->dst);
+    dfree(ps->dorder[0]);
+    dfree(ps->dorder[1]);
+    dfree(ps->dcount);
+    dfree(ps->dkeys);
+    dfree(ps->dhist);
+    dfree(ps->dblk);
+    dfree(ps->dpsteps);
+    dfree(ps->rx);
+    dfree(ps->ry);
+    dfree(ps->rz);
+    dfree(ps->rst);
+    dfree(ps->rci);
+    dfree(ps->rcj);
+    dfree(ps->rck);
+    dfree(ps->dtab);
+    if (ps->htab)
+        (void)hipHostFree(ps->htab);
+    if (ps->hcount)
+        (void)hipHostFree(ps->hcount);
+    if (ps->tab_ev)
+        (void)hipEventDestroy(ps->tab_ev);
+    if (ps->count_ev)
+        (void)hipEventDestroy(ps->count_ev);
+    for (auto &p : ps->prof) {
+        (void)hipEventDestroy(p.first);
+        (void)hipEventDestroy(p.second);
+    }
+    delete ps;
+}
+
+static int pset_create_common(lp_fieldset *fs, int64_t n, const double *lon, const double *lat,
+                              const double *depth, double t0, int64_t step0, bool device_src,
+                              hipStream_t stream, lp_pset **out)
+{
+    if (!fs || !out)
+        return fail(LP_EINVAL, "null argument");
+    *out = nullptr;
+    if (n < 1 || n > 0x7FFFFFFFll)
+        return fail(LP_EINVAL, "particle count %lld out of range [1, 2^31)", (long long)n);
+    if (!lon || !lat || (fs->is3d && !depth))
+        return fail(LP_EINVAL, "null position array");
+    if (!std::isfinite(t0) || step0 < 0)
+        return fail(LP_EINVAL, "bad start time or step");
+    lp_pset *ps = new lp_pset();
+    auto bail = [&](int code) {
+        pset_destroy(ps);
+        return code;
+    };
+    ps->fs = fs;
+    ps->n = n;
+    ps->t0 = t0;
+    ps->step = step0;
+    int rc;
+    const size_t N = (size_t)n;
+    if ((rc = dalloc(&ps->dx, N)) || (rc = dalloc(&ps->dy, N)) ||
+        (fs->is3d && (rc = dalloc(&ps->dz, N))) || (rc = dalloc(&ps->dst, N)) ||
+        (rc = dalloc(&ps->dorder[0], N)) || (rc = dalloc(&ps->dorder[1], N)) ||
+        (rc = dalloc(&ps->dcount, 2)) || (rc = dalloc(&ps->dpsteps, 1)))
+        return bail(rc);
+    ps->nbins = lp::sort_bins(fs->g);
+    if ((rc = dalloc(&ps->dkeys, N)) || (rc = dalloc(&ps->dhist, ps->nbins)) ||
+        (rc = dalloc(&ps->dblk, lp::sort_blocksums(ps->nbins))))
+        return bail(rc);
+    if (hipHostMalloc((void **)&ps->hcount, sizeof(uint32_t), hipHostMallocDefault) != hipSuccess)
+        return bail(fail(LP_ENOMEM, "pinned allocation failed"));
+    if (hipEventCreateWithFlags(&ps->tab_ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ps->count_ev, hipEventDisableTiming) != hipSuccess)
+        return bail(fail(LP_EDEVICE, "event creation failed"));
+    const hipMemcpyKind kind = device_src ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    auto cp = [&](double *dst, const double *src) {
+        return hipMemcpyAsync(dst, src, N * sizeof(double), kind, stream);
+    };
+    if (cp(ps->dx, lon) != hipSuccess || cp(ps->dy, lat) != hipSuccess ||
+        (fs->is3d && cp(ps->dz, depth) != hipSuccess))
+        return bail(fail(LP_EDEVICE, "particle upload failed"));
+    if (hipMemsetAsync(ps->dst, 0, N, stream) != hipSuccess ||
+        hipMemsetAsync(ps->dpsteps, 0, sizeof(unsigned long long), stream) != hipSuccess ||
+        lp::launch_iota(ps->dorder[0], N, stream) != hipSuccess ||
+        lp::launch_fill_u32(ps->dcount, (uint32_t)n, 1, stream) != hipSuccess)
+        return bail(fail(LP_EDEVICE, "particle set initialisation failed"));
+    if (!device_src && hipStreamSynchronize(stream) != hipSuccess)
+        return bail(fail(LP_EDEVICE, "particle upload failed"));
+    ps->n_launch = (uint32_t)n;
+    ps->last_stream = stream;
+    *out = ps;
+    return LP_OK;
+}
+
+extern "C" int pset_create(lp_fieldset *fs, int64_t n, const double *lon, const double *lat,
+                           const double *depth, double t0, int64_t step0, lp_pset **out)
+{
+    return pset_create_common(fs, n, lon, lat, depth, t0, step0, false, nullptr, out);
+}
+
+extern "C" int pset_create_device(lp_fieldset *fs, int64_t n, const double *dlon,
+                                  const double *dlat, const double *ddepth, double t0,
+                                  int64_t step0, void *stream, lp_pset **out)
+{
+    return pset_create_common(fs, n, dlon, dlat, ddepth, t0, step0, true, (hipStream_t)stream,
+                              out);
+}
+
+namespace {
+
+int grow_records(lp_pset *ps, int64_t need)
+{
+    if (need <= ps->rec_cap)
+        return LP_OK;
+    int64_t cap = std::max<int64_t>(need, std::max<int64_t>(4, ps->rec_cap * 2));
+    const size_t old = (size_t)(ps->nrec * ps->nper), tot = (size_t)(cap * ps->nper);
+    const bool is3d = ps->fs->is3d;
+    double *rx, *ry, *rz = nullptr;
+    uint8_t *rst;
+    int32_t *ci, *cj, *ck = nullptr;
+    int rc;
+    if ((rc = dalloc(&rx, tot)) || (rc = dalloc(&ry, tot)) || (is3d && (rc = dalloc(&rz, tot))) ||
+        (rc = dalloc(&rst, tot)) || (rc = dalloc(&ci, tot)) || (rc = dalloc(&cj, tot)) ||
+        (is3d && (rc = dalloc(&ck, tot))))
+        return rc;
+    if (old) {
+        HIPCHECK(hipMemcpy(rx, ps->rx, old * 8, hipMemcpyDeviceToDevice));
+        HIPCHECK(hipMemcpy(ry, ps->ry, old * 8, hipMemcpyDeviceToDevice));
+        if (is3d)
+            HIPCHECK(hipMemcpy(rz, ps->rz, old * 8, hipMemcpyDeviceToDevice));
+        HIPCHECK(hipMemcpy(rst, ps->rst, old, hipMemcpyDeviceToDevice));
+        HIPCHECK(hipMemcpy(ci, ps->rci, old * 4, hipMemcpyDeviceToDevice));
+        HIPCHECK(hipMemcpy(cj, ps->rcj, old * 4, hipMemcpyDeviceToDevice));
+        if (is3d)
+            HIPCHECK(hipMemcpy(ck, ps->rck, old * 4, hipMemcpyDeviceToDevice));
+    }
+    dfree(ps->rx);
+    dfree(ps->ry);
+    dfree(ps->rz);
+    dfree(ps->rst);
+    dfree(ps->rci);
+    dfree(ps->rcj);
+    dfree(ps->rck);
+    ps->rx = rx;
+    ps->ry = ry;
+    ps->rz = rz;
+    ps->rst = rst;
+    ps->rci = ci;
+    ps->rcj = cj;
+    ps->rck = ck;
+    ps->rec_cap = cap;
+    return LP_OK;
+}
+
+int take_record(lp_pset *ps, hipStream_t s)
+{
+    lp::RecordParams R{};
+    R.g = ps->fs->g;
+    R.x = ps->dx;
+    R.y = ps->dy;
+    R.z = ps->dz;
+    R.status = ps->dst;
+    R.n = ps->n;
+    R.stride = ps->stride;
+    R.nper = ps->nper;
+    const size_t off = (size_t)(ps->nrec * ps->nper);
+    R.rx = ps->rx + off;
+    R.ry = ps->ry + off;
+    R.rz = ps->fs->is3d ? ps->rz + off : nullptr;
+    R.rst = ps->rst + off;
+    R.ci = ps->rci + off;
+    R.cj = ps->rcj + off;
+    R.ck = ps->fs->is3d ? ps->rck + off : nullptr;
+    HIPCHECK(lp::launch_record(R, s));
+    ps->nrec++;
+    return LP_OK;
+}
+
+}  // namespace
+
+extern "C" int pset_execute(lp_pset *ps, double runtime, double dt, double outputdt,
+                            const lp_exec_opts *o, void *stream_)
+{
+    if (!ps || !o)
+        return fail(LP_EINVAL, "null argument");
+    lp_fieldset *fs = ps->fs;
+    hipStream_t stream = (hipStream_t)stream_;
+    if (o->kernel != LP_KERNEL_RK4)
+        return fail(LP_EINVAL, "unknown kernel %d", o->kernel);
+    if (o->recovery != LP_DELETE && o->recovery != LP_FREEZE)
+        return fail(LP_EINVAL, "unknown recovery policy %d", o->recovery);
+    if (!(dt > 0.0) || !std::isfinite(dt))
+        return fail(LP_EINVAL, "dt must be positive and finite");
+    if (!(runtime >= 0.0) || !std::isfinite(runtime) || !(outputdt >= 0.0))
+        return fail(LP_EINVAL, "runtime and outputdt must be >= 0");
+    if (!(o->Kh >= 0.0) || o->output_stride < 0 || o->sort_every < 0)
+        return fail(LP_EINVAL, "bad options");
+    const double fsteps = runtime / dt;
+    const int64_t nsteps = (int64_t)std::llround(fsteps);
+    if (std::fabs((double)nsteps * dt - runtime) > 1e-9 * std::max(runtime, dt))
+        return fail(LP_EINVAL, "dt %g does not divide runtime %g", dt, runtime);
+    int64_t per = nsteps;
+    if (outputdt > 0.0) {
+        per = (int64_t)std::llround(outputdt / dt);
+        if (per < 1 || std::fabs((double)per * dt - outputdt) > 1e-9 * std::max(outputdt, dt))
+            return fail(LP_EINVAL, "dt %g does not divide outputdt %g", dt, outputdt);
+    }
+    if (nsteps > 0x3FFFFFFF || per > 0x3FFFFFFF)
+        return fail(LP_EINVAL, "too many steps in one call");
+    if (o->output_stride > 0) {
+        const int64_t nper = (ps->n + o->output_stride - 1) / o->output_stride;
+        if (ps->stride && ps->stride != o->output_stride)
+            return fail(LP_EINVAL, "output_stride changed between calls (%lld then %d)",
+                        (long long)ps->stride, o->output_stride);
+        ps->stride = o->output_stride;
+        ps->nper = nper;
+    }
+    if (nsteps == 0)
+        return LP_OK;
+    // time origin: t = t0 + step*dt for the current dt
+    if (ps->dt != 0.0 && dt != ps->dt)
+        ps->t0 = (ps->t0 + (double)ps->step * ps->dt) - (double)ps->step * dt;
+    const double t0 = ps->t0;
+
+    // stage-time table for every segment: t_n, t_n + dt/2, t_n + dt, ...
+    std::vector<std::pair<int64_t, int64_t>> segs;  // (first step, steps)
+    for (int64_t a = 0; a < nsteps; a += per)
+        segs.emplace_back(ps->step + a, std::min(per, nsteps - a));
+    size_t ntab = 0;
+    for (auto &sg : segs)
+        ntab += 2 * (size_t)sg.second + 1;
+    if (ps->tab_pending) {
+        HIPCHECK(hipEventSynchronize(ps->tab_ev));
+        ps->tab_pending = false;
+    }
+    if (ntab > ps->tab_cap) {
+        dfree(ps->dtab);
+        if (ps->htab)
+            (void)hipHostFree(ps->htab);
+        ps->htab = nullptr;
+        ps->tab_cap = 0;
+        int rc = dalloc(&ps->dtab, ntab);
+        if (rc)
+            return rc;
+        if (hipHostMalloc((void **)&ps->htab, ntab * sizeof(TimeEntry), hipHostMallocDefault) !=
+            hipSuccess)
+            return fail(LP_ENOMEM, "pinned allocation of the time table failed");
+        ps->tab_cap = ntab;
+    }
+    const auto res = resident(fs);
+    std::vector<char> used(fs->capacity, 0);
+    {
+        size_t q = 0;
+        for (auto &sg : segs) {
+            for (int64_t h = 0; h <= 2 * sg.second; ++h) {
+                const int64_t nn = sg.first + h / 2;
+                const double t = (h & 1) ? t0 + ((double)nn + 0.5) * dt : t0 + (double)nn * dt;
+                int rc = bracket(fs, res, t, ps->htab[q]);
+                if (rc)
+                    return rc;
+                used[ps->htab[q].sa] = used[ps->htab[q].sb] = 1;
+                ++q;
+            }
+        }
+    }
+    HIPCHECK(hipMemcpyAsync(ps->dtab, ps->htab, ntab * sizeof(TimeEntry), hipMemcpyHostToDevice,
+                            stream));
+    HIPCHECK(hipEventRecord(ps->tab_ev, stream));
+    ps->tab_pending = true;
+    for (int s = 0; s < fs->capacity; ++s)
+        if (used[s])
+            HIPCHECK(hipStreamWaitEvent(stream, fs->ready[s], 0));
+    // learn the active count of the previous call if it has arrived
+    if (ps->count_pending && hipEventQuery(ps->count_ev) == hipSuccess) {
+        ps->n_launch = std::min<uint32_t>(ps->n_launch, *ps->hcount);
+        ps->count_pending = false;
+    }
+    ps->dt = dt;
+    if (ps->stride > 0) {
+        int rc = grow_records(ps, ps->nrec + (int64_t)segs.size() + 1);
+        if (rc)
+            return rc;
+        if (ps->nrec == 0 && (rc = take_record(ps, stream)))
+            return rc;
+    }
+
+    lp::AdvectParams P{};
+    P.g = fs->g;
+    P.f.slots = fs->dslots;
+    P.f.slot_bytes = fs->slot_bytes;
+    P.f.scales = fs->dscales;
+    P.f.nzl = fs->nzl;
+    P.f.steady = (fs->npushed == 1) ? 1 : 0;
+    P.dt = dt;
+    P.policy = o->recovery == LP_DELETE ? 0 : 1;
+    P.Kh = o->Kh;
+    P.run_id = o->run_id;
+    P.seed = o->seed;
+    P.x = ps->dx;
+    P.y = ps->dy;
+    P.z = ps->dz;
+    P.status = ps->dst;
+    P.psteps = ps->dpsteps;
+    size_t toff = 0;
+    for (auto &sg : segs) {
+        if (o->sort_every > 0 && ps->segs_since_sort >= o->sort_every) {
+            HIPCHECK(lp::launch_sort(fs->g, ps->dx, ps->dy, ps->dz, ps->dst, ps->dorder[ps->cur],
+                                     ps->dcount + ps->cur, ps->n_launch, ps->dkeys, ps->dhist,
+                                     ps->nbins, ps->dblk, ps->dorder[1 - ps->cur],
+                                     ps->dcount + (1 - ps->cur), stream));
+            ps->cur = 1 - ps->cur;
+            ps->segs_since_sort = 0;
+        }
+        P.tab = ps->dtab + toff;
+        P.step0 = sg.first;
+        P.nsteps = (int32_t)sg.second;
+        P.order = ps->dorder[ps->cur];
+        P.n_active = ps->dcount + ps->cur;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (o->profile) {
+            HIPCHECK(hipEventCreate(&e0));
+            HIPCHECK(hipEventCreate(&e1));
+            HIPCHECK(hipEventRecord(e0, stream));
+        }
+        HIPCHECK(lp::launch_advect(fs->dtype, fs->is3d, P, ps->n_launch, stream));
+        if (o->profile) {
+            HIPCHECK(hipEventRecord(e1, stream));
+            ps->prof.emplace_back(e0, e1);
+        }
+        HIPCHECK(lp::launch_compact(ps->dorder[ps->cur], ps->dcount + ps->cur, ps->dst,
+                                    ps->dorder[1 - ps->cur], ps->dcount + (1 - ps->cur),
+                                    ps->n_launch, stream));
+        ps->cur = 1 - ps->cur;
+        ps->segs_since_sort++;
+        if (ps->stride > 0) {
+            int rc = take_record(ps, stream);
+            if (rc)
+                return rc;
+        }
+        toff += 2 * (size_t)sg.second + 1;
+    }
+    for (int s = 0; s < fs->capacity; ++s)
+        if (used[s])
+            HIPCHECK(hipEventRecord(fs->release[s], stream));
+    HIPCHECK(hipMemcpyAsync(ps->hcount, ps->dcount + ps->cur, sizeof(uint32_t),
+                            hipMemcpyDeviceToHost, stream));
+    HIPCHECK(hipEventRecord(ps->count_ev, stream));
+    ps->count_pending = true;
+    ps->step += nsteps;
+    ps->last_stream = stream;
+    return LP_OK;
+}
+
+extern "C" int pset_status(lp_pset *ps, lp_counts *c, uint8_t *status)
+{
+    if (!ps || !c)
+        return fail(LP_EINVAL, "null argument");
+    HIPCHECK(hipStreamSynchronize(ps->last_stream));
+    std::vector<uint8_t> st((size_t)ps->n);
+    HIPCHECK(hipMemcpy(st.data(), ps->dst, st.size(), hipMemcpyDeviceToHost));
+    unsigned long long steps = 0;
+    HIPCHECK(hipMemcpy(&steps, ps->dpsteps, sizeof steps, hipMemcpyDeviceToHost));
+    lp_counts r{};
+    r.n = ps->n;
+    for (uint8_t s : st) {
+        if (s == 0) r.active++;
+        if (s & LP_ST_OOB) r.oob++;
+        if (s & LP_ST_LAND) r.land++;
+        if (s & LP_ST_DELETED) r.deleted++;
+    }
+    r.particle_steps = (int64_t)steps;
+    r.step = ps->step;
+    r.time = ps->t0 + (double)ps->step * (ps->dt != 0.0 ? ps->dt : 0.0);
+    *c = r;
+    if (status)
+        std::memcpy(status, st.data(), st.size());
+    return LP_OK;
+}
+
+extern "C" int pset_get(lp_pset *ps, double *lon, double *lat, double *depth, int32_t *ci,
+                        int32_t *cj, int32_t *ck)
+{
+    if (!ps)
+        return fail(LP_EINVAL, "null argument");
+    HIPCHECK(hipStreamSynchronize(ps->last_stream));
+    const size_t N = (size_t)ps->n;
+    if (lon) HIPCHECK(hipMemcpy(lon, ps->dx, N * 8, hipMemcpyDeviceToHost));
+    if (lat) HIPCHECK(hipMemcpy(lat, ps->dy, N * 8, hipMemcpyDeviceToHost));
+    if (depth && ps->fs->is3d) HIPCHECK(hipMemcpy(depth, ps->dz, N * 8, hipMemcpyDeviceToHost));
+    if (ci || cj || ck) {
+        int32_t *d = nullptr;
+        int rc = dalloc(&d, 3 * N);
+        if (rc)
+            return rc;
+        lp::RecordParams R{};
+        R.g = ps->fs->g;
+        R.x = ps->dx;
+        R.y = ps->dy;
+        R.z = ps->dz;
+        R.status = ps->dst;
+        R.n = ps->n;
+        R.stride = 1;
+        R.nper = ps->n;
+        R.ci = d;
+        R.cj = d + N;
+        R.ck = d + 2 * N;
+        hipError_t e = lp::launch_record(R, nullptr);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e == hipSuccess && ci) e = hipMemcpy(ci, d, N * 4, hipMemcpyDeviceToHost);
+        if (e == hipSuccess && cj) e = hipMemcpy(cj, d + N, N * 4, hipMemcpyDeviceToHost);
+        if (e == hipSuccess && ck) e = hipMemcpy(ck, d + 2 * N, N * 4, hipMemcpyDeviceToHost);
+        dfree(d);
+        HIPCHECK(e);
+    }
+    return LP_OK;
+}
+
+extern "C" int pset_records(lp_pset *ps, int64_t *nrec, int64_t *nper, double *lon, double *lat,
+                            double *depth, uint8_t *status, int32_t *ci, int32_t *cj,
+                            int32_t *ck)
+{
+    if (!ps || !nrec || !nper)
+        return fail(LP_EINVAL, "null argument");
+    *nrec = ps->nrec;
+    *nper = ps->nper;
+    if (!(lon || lat || depth || status || ci || cj || ck))
+        return LP_OK;
+    HIPCHECK(hipStreamSynchronize(ps->last_stream));
+    const size_t T = (size_t)(ps->nrec * ps->nper);
+    if (T == 0)
+        return LP_OK;
+    if (lon) HIPCHECK(hipMemcpy(lon, ps->rx, T * 8, hipMemcpyDeviceToHost));
+    if (lat) HIPCHECK(hipMemcpy(lat, ps->ry, T * 8, hipMemcpyDeviceToHost));
+    if (depth && ps->rz) HIPCHECK(hipMemcpy(depth, ps->rz, T * 8, hipMemcpyDeviceToHost));
+    if (status) HIPCHECK(hipMemcpy(status, ps->rst, T, hipMemcpyDeviceToHost));
+    if (ci) HIPCHECK(hipMemcpy(ci, ps->rci, T * 4, hipMemcpyDeviceToHost));
+    if (cj) HIPCHECK(hipMemcpy(cj, ps->rcj, T * 4, hipMemcpyDeviceToHost));
+    if (ck && ps->rck) HIPCHECK(hipMemcpy(ck, ps->rck, T * 4, hipMemcpyDeviceToHost));
+    return LP_OK;
+}
+
+extern "C" int pset_timing(lp_pset *ps, double *kernel_ms, int64_t *launches)
+{
+    if (!ps || !kernel_ms || !launches)
+        return fail(LP_EINVAL, "null argument");
+    double tot = 0.0;
+    for (auto &p : ps->prof) {
+        HIPCHECK(hipEventSynchronize(p.second));
+        float ms = 0.f;
+        HIPCHECK(hipEventElapsedTime(&ms, p.first, p.second));
+        tot += ms;
+    }
+    *kernel_ms = tot;
+    *launches = (int64_t)ps->prof.size();
+    for (auto &p : ps->prof) {
+        (void)hipEventDestroy(p.first);
+        (void)hipEventDestroy(p.second);
+    }
+    ps->prof.clear();
+    return LP_OK;
+}
+
+extern "C" const char *lp_last_error(void) { return g_err.c_str(); }
+
+extern "C" const char *lp_version(void) { return "lp-mi355x 0.1 (gfx950)"; }

@@ -1,0 +1,100 @@
+// lp_internal.h -- device-side parameter blocks and launcher declarations shared by
+// the library's translation units (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace lp {
+
+constexpr double kMetresPerDegree = 111120.0;  // 1852 m per arc minute
+constexpr double kDegToRad = 0.017453292519943295;
+constexpr int kTile = 16;        // horizontal cells per tile side (sort key)
+constexpr int kGuessBins = 4096; // bins of the cell-guess table of a non-uniform axis
+constexpr int kBlock = 256;      // threads per block of the advection kernels
+
+enum Store : int { kF64 = 0, kF32 = 1, kBF16 = 2, kF16S = 3 };
+
+// One axis of a rectilinear grid.
+struct AxisDev {
+    const double *c;         // n coordinates
+    const double *rw;        // n-1 inverse cell widths 1/(c[i+1]-c[i])
+    const int32_t *guess;    // kGuessBins entries (non-uniform axes) or null
+    double lo, hi;           // c[0], c[n-1]
+    double ginv;             // bins (or cells, if uniform) per unit coordinate
+    int32_t n;
+    int32_t uniform;         // 1: (x-lo)*ginv is the cell to within one
+};
+
+struct GridDev {
+    AxisDev ax, ay, az;      // az.n == 0 in 2D
+    const uint8_t *landcell; // (ny-1)*(nx-1) cells, 1 = four land corners; or null
+    int32_t spherical;
+};
+
+// Bracketing snapshots and weight of one stage time.
+struct TimeEntry {
+    double tau;
+    int32_t sa, sb;          // slot indices
+};
+
+struct FieldDev {
+    const void *slots;       // capacity slots, each slot_bytes long
+    size_t slot_bytes;
+    const float *scales;     // LP_F16_SCALED: [slot][level][var] power-of-two scales
+    int32_t nzl;             // levels per slot (1 in 2D)
+    int32_t steady;          // single snapshot: no time interpolation
+};
+
+struct AdvectParams {
+    GridDev g;
+    FieldDev f;
+    const TimeEntry *tab;    // 2*nsteps+1 entries: t_n, t_n+dt/2, t_n+dt, ...
+    double dt;
+    int64_t step0;           // step index (from t0) of the first step of the launch
+    int32_t nsteps;
+    int32_t policy;          // 0 delete, 1 freeze
+    double Kh;
+    uint32_t run_id, seed;
+    double *x, *y, *z;       // particle state, id order
+    uint8_t *status;
+    const uint32_t *order;   // active ids, processing order
+    const uint32_t *n_active;// device count of `order`
+    unsigned long long *psteps;
+};
+
+struct RecordParams {
+    GridDev g;
+    const double *x, *y, *z;
+    const uint8_t *status;
+    int64_t n, stride, nper;
+    double *rx, *ry, *rz;
+    uint8_t *rst;
+    int32_t *ci, *cj, *ck;
+};
+
+// launchers (return hipError_t of the launch)
+hipError_t launch_advect(int store, bool is3d, const AdvectParams &p, uint32_t n_launch,
+                         hipStream_t s);
+hipError_t launch_record(const RecordParams &p, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
+hipError_t launch_iota(uint32_t *p, size_t n, hipStream_t s);
+hipError_t launch_compact(const uint32_t *order_in, const uint32_t *n_in, const uint8_t *status,
+                          uint32_t *order_out, uint32_t *n_out, uint32_t n_launch,
+                          hipStream_t s);
+hipError_t launch_sort(const GridDev &g, const double *x, const double *y, const double *z,
+                       const uint8_t *status, const uint32_t *order_in, const uint32_t *n_in,
+                       uint32_t n_launch, uint32_t *keys, uint32_t *hist, uint32_t nbins,
+                       uint32_t *blocksums, uint32_t *order_out, uint32_t *n_out,
+                       hipStream_t s);
+uint32_t sort_bins(const GridDev &g);
+size_t sort_blocksums(uint32_t nbins);
+hipError_t launch_convert_snapshot(int store, bool is3d, const float *U, const float *V,
+                                   const float *W, const double *U64, const double *V64,
+                                   const double *W64, size_t plane, int nzl, void *slot,
+                                   float *scales, float *tmp, hipStream_t s);
+hipError_t launch_level_absmax(const float *F, size_t plane, int nzl, float *out,
+                               hipStream_t s);
+
+}  // namespace lp
