@@ -35,7 +35,8 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector (FMA = 2 flops)
 # a division counted as one flop).
 STENCIL_BYTES_2D_F32 = 4 * 2 * 2 * 4     # 64 B
 STATE_BYTES_2D = 8 + 8 + 8 + 8 + 4 + 1 + 1  # lon, lat read + write, order id, status r/w
-FLOPS_2D_STEP = 234
+FLOPS_2D_STEP = 230
+FLOPS_3D_STEP = 567
 
 
 def parse():
@@ -50,6 +51,10 @@ def parse():
     p.add_argument("--sort-every", type=int, default=1)
     p.add_argument("--cpu-baseline", type=int, default=1)
     p.add_argument("--cpu-sample-stride", type=int, default=100)
+    p.add_argument("--config", default="cfg1", choices=["cfg1", "cfg2"])
+    p.add_argument("--stencil-cache", type=int, default=1)
+    p.add_argument("--error-stride", type=int, default=100,
+                   help="cfg2: oracle error report on ids = 0 mod this (0 = skip)")
     return p.parse_args()
 
 
@@ -70,12 +75,146 @@ def cpu_baseline(w, stride: int):
                        f"{st.psteps} particle-steps in {el:.2f} s")
 
 
+def roofline(steps_per_launch, avg_launch_s, bytes_per_step, flops_per_step):
+    hbm_ach = steps_per_launch * bytes_per_step / avg_launch_s / 1e9
+    alu_ach = steps_per_launch * flops_per_step / avg_launch_s / 1e12
+    hbm = {"bound": "hbm", "achieved": round(hbm_ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(hbm_ach / HBM_PEAK_GBS, 4), "traffic": None}
+    alu = {"bound": "alu", "achieved": round(alu_ach, 3), "peak": FP64_VECTOR_PEAK_TFLOPS,
+           "unit": "TFLOP/s", "frac": round(alu_ach / FP64_VECTOR_PEAK_TFLOPS, 4),
+           "traffic": None}
+    return (hbm, alu) if hbm["frac"] >= alu["frac"] else (alu, hbm)
+
+
+def great_circle_km(lon1, lat1, lon2, lat2):
+    R = 111120.0 * 180.0 / np.pi / 1000.0
+    p1, p2 = np.deg2rad(lat1), np.deg2rad(lat2)
+    dl = np.deg2rad(lon2 - lon1)
+    h = np.sin((p2 - p1) / 2) ** 2 + np.cos(p1) * np.cos(p2) * np.sin(dl / 2) ** 2
+    return 2 * R * np.arcsin(np.sqrt(np.clip(h, 0, 1)))
+
+
+def main_cfg2(a):
+    """3D: 10M particles on 3600 x 1800 x 50, 11 daily snapshots built in HBM and
+    streamed through a three-slot ring (two resident, one being converted), the
+    paper's execute-one-day-then-advancetime loop."""
+    import torch
+    from paper_1707_05163_amd import FieldSet, ParticleSet
+    from synthetic import configs as SC
+
+    torch.cuda.set_device(0)
+    w = SC.cfg2_global_3d(n_particles=a.particles if a.particles != 1_000_000 else 10_000_000)
+    days = min(a.days, w.fields.nt - 1)
+    print(f"[bench] workload {w.name}: {w.n} particles x {days * 144} steps, "
+          f"{w.fields.nt} snapshots, building fields in HBM", file=sys.stderr, flush=True)
+    cache = {}
+    snaps = [SC.cfg2_snapshot_torch(w, s, "cuda", cache) for s in range(w.fields.nt)]
+    del cache
+    lon0 = torch.from_numpy(w.lon0).cuda()
+    lat0 = torch.from_numpy(w.lat0).cuda()
+    dep0 = torch.from_numpy(w.depth0).cuda()
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    stride = a.error_stride if a.error_stride > 0 else 0
+    total = 0.0
+    psteps = 0
+    kms = 0.0
+    launches = 0
+    last = None
+    for it in range(a.warmup + a.steps):
+        fs = FieldSet(w.grid.lon, w.grid.lat, w.grid.depth, "spherical", a.dtype, 3, 0.0)
+        ps = ParticleSet(fs, lon0, lat0, dep0, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fs.push_snapshot(w.fields.times[0], *snaps[0], stream=stream)
+        fs.push_snapshot(w.fields.times[1], *snaps[1], stream=stream)
+        for d in range(days):
+            ps.execute(86400.0, w.dt, 86400.0, output_stride=stride, sort_every=a.sort_every,
+                       profile=it >= a.warmup, stencil_cache=bool(a.stencil_cache),
+                       stream=stream)
+            if d + 2 < w.fields.nt:
+                fs.push_snapshot(w.fields.times[d + 2], *snaps[d + 2], stream=stream)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        print(f"[bench] step {it}: {el * 1e3:.1f} ms", file=sys.stderr, flush=True)
+        if it >= a.warmup:
+            total += el
+            c, _ = ps.status()
+            psteps += c["particle_steps"]
+            ms, k = ps.timing()
+            kms += ms
+            launches += k
+        if last is not None:
+            last[0].close()
+            last[1].close()
+        last = (ps, fs)
+    rate = psteps / total
+    avg_launch_s = kms / 1e3 / launches
+    spl = psteps / launches
+    S = 144
+    half = a.dtype != "f32"
+    bytes_per_step = (96 if half else 192) + 56.0 / S
+    roof, other = roofline(spl, avg_launch_s, bytes_per_step, FLOPS_3D_STEP)
+    out = {
+        "metric": "RK4 particle-steps/s", "value": rate, "unit": "particle-steps/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": total / a.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if a.dtype == "f32" else "f64+" + a.dtype,
+        "data": "synthetic",
+        "config": {"workload": w.name, "grid": "3600x1800x50", "snapshots": w.fields.nt,
+                   "ring_slots": 3, "particles": w.n, "rk4_steps": days * 144, "dt_s": w.dt,
+                   "field_dtype": a.dtype, "stencil_cache": a.stencil_cache,
+                   "sort_every": a.sort_every},
+        "roofline": roof, "roofline_other": other,
+        "kernel": {"name": "k_advect3d" if a.stencil_cache else "k_advect", "launches": launches,
+                   "avg_launch_ms": round(avg_launch_s * 1e3, 4),
+                   "particle_steps_per_launch": spl,
+                   "kernel_share_of_step": round(kms / 1e3 / total, 4)},
+    }
+    if stride:
+        # error in km against the FP64 oracle on the unquantised float32 fields
+        from oracle import oracle as O
+        print("[bench] oracle on the error subset", file=sys.stderr, flush=True)
+        recs = last[0].records()
+        ids = np.arange(0, w.n, stride)
+        shape = (days + 1,) + tuple(snaps[0][0].shape)
+        U, V, W = (np.empty(shape, np.float32) for _ in range(3))
+        for q in range(days + 1):
+            U[q] = snaps[q][0].cpu().numpy()
+            V[q] = snaps[q][1].cpu().numpy()
+            W[q] = snaps[q][2].cpu().numpy()
+        ofs = O.OracleFieldSet(w.grid.lon, w.grid.lat, w.grid.depth, w.fields.times[: days + 1],
+                               U, V, W, spherical=True)
+        st = O.make_state(w.lon0[ids], w.lat0[ids], w.depth0[ids], pid=ids.astype(np.uint32))
+        t = time.perf_counter()
+        rc = O.advance(ofs, st, w.dt, days * 144, nthreads=O.max_threads())
+        ot = time.perf_counter() - t
+        assert rc == 0
+        g_lon, g_lat = recs["lon"][-1], recs["lat"][-1]
+        both = (st.status == 0) & (recs["status"][-1] == 0)
+        km = great_circle_km(g_lon[both], g_lat[both], st.x[both], st.y[both])
+        out["error_km_vs_fp64_oracle"] = {
+            "subset": f"ids = 0 mod {stride} ({ids.size})", "compared": int(both.sum()),
+            "status_mismatch": int((st.status != recs["status"][-1]).sum()),
+            "median": float(np.median(km)), "p95": float(np.percentile(km, 95)),
+            "max": float(km.max()), "depth_max_m": float(np.abs(recs["depth"][-1][both] - st.z[both]).max())}
+        if a.cpu_baseline:
+            out["cpu_baseline"] = dict(value=st.psteps / ot, unit="particle-steps/s",
+                                       cores=O.max_threads(), kind="oracle",
+                                       sample=f"ids = 0 mod {stride} ({ids.size}) for "
+                                              f"{days * 144} steps: {st.psteps} particle-steps "
+                                              f"in {ot:.2f} s")
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": a.gpus}))
         sys.exit(2)
+    if a.config == "cfg2":
+        return main_cfg2(a)
     import torch
     from paper_1707_05163_amd import FieldSet, ParticleSet
     from synthetic import configs as SC
@@ -95,7 +234,8 @@ def main():
 
     def step(ps, profile):
         ps.execute(runtime, w.dt, w.outputdt, output_stride=a.output_stride,
-                   sort_every=a.sort_every, profile=profile, stream=stream)
+                   sort_every=a.sort_every, profile=profile,
+                   stencil_cache=bool(a.stencil_cache), stream=stream)
 
     for i in range(a.warmup):
         step(psets[i], False)
@@ -120,13 +260,7 @@ def main():
     steps_per_launch = psteps / launches
     S = w.outputdt / w.dt
     bytes_per_step = STENCIL_BYTES_2D_F32 * (0.5 if a.dtype != "f32" else 1.0) + STATE_BYTES_2D / S
-    hbm_ach = steps_per_launch * bytes_per_step / avg_launch_s / 1e9
-    alu_ach = steps_per_launch * FLOPS_2D_STEP / avg_launch_s / 1e12
-    hbm = {"bound": "hbm", "achieved": round(hbm_ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": round(hbm_ach / HBM_PEAK_GBS, 4), "traffic": None}
-    alu = {"bound": "alu", "achieved": round(alu_ach, 3), "peak": FP64_VECTOR_PEAK_TFLOPS,
-           "unit": "TFLOP/s", "frac": round(alu_ach / FP64_VECTOR_PEAK_TFLOPS, 4), "traffic": None}
-    roof, other = (hbm, alu) if hbm["frac"] >= alu["frac"] else (alu, hbm)
+    roof, other = roofline(steps_per_launch, avg_launch_s, bytes_per_step, FLOPS_2D_STEP)
     out = {
         "metric": "RK4 particle-steps/s",
         "value": rate,

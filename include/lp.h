@@ -135,6 +135,10 @@ typedef struct {
     int32_t sort_every;   /* re-sort particles by grid tile every k output
                              segments (0 = never) */
     int32_t profile;      /* 1: time each advection launch with HIP events */
+    int32_t stencil_cache;/* 1: each lane keeps its cell's stencil in registers and
+                             reloads it only when it changes cell or snapshot pair;
+                             0: gather the stencil at every stage (same results up
+                             to rounding) */
 } lp_exec_opts;
 
 /* Advance every active particle by runtime/dt steps of dt (dt > 0), taking an

@@ -38,7 +38,8 @@ class lp_grid_desc(C.Structure):
 class lp_exec_opts(C.Structure):
     _fields_ = [("kernel", C.c_int32), ("recovery", C.c_int32), ("Kh", C.c_double),
                 ("run_id", C.c_uint32), ("seed", C.c_uint32), ("output_stride", C.c_int32),
-                ("sort_every", C.c_int32), ("profile", C.c_int32)]
+                ("sort_every", C.c_int32), ("profile", C.c_int32),
+                ("stencil_cache", C.c_int32)]
 
 
 class lp_counts(C.Structure):
@@ -83,6 +84,14 @@ def _declare(L):
 
 
 def load():
+    # torch carries its own HIP runtime (soname libamdhip64.so.7).  Loading torch
+    # first makes this library bind to that same runtime instance, so the stream
+    # handles and device pointers torch hands over are valid here; loading the
+    # library first would put a second HIP runtime into the process.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIBPATH):
         raise ImportError(f"HIP library not built: {LIBPATH} is missing "
                           "(run __graft_entry__.build())")

@@ -143,10 +143,10 @@ class ParticleSet:
     def execute(self, runtime: float, dt: float, outputdt: float = 0.0,
                 recovery: str = "delete", Kh: float = 0.0, run_id: int = 0, seed: int = SEED,
                 output_stride: int = 0, sort_every: int = 1, profile: bool = False,
-                stream=None):
+                stencil_cache: bool = True, stream=None):
         o = L.lp_exec_opts(L.LP_KERNEL_RK4, _RECOVERY[recovery], float(Kh), int(run_id),
                            int(seed) & 0xFFFFFFFF, int(output_stride), int(sort_every),
-                           int(bool(profile)))
+                           int(bool(profile)), int(bool(stencil_cache)))
         L.check(L.lib.pset_execute(self._h, float(runtime), float(dt), float(outputdt),
                                    C.byref(o), _stream(stream)))
 

@@ -322,6 +322,516 @@ __global__ __launch_bounds__(kBlock) void k_advect(AdvectParams P)
         atomicAdd(P.psteps, (unsigned long long)steps);
 }
 
+// ---------------------------------------------------------------- 2D with a stencil cache
+// Each lane keeps the stencil of the cell it is in, as the coefficients of the
+// bilinear polynomial f = c0 + c1 xi + c2 eta + c3 xi eta of U and V for the
+// earlier snapshot and for the difference (later - earlier).  A stage point in the
+// cached cell then costs only arithmetic: the stencil is reloaded when the point
+// leaves the cell or when the time bracket moves on.  The polynomial is the same
+// bilinear interpolant as the corner-weight form (Sect. 2.3), and f_a + tau (f_b -
+// f_a) is the same linear time interpolation (Sect. 2.4); only rounding differs.
+template <class R>
+struct Cell2 {
+    double x0, ux, y0, uy;  // lower faces; exclusive upper faces (+inf for the last cell)
+    double rx, ry;          // inverse cell widths
+    double cl, sl;          // cos and sin of the lower latitude face
+    R a[2][4];              // earlier snapshot: U, V coefficients
+    R d[2][4];              // later minus earlier
+    bool land;
+    bool valid;
+};
+
+template <class R>
+__device__ inline void coeffs(const R f00, const R f10, const R f01, const R f11, R c[4])
+{
+    c[0] = f00;
+    c[1] = f10 - f00;
+    c[2] = f01 - f00;
+    c[3] = (f11 - f10) - c[2];
+}
+
+template <class R>
+__device__ inline R poly(const R c[4], R xi, R eta)
+{
+    return fma(eta, fma(xi, c[3], c[2]), fma(xi, c[1], c[0]));
+}
+
+template <int ST, bool STEADY>
+__device__ inline bool reload2(const AdvectParams &P, Cell2<typename Real<ST>::T> &c, int sa,
+                               int sb, double x, double y)
+{
+    using R = typename Real<ST>::T;
+    int i, j;
+    double f;
+    if (!locate(P.g.ax, x, i, f) || !locate(P.g.ay, y, j, f))
+        return false;
+    const AxisDev &ax = P.g.ax, &ay = P.g.ay;
+    c.x0 = ax.c[i];
+    c.ux = (i == ax.n - 2) ? __builtin_inf() : ax.c[i + 1];
+    c.rx = ax.rw[i];
+    c.y0 = ay.c[j];
+    c.uy = (j == ay.n - 2) ? __builtin_inf() : ay.c[j + 1];
+    c.ry = ay.rw[j];
+    if (P.g.coslat) {
+        c.cl = P.g.coslat[j];
+        c.sl = P.g.sinlat[j];
+    }
+    const size_t nx = (size_t)ax.n;
+    c.land = P.g.landcell ? P.g.landcell[(size_t)j * (nx - 1) + (size_t)i] != 0 : false;
+    const size_t n00 = (size_t)j * nx + (size_t)i;
+    const char *base = static_cast<const char *>(P.f.slots);
+    const char *A = base + (size_t)sa * P.f.slot_bytes;
+    const float *sca = ST == kF16S ? P.f.scales + (size_t)sa * P.f.nzl * 3 : nullptr;
+    R p00[3], p10[3], p01[3], p11[3];
+    load_node<ST, false>(A, n00, sca, p00);
+    load_node<ST, false>(A, n00 + 1, sca, p10);
+    load_node<ST, false>(A, n00 + nx, sca, p01);
+    load_node<ST, false>(A, n00 + nx + 1, sca, p11);
+    if constexpr (!STEADY) {
+        const char *B = base + (size_t)sb * P.f.slot_bytes;
+        const float *scb = ST == kF16S ? P.f.scales + (size_t)sb * P.f.nzl * 3 : nullptr;
+        R q00[3], q10[3], q01[3], q11[3];
+        load_node<ST, false>(B, n00, scb, q00);
+        load_node<ST, false>(B, n00 + 1, scb, q10);
+        load_node<ST, false>(B, n00 + nx, scb, q01);
+        load_node<ST, false>(B, n00 + nx + 1, scb, q11);
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+            R cb[4];
+            coeffs<R>(q00[v], q10[v], q01[v], q11[v], cb);
+            coeffs<R>(p00[v], p10[v], p01[v], p11[v], c.a[v]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                c.d[v][q] = cb[q] - c.a[v][q];
+        }
+    } else {
+#pragma unroll
+        for (int v = 0; v < 2; ++v)
+            coeffs<R>(p00[v], p10[v], p01[v], p11[v], c.a[v]);
+    }
+    c.valid = true;
+    return true;
+}
+
+template <class R>
+__device__ inline bool in_cell(const Cell2<R> &c, const AdvectParams &P, double x, double y)
+{
+    return c.valid && x >= c.x0 && x < c.ux && x <= P.g.ax.hi && y >= c.y0 && y < c.uy &&
+           y <= P.g.ay.hi;
+}
+
+// 1 / d to within an ulp or two: hardware reciprocal refined by two Newton steps
+__device__ inline double recip(double d)
+{
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(fma(-d, r, 1.0), r, r);
+    r = fma(fma(-d, r, 1.0), r, r);
+    return r;
+}
+
+// cos of a latitude inside the cached cell: cos(l0 + dl) = cos l0 cos dl - sin l0 sin dl
+// with dl = lat - l0 (at most 5 degrees) and cos dl, sin dl by their Taylor series to
+// order dl^8 / dl^9 (truncation below 1e-17).
+template <class R>
+__device__ inline double cos_lat(const Cell2<R> &c, const AdvectParams &P, double y)
+{
+    if (!P.g.coslat)
+        return cos(y * kDegToRad);
+    const double dl = (y - c.y0) * kDegToRad, d2 = dl * dl;
+    const double cd = fma(d2, fma(d2, fma(d2, fma(d2, 1.0 / 40320.0, -1.0 / 720.0), 1.0 / 24.0),
+                                  -0.5), 1.0);
+    const double sd = dl * fma(d2, fma(d2, fma(d2, fma(d2, 1.0 / 362880.0, -1.0 / 5040.0),
+                                                1.0 / 120.0), -1.0 / 6.0), 1.0);
+    return c.cl * cd - c.sl * sd;
+}
+
+template <int ST, bool STEADY, bool SPH>
+__device__ inline bool stage2(const AdvectParams &P, Cell2<typename Real<ST>::T> &c,
+                              const TimeEntry &e, double x, double y, double &kx, double &ky)
+{
+    using R = typename Real<ST>::T;
+    if (!in_cell(c, P, x, y)) {
+        if (!reload2<ST, STEADY>(P, c, e.sa, e.sb, x, y))
+            return false;
+    }
+    const R xi = (R)((x - c.x0) * c.rx), eta = (R)((y - c.y0) * c.ry);
+    R u = poly<R>(c.a[0], xi, eta), v = poly<R>(c.a[1], xi, eta);
+    if constexpr (!STEADY) {
+        const R tau = (R)e.tau;
+        u = fma(tau, poly<R>(c.d[0], xi, eta), u);
+        v = fma(tau, poly<R>(c.d[1], xi, eta), v);
+    }
+    if constexpr (SPH) {
+        kx = (double)u * recip(kMetresPerDegree * cos_lat(c, P, y));
+        ky = (double)v * (1.0 / kMetresPerDegree);
+    } else {
+        kx = (double)u;
+        ky = (double)v;
+    }
+    return true;
+}
+
+template <int ST, bool STEADY, bool SPH>
+__global__ __launch_bounds__(kBlock) void k_advect2d(AdvectParams P)
+{
+    using R = typename Real<ST>::T;
+    const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const uint32_t k = blk * kBlock + threadIdx.x;
+    const uint32_t nact = *P.n_active;
+    long long steps = 0;
+    if (k < nact) {
+        const uint32_t id = P.order[k];
+        uint8_t st = P.status[id];
+        if (st == 0) {
+            double x = P.x[id], y = P.y[id];
+            Cell2<R> c;
+            c.valid = false;
+            int csa = -1, csb = -1;  // bracket the cached stencils belong to
+            const double dt = P.dt, hd = 0.5 * dt, dt6 = dt * (1.0 / 6.0);
+            for (int s = 0; s < P.nsteps; ++s) {
+                ++steps;
+                const TimeEntry e0 = P.tab[2 * s], e1 = P.tab[2 * s + 1], e2 = P.tab[2 * s + 2];
+                uint8_t err = ST_OOB;
+                // the four stages: offsets 0, dt/2, dt/2, dt from X_n along the previous
+                // slope; weights 1, 2, 2, 1
+                double kx = 0.0, ky = 0.0, sx = 0.0, sy = 0.0;
+#pragma nounroll
+                for (int q = 0; q < 4; ++q) {
+                    const TimeEntry e = q == 0 ? e0 : (q == 3 ? e2 : e1);
+                    const double h = q == 0 ? 0.0 : (q == 3 ? dt : hd);
+                    if (e.sa != csa || e.sb != csb) {
+                        c.valid = false;
+                        csa = e.sa;
+                        csb = e.sb;
+                    }
+                    if (!stage2<ST, STEADY, SPH>(P, c, e, x + kx * h, y + ky * h, kx, ky))
+                        goto fail;
+                    if (q == 1 || q == 2) {
+                        sx += 2.0 * kx;
+                        sy += 2.0 * ky;
+                    } else if (q == 0) {
+                        sx = kx;
+                        sy = ky;
+                    }
+                }
+                {
+                    double xs = x + (sx + kx) * dt6;
+                    double ys = y + (sy + ky) * dt6;
+                    if (P.Kh > 0.0) {
+                        uint32_t w[4] = {id, (uint32_t)(P.step0 + s), 0u, 0u};
+                        philox4x32_10(w, P.run_id, P.seed);
+                        const double u1 = unit53(w[0], w[1]), u2 = unit53(w[2], w[3]);
+                        const double r = sqrt(-2.0 * log(u1));
+                        double sn, cs;
+                        sincos((2.0 * 3.141592653589793) * u2, &sn, &cs);
+                        const double sig = sqrt(2.0 * P.Kh * dt);
+                        double dx = sig * (r * cs), dy = sig * (r * sn);
+                        if constexpr (SPH) {
+                            dx = dx / (kMetresPerDegree * cos(ys * kDegToRad));
+                            dy = dy / kMetresPerDegree;
+                        }
+                        xs = xs + dx;
+                        ys = ys + dy;
+                    }
+                    bool land;
+                    if (in_cell(c, P, xs, ys)) {
+                        land = c.land;
+                    } else {
+                        int ci, cj;
+                        double f;
+                        if (!locate(P.g.ax, xs, ci, f) || !locate(P.g.ay, ys, cj, f))
+                            goto fail;
+                        land = P.g.landcell &&
+                               P.g.landcell[(size_t)cj * (size_t)(P.g.ax.n - 1) + (size_t)ci];
+                    }
+                    if (land) {
+                        err = ST_LAND;
+                        goto fail;
+                    }
+                    x = xs;
+                    y = ys;
+                }
+                continue;
+            fail:
+                st = (uint8_t)(err | (P.policy == 0 ? ST_DELETED : 0));
+                break;
+            }
+            P.x[id] = x;
+            P.y[id] = y;
+            if (st)
+                P.status[id] = st;
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1)
+        steps += __shfl_xor(steps, off, 64);
+    if ((threadIdx.x & 63) == 0 && steps)
+        atomicAdd(P.psteps, (unsigned long long)steps);
+}
+
+// ---------------------------------------------------------------- 3D with a stencil cache
+// Same scheme in three dimensions: the trilinear interpolant of U, V, W in the
+// cached cell written as c0 + c1 xi + c2 eta + c3 zeta + c4 xi eta + c5 xi zeta +
+// c6 eta zeta + c7 xi eta zeta, for the earlier snapshot and the difference.
+template <class R>
+struct Cell3 {
+    double x0, ux, y0, uy, z0, uz;
+    double rx, ry, rz;
+    double cl, sl;
+    R a[3][8];
+    R d[3][8];
+    bool land;
+    bool valid;
+};
+
+template <class R>
+__device__ inline void coeffs3(const R f[8], R c[8])
+{
+    // f index = di + 2 dj + 4 dk
+    c[0] = f[0];
+    c[1] = f[1] - f[0];
+    c[2] = f[2] - f[0];
+    c[3] = f[4] - f[0];
+    c[4] = (f[3] - f[2]) - c[1];
+    c[5] = (f[5] - f[4]) - c[1];
+    c[6] = (f[6] - f[4]) - c[2];
+    c[7] = ((f[7] - f[6]) - (f[5] - f[4])) - ((f[3] - f[2]) - c[1]);
+}
+
+template <class R>
+__device__ inline R poly3(const R c[8], R xi, R eta, R zeta)
+{
+    const R tx = fma(zeta, c[5], fma(eta, fma(zeta, c[7], c[4]), c[1]));
+    const R r = fma(eta, fma(zeta, c[6], c[2]), fma(zeta, c[3], c[0]));
+    return fma(xi, tx, r);
+}
+
+template <int ST, bool STEADY>
+__device__ inline bool reload3(const AdvectParams &P, Cell3<typename Real<ST>::T> &c, int sa,
+                               int sb, double x, double y, double z)
+{
+    using R = typename Real<ST>::T;
+    int i, j, k;
+    double f;
+    if (!locate(P.g.ax, x, i, f) || !locate(P.g.ay, y, j, f) || !locate(P.g.az, z, k, f))
+        return false;
+    const AxisDev &ax = P.g.ax, &ay = P.g.ay, &az = P.g.az;
+    c.x0 = ax.c[i];
+    c.ux = (i == ax.n - 2) ? __builtin_inf() : ax.c[i + 1];
+    c.rx = ax.rw[i];
+    c.y0 = ay.c[j];
+    c.uy = (j == ay.n - 2) ? __builtin_inf() : ay.c[j + 1];
+    c.ry = ay.rw[j];
+    c.z0 = az.c[k];
+    c.uz = (k == az.n - 2) ? __builtin_inf() : az.c[k + 1];
+    c.rz = az.rw[k];
+    if (P.g.coslat) {
+        c.cl = P.g.coslat[j];
+        c.sl = P.g.sinlat[j];
+    }
+    const size_t nx = (size_t)ax.n, plane = nx * (size_t)ay.n;
+    c.land = P.g.landcell ? P.g.landcell[(size_t)j * (nx - 1) + (size_t)i] != 0 : false;
+    const size_t n000 = (size_t)k * plane + (size_t)j * nx + (size_t)i;
+    const size_t off[8] = {0, 1, nx, nx + 1, plane, plane + 1, plane + nx, plane + nx + 1};
+    const char *base = static_cast<const char *>(P.f.slots);
+    {
+        const char *A = base + (size_t)sa * P.f.slot_bytes;
+        R fa[3][8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const float *sc = ST == kF16S ? P.f.scales + ((size_t)sa * P.f.nzl + k + (q >> 2)) * 3
+                                          : nullptr;
+            R v[3];
+            load_node<ST, true>(A, n000 + off[q], sc, v);
+            fa[0][q] = v[0];
+            fa[1][q] = v[1];
+            fa[2][q] = v[2];
+        }
+#pragma unroll
+        for (int v = 0; v < 3; ++v)
+            coeffs3<R>(fa[v], c.a[v]);
+    }
+    if constexpr (!STEADY) {
+        const char *B = base + (size_t)sb * P.f.slot_bytes;
+        R fb[3][8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const float *sc = ST == kF16S ? P.f.scales + ((size_t)sb * P.f.nzl + k + (q >> 2)) * 3
+                                          : nullptr;
+            R v[3];
+            load_node<ST, true>(B, n000 + off[q], sc, v);
+            fb[0][q] = v[0];
+            fb[1][q] = v[1];
+            fb[2][q] = v[2];
+        }
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+            R cb[8];
+            coeffs3<R>(fb[v], cb);
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                c.d[v][q] = cb[q] - c.a[v][q];
+        }
+    }
+    c.valid = true;
+    return true;
+}
+
+template <class R>
+__device__ inline bool in_cell3(const Cell3<R> &c, const AdvectParams &P, double x, double y,
+                                double z)
+{
+    return c.valid && x >= c.x0 && x < c.ux && x <= P.g.ax.hi && y >= c.y0 && y < c.uy &&
+           y <= P.g.ay.hi && z >= c.z0 && z < c.uz && z <= P.g.az.hi;
+}
+
+template <int ST, bool STEADY, bool SPH>
+__device__ inline bool stage3(const AdvectParams &P, Cell3<typename Real<ST>::T> &c,
+                              const TimeEntry &e, double x, double y, double z, double k[3])
+{
+    using R = typename Real<ST>::T;
+    if (!in_cell3(c, P, x, y, z)) {
+        if (!reload3<ST, STEADY>(P, c, e.sa, e.sb, x, y, z))
+            return false;
+    }
+    const R xi = (R)((x - c.x0) * c.rx), eta = (R)((y - c.y0) * c.ry);
+    const R zeta = (R)((z - c.z0) * c.rz);
+    R v[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        v[q] = poly3<R>(c.a[q], xi, eta, zeta);
+        if constexpr (!STEADY)
+            v[q] = fma((R)e.tau, poly3<R>(c.d[q], xi, eta, zeta), v[q]);
+    }
+    if constexpr (SPH) {
+        double cosl;
+        if (P.g.coslat) {
+            const double dl = (y - c.y0) * kDegToRad, d2 = dl * dl;
+            const double cd = fma(d2, fma(d2, fma(d2, fma(d2, 1.0 / 40320.0, -1.0 / 720.0),
+                                                  1.0 / 24.0), -0.5), 1.0);
+            const double sd = dl * fma(d2, fma(d2, fma(d2, fma(d2, 1.0 / 362880.0,
+                                                                -1.0 / 5040.0), 1.0 / 120.0),
+                                                -1.0 / 6.0), 1.0);
+            cosl = c.cl * cd - c.sl * sd;
+        } else {
+            cosl = cos(y * kDegToRad);
+        }
+        k[0] = (double)v[0] * recip(kMetresPerDegree * cosl);
+        k[1] = (double)v[1] * (1.0 / kMetresPerDegree);
+    } else {
+        k[0] = (double)v[0];
+        k[1] = (double)v[1];
+    }
+    k[2] = (double)v[2];
+    return true;
+}
+
+template <int ST, bool STEADY, bool SPH>
+__global__ __launch_bounds__(kBlock) void k_advect3d(AdvectParams P)
+{
+    using R = typename Real<ST>::T;
+    const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const uint32_t kk = blk * kBlock + threadIdx.x;
+    const uint32_t nact = *P.n_active;
+    long long steps = 0;
+    if (kk < nact) {
+        const uint32_t id = P.order[kk];
+        uint8_t st = P.status[id];
+        if (st == 0) {
+            double x = P.x[id], y = P.y[id], z = P.z[id];
+            Cell3<R> c;
+            c.valid = false;
+            int csa = -1, csb = -1;
+            const double dt = P.dt, hd = 0.5 * dt, dt6 = dt * (1.0 / 6.0);
+            for (int s = 0; s < P.nsteps; ++s) {
+                ++steps;
+                const TimeEntry e0 = P.tab[2 * s], e1 = P.tab[2 * s + 1], e2 = P.tab[2 * s + 2];
+                uint8_t err = ST_OOB;
+                double k[3] = {0.0, 0.0, 0.0}, sm[3] = {0.0, 0.0, 0.0};
+#pragma nounroll
+                for (int q = 0; q < 4; ++q) {
+                    const TimeEntry e = q == 0 ? e0 : (q == 3 ? e2 : e1);
+                    const double h = q == 0 ? 0.0 : (q == 3 ? dt : hd);
+                    if (e.sa != csa || e.sb != csb) {
+                        c.valid = false;
+                        csa = e.sa;
+                        csb = e.sb;
+                    }
+                    if (!stage3<ST, STEADY, SPH>(P, c, e, x + k[0] * h, y + k[1] * h,
+                                                 z + k[2] * h, k))
+                        goto fail;
+#pragma unroll
+                    for (int v = 0; v < 3; ++v)
+                        sm[v] = q == 0 ? k[v] : (q == 3 ? sm[v] : fma(2.0, k[v], sm[v]));
+                }
+                {
+                    double xs = x + (sm[0] + k[0]) * dt6;
+                    double ys = y + (sm[1] + k[1]) * dt6;
+                    const double zs = z + (sm[2] + k[2]) * dt6;
+                    if (P.Kh > 0.0) {
+                        uint32_t w[4] = {id, (uint32_t)(P.step0 + s), 0u, 0u};
+                        philox4x32_10(w, P.run_id, P.seed);
+                        const double u1 = unit53(w[0], w[1]), u2 = unit53(w[2], w[3]);
+                        const double r = sqrt(-2.0 * log(u1));
+                        double sn, cs;
+                        sincos((2.0 * 3.141592653589793) * u2, &sn, &cs);
+                        const double sig = sqrt(2.0 * P.Kh * dt);
+                        double dx = sig * (r * cs), dy = sig * (r * sn);
+                        if constexpr (SPH) {
+                            dx = dx / (kMetresPerDegree * cos(ys * kDegToRad));
+                            dy = dy / kMetresPerDegree;
+                        }
+                        xs = xs + dx;
+                        ys = ys + dy;
+                    }
+                    bool land;
+                    if (in_cell3(c, P, xs, ys, zs)) {
+                        land = c.land;
+                    } else {
+                        int ci, cj, ck;
+                        double f;
+                        if (!locate(P.g.ax, xs, ci, f) || !locate(P.g.ay, ys, cj, f) ||
+                            !locate(P.g.az, zs, ck, f))
+                            goto fail;
+                        land = P.g.landcell &&
+                               P.g.landcell[(size_t)cj * (size_t)(P.g.ax.n - 1) + (size_t)ci];
+                    }
+                    if (land) {
+                        err = ST_LAND;
+                        goto fail;
+                    }
+                    x = xs;
+                    y = ys;
+                    z = zs;
+                }
+                continue;
+            fail:
+                st = (uint8_t)(err | (P.policy == 0 ? ST_DELETED : 0));
+                break;
+            }
+            P.x[id] = x;
+            P.y[id] = y;
+            P.z[id] = z;
+            if (st)
+                P.status[id] = st;
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1)
+        steps += __shfl_xor(steps, off, 64);
+    if ((threadIdx.x & 63) == 0 && steps)
+        atomicAdd(P.psteps, (unsigned long long)steps);
+}
+
+__global__ void k_lat_tables(const double *lat, int ny, double *cl, double *sl)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < ny) {
+        double s, c;
+        sincos(lat[j] * kDegToRad, &s, &c);
+        cl[j] = c;
+        sl[j] = s;
+    }
+}
+
 // Output record (or cell-index query) of the particles with id = r * stride.
 __global__ void k_record(RecordParams R)
 {
@@ -356,11 +866,42 @@ hipError_t launch3(const AdvectParams &p, bool steady, uint32_t n_launch, hipStr
     const uint32_t blocks = (n_launch + kBlock - 1) / kBlock;
     if (blocks == 0)
         return hipSuccess;
-    if (steady)
-        hipLaunchKernelGGL((k_advect<ST, IS3D, true>), dim3(blocks), dim3(kBlock), 0, s, p);
-    else
-        hipLaunchKernelGGL((k_advect<ST, IS3D, false>), dim3(blocks), dim3(kBlock), 0, s, p);
-    return hipGetLastError();
+    if (!p.cache) {
+        if (steady)
+            hipLaunchKernelGGL((k_advect<ST, IS3D, true>), dim3(blocks), dim3(kBlock), 0, s, p);
+        else
+            hipLaunchKernelGGL((k_advect<ST, IS3D, false>), dim3(blocks), dim3(kBlock), 0, s, p);
+        return hipGetLastError();
+    }
+    if constexpr (!IS3D) {
+        const dim3 g(blocks), b(kBlock);
+        if (p.g.spherical) {
+            if (steady)
+                hipLaunchKernelGGL((k_advect2d<ST, true, true>), g, b, 0, s, p);
+            else
+                hipLaunchKernelGGL((k_advect2d<ST, false, true>), g, b, 0, s, p);
+        } else {
+            if (steady)
+                hipLaunchKernelGGL((k_advect2d<ST, true, false>), g, b, 0, s, p);
+            else
+                hipLaunchKernelGGL((k_advect2d<ST, false, false>), g, b, 0, s, p);
+        }
+        return hipGetLastError();
+    } else {
+        const dim3 g(blocks), b(kBlock);
+        if (p.g.spherical) {
+            if (steady)
+                hipLaunchKernelGGL((k_advect3d<ST, true, true>), g, b, 0, s, p);
+            else
+                hipLaunchKernelGGL((k_advect3d<ST, false, true>), g, b, 0, s, p);
+        } else {
+            if (steady)
+                hipLaunchKernelGGL((k_advect3d<ST, true, false>), g, b, 0, s, p);
+            else
+                hipLaunchKernelGGL((k_advect3d<ST, false, false>), g, b, 0, s, p);
+        }
+        return hipGetLastError();
+    }
 }
 
 }  // namespace
@@ -380,6 +921,14 @@ hipError_t launch_advect(int store, bool is3d, const AdvectParams &p, uint32_t n
                             : launch3<kF16S, false>(p, steady, n_launch, s);
     }
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_lat_tables(const double *lat, int ny, double *coslat, double *sinlat,
+                              hipStream_t s)
+{
+    hipLaunchKernelGGL(k_lat_tables, dim3((ny + 255) / 256), dim3(256), 0, s, lat, ny, coslat,
+                       sinlat);
+    return hipGetLastError();
 }
 
 hipError_t launch_record(const RecordParams &p, hipStream_t s)

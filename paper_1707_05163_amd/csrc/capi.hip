@@ -162,6 +162,7 @@ struct lp_fieldset {
     DevAxis dx_, dy_, dz_;
     GridDev g{};
     uint8_t *dland = nullptr;
+    double *dcoslat = nullptr, *dsinlat = nullptr;
     char *dslots = nullptr;
     size_t slot_bytes = 0;
     float *dscales = nullptr;
@@ -258,6 +259,22 @@ extern "C" int fieldset_create(const lp_grid_desc *g, lp_fieldset **out)
     if (fs->is3d && (rc = upload_axis(hz, fs->dz_, fs->g.az)))
         return bail(rc);
     fs->g.spherical = g->mesh == LP_MESH_SPHERICAL;
+    if (fs->g.spherical) {
+        double tallest = 0.0;
+        for (int j = 0; j + 1 < g->ny; ++j)
+            tallest = std::max(tallest, g->lat[j + 1] - g->lat[j]);
+        if (tallest <= 5.0) {  // cos(lat) from per-node tables plus a short series
+            if ((rc = dalloc(&fs->dcoslat, (size_t)g->ny)) ||
+                (rc = dalloc(&fs->dsinlat, (size_t)g->ny)))
+                return bail(rc);
+            if (lp::launch_lat_tables(fs->g.ay.c, g->ny, fs->dcoslat, fs->dsinlat, nullptr) !=
+                    hipSuccess ||
+                hipDeviceSynchronize() != hipSuccess)
+                return bail(fail(LP_EDEVICE, "latitude table kernel failed"));
+            fs->g.coslat = fs->dcoslat;
+            fs->g.sinlat = fs->dsinlat;
+        }
+    }
     if (g->land) {
         std::vector<uint8_t> cell((size_t)(g->ny - 1) * (g->nx - 1));
         const size_t nx = g->nx;
@@ -306,6 +323,8 @@ extern "C" void fieldset_destroy(lp_fieldset *fs)
     free_axis(fs->dy_);
     free_axis(fs->dz_);
     dfree(fs->dland);
+    dfree(fs->dcoslat);
+    dfree(fs->dsinlat);
     dfree(fs->dslots);
     dfree(fs->dscales);
     dfree(fs->dtmp);
@@ -779,6 +798,7 @@ extern "C" int pset_execute(lp_pset *ps, double runtime, double dt, double outpu
     P.f.steady = (fs->npushed == 1) ? 1 : 0;
     P.dt = dt;
     P.policy = o->recovery == LP_DELETE ? 0 : 1;
+    P.cache = o->stencil_cache ? 1 : 0;
     P.Kh = o->Kh;
     P.run_id = o->run_id;
     P.seed = o->seed;

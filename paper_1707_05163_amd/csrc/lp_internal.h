@@ -30,6 +30,8 @@ struct AxisDev {
 struct GridDev {
     AxisDev ax, ay, az;      // az.n == 0 in 2D
     const uint8_t *landcell; // (ny-1)*(nx-1) cells, 1 = four land corners; or null
+    const double *coslat;    // cos and sin of each latitude node (spherical meshes whose
+    const double *sinlat;    // cells are at most 5 degrees tall), else null
     int32_t spherical;
 };
 
@@ -55,6 +57,7 @@ struct AdvectParams {
     int64_t step0;           // step index (from t0) of the first step of the launch
     int32_t nsteps;
     int32_t policy;          // 0 delete, 1 freeze
+    int32_t cache;           // 1: register stencil cache kernels
     double Kh;
     uint32_t run_id, seed;
     double *x, *y, *z;       // particle state, id order
@@ -94,6 +97,8 @@ hipError_t launch_convert_snapshot(int store, bool is3d, const float *U, const f
                                    const float *W, const double *U64, const double *V64,
                                    const double *W64, size_t plane, int nzl, void *slot,
                                    float *scales, float *tmp, hipStream_t s);
+hipError_t launch_lat_tables(const double *lat, int ny, double *coslat, double *sinlat,
+                              hipStream_t s);
 hipError_t launch_level_absmax(const float *F, size_t plane, int nzl, float *out,
                                hipStream_t s);
 

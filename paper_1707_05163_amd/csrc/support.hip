@@ -35,11 +35,18 @@ uint32_t grid_blocks(size_t n, uint32_t threads, uint32_t cap = 1u << 16)
 }
 
 // Keep the ids whose status is still 0.  Each wave finds its survivors with a
-// ballot, ranks them with mbcnt and reserves room with one atomic.
-__global__ __launch_bounds__(256) void k_compact(const uint32_t *order_in, const uint32_t *n_in,
-                                                 const uint8_t *status, uint32_t *order_out,
-                                                 uint32_t *n_out)
+// ballot and ranks them with mbcnt; the waves of a block add up their counts in LDS
+// and the block reserves room in the output with a single atomic.
+constexpr int kCompactThreads = 1024;
+
+__global__ __launch_bounds__(kCompactThreads) void k_compact(const uint32_t *order_in,
+                                                             const uint32_t *n_in,
+                                                             const uint8_t *status,
+                                                             uint32_t *order_out,
+                                                             uint32_t *n_out)
 {
+    __shared__ uint32_t wcount[kCompactThreads / 64];
+    __shared__ uint32_t block_base;
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t n = *n_in;
     uint32_t id = 0;
@@ -51,14 +58,41 @@ __global__ __launch_bounds__(256) void k_compact(const uint32_t *order_in, const
     const uint64_t mask = __ballot(keep);
     const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-    uint32_t base = 0;
-    if (rank == 0 && keep)
-        base = atomicAdd(n_out, (uint32_t)__popcll(mask));
-    // the first surviving lane holds the base; broadcast it from that lane
-    const int src = mask ? __ffsll((unsigned long long)mask) - 1 : 0;
-    base = __shfl(base, src, 64);
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0)
+        wcount[wid] = (uint32_t)__popcll(mask);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t tot = 0;
+        for (int w = 0; w < kCompactThreads / 64; ++w) {
+            const uint32_t c = wcount[w];
+            wcount[w] = tot;
+            tot += c;
+        }
+        block_base = tot ? atomicAdd(n_out, tot) : 0u;
+    }
+    __syncthreads();
     if (keep)
-        order_out[base + rank] = id;
+        order_out[block_base + wcount[wid] + rank] = id;
+}
+
+// Runs of equal keys inside a wave (the order is nearly sorted already): each lane
+// learns the lane that starts its run and the run length, so one lane per run can
+// do the atomic for the whole run.
+__device__ inline void wave_runs(uint32_t key, bool valid, int &start, uint32_t &len)
+{
+    const int lane = threadIdx.x & 63;
+    const uint32_t prev = __shfl_up(key, 1, 64);
+    const bool prev_valid = __shfl_up(valid ? 1 : 0, 1, 64) != 0;
+    const bool is_start = valid && (lane == 0 || !prev_valid || prev != key);
+    // lanes that are not valid also end runs
+    const uint64_t starts = __ballot(is_start) | __ballot(!valid);
+    const uint64_t below = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+    const uint64_t at_or_below = starts & below;
+    start = at_or_below ? 63 - __clzll((long long)at_or_below) : lane;
+    const uint64_t above = starts & ~below;
+    const int next = above ? __ffsll((unsigned long long)above) - 1 : 64;
+    len = (uint32_t)(next - lane);  // meaningful on the start lane
 }
 
 __device__ inline int cell_of(const AxisDev &a, double x)
@@ -88,22 +122,28 @@ __global__ __launch_bounds__(256) void k_sort_keys(GridDev g, const double *x, c
                                                    uint32_t *keys, uint32_t *hist)
 {
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= *n_in)
-        return;
-    const uint32_t id = order[k];
+    const uint32_t n = *n_in;
     uint32_t key = 0xFFFFFFFFu;
-    if (status[id] == 0) {
-        const int i = cell_of(g.ax, x[id]);
-        const int j = cell_of(g.ay, y[id]);
-        const uint32_t ntx = (uint32_t)(g.ax.n - 2) / kTile + 1;
-        key = (uint32_t)(j / kTile) * ntx + (uint32_t)(i / kTile);
-        if (g.az.n) {
-            const int kk = cell_of(g.az, z[id]);
-            key = key * (uint32_t)(g.az.n - 1) + (uint32_t)kk;
+    if (k < n) {
+        const uint32_t id = order[k];
+        if (status[id] == 0) {
+            const int i = cell_of(g.ax, x[id]);
+            const int j = cell_of(g.ay, y[id]);
+            const uint32_t ntx = (uint32_t)(g.ax.n - 2) / kTile + 1;
+            key = (uint32_t)(j / kTile) * ntx + (uint32_t)(i / kTile);
+            if (g.az.n) {
+                const int kk = cell_of(g.az, z[id]);
+                key = key * (uint32_t)(g.az.n - 1) + (uint32_t)kk;
+            }
         }
-        atomicAdd(&hist[key], 1u);
+        keys[k] = key;
     }
-    keys[k] = key;
+    const bool valid = key != 0xFFFFFFFFu;
+    int start;
+    uint32_t len;
+    wave_runs(key, valid, start, len);
+    if (valid && start == (int)(threadIdx.x & 63))
+        atomicAdd(&hist[key], len);
 }
 
 constexpr int kScanThreads = 256;
@@ -194,13 +234,19 @@ __global__ __launch_bounds__(256) void k_sort_scatter(const uint32_t *order_in,
                                                       uint32_t *offsets, uint32_t *order_out)
 {
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= *n_in)
-        return;
-    const uint32_t key = keys[k];
-    if (key == 0xFFFFFFFFu)
-        return;
-    const uint32_t pos = atomicAdd(&offsets[key], 1u);
-    order_out[pos] = order_in[k];
+    const uint32_t n = *n_in;
+    const uint32_t key = k < n ? keys[k] : 0xFFFFFFFFu;
+    const bool valid = key != 0xFFFFFFFFu;
+    int start;
+    uint32_t len;
+    wave_runs(key, valid, start, len);
+    const int lane = threadIdx.x & 63;
+    uint32_t base = 0;
+    if (valid && start == lane)
+        base = atomicAdd(&offsets[key], len);
+    base = __shfl(base, start, 64);
+    if (valid)
+        order_out[base + (uint32_t)(lane - start)] = order_in[k];
 }
 
 // ---------------------------------------------------------------- snapshot conversion
@@ -330,8 +376,8 @@ hipError_t launch_compact(const uint32_t *order_in, const uint32_t *n_in, const 
     hipError_t e = launch_fill_u32(n_out, 0u, 1, s);
     if (e != hipSuccess || n_launch == 0)
         return e;
-    hipLaunchKernelGGL(k_compact, dim3((n_launch + 255) / 256), dim3(256), 0, s, order_in, n_in,
-                       status, order_out, n_out);
+    hipLaunchKernelGGL(k_compact, dim3((n_launch + kCompactThreads - 1) / kCompactThreads),
+                       dim3(kCompactThreads), 0, s, order_in, n_in, status, order_out, n_out);
     return hipGetLastError();
 }
 

@@ -270,9 +270,38 @@ def cfg2_global_3d(nx: int = 3600, ny: int = 1800, nz: int = 50, nt: int = 11,
     y0 = g.uniform(lat[0], lat[-1], n_particles)
     d0 = g.uniform(z[0], z[-1], n_particles)
     grid = Grid(lon=lon, lat=lat, depth=z, spherical=True)
+    meta = dict(base=(ua, va, ub, vb, C), decay=decay, wprof=wprof, omega=omega)
     return Workload(f"cfg2_3d_{nx}x{ny}x{nz}_{n_particles}", grid,
                     Fields(times=times, period=0.0, maker=maker),
-                    x0, y0, d0, dt=dt, nsteps=nsteps, outputdt=outputdt)
+                    x0, y0, d0, dt=dt, nsteps=nsteps, outputdt=outputdt, meta=meta)
+
+
+def cfg2_snapshot_torch(w: Workload, s: int, device="cuda", cache: Optional[dict] = None):
+    """Snapshot s of a cfg2 workload built directly in device memory with torch.
+    Same arithmetic as the numpy maker (scalar coefficients in numpy float64, then
+    separate float64 products and a sum, rounded to float32), so the values are
+    bit-identical."""
+    import torch
+    m = w.meta
+    if cache is None:
+        cache = {}
+    if "base" not in cache:
+        cache["base"] = [torch.from_numpy(a).to(device) for a in m["base"]]
+    ua, va, ub, vb, C = cache["base"]
+    z = w.grid.depth
+    t = w.fields.times[s]
+    omega = m["omega"]
+    nz, ny, nx = z.size, w.grid.ny, w.grid.nx
+    U = torch.empty((nz, ny, nx), dtype=torch.float32, device=device)
+    V = torch.empty_like(U)
+    W = torch.empty_like(U)
+    for k in range(nz):
+        c = float(m["decay"][k] * np.cos(omega * t + z[k] / 800.0))
+        sn = float(m["decay"][k] * np.sin(omega * t + z[k] / 800.0))
+        U[k] = (c * ua + sn * ub).to(torch.float32)
+        V[k] = (c * va + sn * vb).to(torch.float32)
+        W[k] = (float(m["wprof"][k] * np.cos(omega * t)) * C).to(torch.float32)
+    return U, V, W
 
 
 # --------------------------------------------------------------------------- cfg3
