@@ -53,6 +53,9 @@ def parse():
     p.add_argument("--cpu-sample-stride", type=int, default=100)
     p.add_argument("--config", default="cfg1", choices=["cfg1", "cfg2"])
     p.add_argument("--stencil-cache", type=int, default=1)
+    p.add_argument("--calibrate-copy", type=float, default=0.0,
+                   help="first copy this many GB device-to-device (a plain copy kernel of "
+                        "known size, to scale hardware byte counters)")
     p.add_argument("--error-stride", type=int, default=100,
                    help="cfg2: oracle error report on ids = 0 mod this (0 = skip)")
     return p.parse_args()
@@ -213,6 +216,16 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": a.gpus}))
         sys.exit(2)
+    if a.calibrate_copy > 0:
+        import torch
+        n = int(a.calibrate_copy * 1e9) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copy of {n * 4} bytes", file=sys.stderr, flush=True)
+        del src, dst
     if a.config == "cfg2":
         return main_cfg2(a)
     import torch

@@ -106,6 +106,10 @@ int fieldset_push_snapshot_f64(lp_fieldset *fs, double t, const double *U, const
 /* Same with float arrays already in device memory (no host copy). */
 int fieldset_push_snapshot_device(lp_fieldset *fs, double t, const float *dU, const float *dV,
                                   const float *dW, void *stream);
+/* Values held for the resident snapshot at time t, as float [max(nz,1)][ny][nx]
+ * arrays (bfloat16 and scaled float16 values are returned exactly, as floats);
+ * W may be NULL in 2D.  LP_ETIME if no resident snapshot has time t.  Syncs. */
+int fieldset_get_snapshot(lp_fieldset *fs, double t, float *U, float *V, float *W);
 /* Number of snapshots currently resident and their times (times may be NULL). */
 int fieldset_resident(const lp_fieldset *fs, int32_t *count, double *times);
 void fieldset_destroy(lp_fieldset *fs);
@@ -156,6 +160,31 @@ typedef struct {
     int64_t step;           /* steps taken since t0 */
 } lp_counts;
 
+/* Run many independent particle sets (each with its own field set: grid size,
+ * snapshots and particle count may all differ) through one persistent launch per
+ * output segment.  Same result per set as calling pset_execute on each with its
+ * own opts[r] (which must agree on stencil_cache); the field sets must all be 2D
+ * with one storage type, one mesh kind, and all steady or all time-varying.  The
+ * active particles of all sets are cut into chunks of `block` (64, 128, 256 or
+ * 512; 0 = 256) particles, handed out through per-XCD atomic work queues. */
+int pset_execute_batch(lp_pset **ps, int32_t nruns, double runtime, double dt, double outputdt,
+                       const lp_exec_opts *opts, int32_t block, void *stream);
+
+typedef struct {
+    int32_t block, stencil_cache, sort_every; /* chosen launch shape */
+    double ms;                                /* kernel time of the winning trial */
+} lp_tune;
+
+/* Autotuner for pset_execute_batch: times every combination of block size (128,
+ * 256, 512), stencil cache (on, off) and sorting (every segment, never) over
+ * trial_steps steps of dt from the current state, restores the state after each
+ * trial, and returns the fastest.  The choice is cached in the JSON file at
+ * cache_path (NULL = no cache) under a key made of the storage type, mesh, run
+ * count and the log2 of the mean grid size and of the particle count; a cached
+ * entry is returned without trials.  Synchronises. */
+int pset_autotune_batch(lp_pset **ps, int32_t nruns, double dt, int32_t trial_steps,
+                        const lp_exec_opts *opts, const char *cache_path, lp_tune *best);
+
 /* Counts (and, if status != NULL, the n status bytes in id order).  Syncs. */
 int pset_status(lp_pset *ps, lp_counts *c, uint8_t *status);
 /* Positions and cell indices (-1 outside the grid) in id order; any output
@@ -171,6 +200,16 @@ int pset_records(lp_pset *ps, int64_t *nrec, int64_t *nper, double *lon, double 
  * opts.profile = 1).  Synchronises. */
 int pset_timing(lp_pset *ps, double *kernel_ms, int64_t *launches);
 void pset_destroy(lp_pset *ps);
+
+/* The random numbers of the Brownian term (Sect. 4.2.7), computed on the device by
+ * the same code the advection kernels use: for each i < n, Philox4x32-10 (Salmon
+ * et al., SC'11) with key (run_id, seed) and counter (pid[i], step[i], 0, 0) gives
+ * words[4i..4i+3]; uniforms u1 = top 53 bits of (w0:w1) * 2^-53 + 2^-54 and u2 from
+ * (w2:w3); Box-Muller gives normals[2i] = r cos(2 pi u2), normals[2i+1] =
+ * r sin(2 pi u2), r = sqrt(-2 ln u1).  Host arrays; words or normals may be NULL.
+ * Synchronises. */
+int lp_philox_normals(uint32_t run_id, uint32_t seed, int64_t n, const uint32_t *pid,
+                      const uint32_t *step, uint32_t *words, double *normals);
 
 const char *lp_last_error(void);
 /* Library version string. */

@@ -4,7 +4,8 @@
 ImportError if it has not been built; nothing here computes on the CPU.
 """
 
-__all__ = ["FieldSet", "ParticleSet", "SEED"]
+__all__ = ["FieldSet", "ParticleSet", "SEED", "philox_normals", "execute_batch",
+           "autotune_batch"]
 
 
 def __getattr__(name):

@@ -22,9 +22,11 @@ LP_KERNEL_RK4 = 0
 # every function declared in include/lp.h
 EXPORTS = (
     "fieldset_create", "fieldset_push_snapshot", "fieldset_push_snapshot_f64",
-    "fieldset_push_snapshot_device", "fieldset_resident", "fieldset_destroy",
+    "fieldset_push_snapshot_device", "fieldset_get_snapshot", "fieldset_resident",
+    "fieldset_destroy", "lp_philox_normals",
     "pset_create", "pset_create_device", "pset_execute", "pset_status", "pset_get",
     "pset_records", "pset_timing", "pset_destroy", "lp_last_error", "lp_version",
+    "pset_execute_batch", "pset_autotune_batch",
 )
 
 
@@ -48,6 +50,11 @@ class lp_counts(C.Structure):
                 ("time", C.c_double), ("step", C.c_int64)]
 
 
+class lp_tune(C.Structure):
+    _fields_ = [("block", C.c_int32), ("stencil_cache", C.c_int32), ("sort_every", C.c_int32),
+                ("ms", C.c_double)]
+
+
 class LPError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"lp error {code}: {msg}")
@@ -63,6 +70,8 @@ def _declare(L):
         "fieldset_push_snapshot": ([P, C.c_double, P, P, P, P], I),
         "fieldset_push_snapshot_f64": ([P, C.c_double, P, P, P, P], I),
         "fieldset_push_snapshot_device": ([P, C.c_double, P, P, P, P], I),
+        "fieldset_get_snapshot": ([P, C.c_double, P, P, P], I),
+        "lp_philox_normals": ([C.c_uint32, C.c_uint32, C.c_int64, P, P, P, P], I),
         "fieldset_resident": ([P, C.POINTER(C.c_int32), P], I),
         "fieldset_destroy": ([P], None),
         "pset_create": ([P, C.c_int64, P, P, P, C.c_double, C.c_int64, pp], I),
@@ -72,6 +81,10 @@ def _declare(L):
         "pset_get": ([P, P, P, P, P, P, P], I),
         "pset_records": ([P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), P, P, P, P, P, P, P], I),
         "pset_timing": ([P, C.POINTER(C.c_double), C.POINTER(C.c_int64)], I),
+        "pset_execute_batch": ([C.POINTER(C.c_void_p), C.c_int32, C.c_double, C.c_double,
+                                C.c_double, C.POINTER(lp_exec_opts), C.c_int32, P], I),
+        "pset_autotune_batch": ([C.POINTER(C.c_void_p), C.c_int32, C.c_double, C.c_int32,
+                                 C.POINTER(lp_exec_opts), C.c_char_p, C.POINTER(lp_tune)], I),
         "pset_destroy": ([P], None),
         "lp_last_error": ([], C.c_char_p),
         "lp_version": ([], C.c_char_p),

@@ -102,6 +102,14 @@ class FieldSet:
 
     advancetime = push_snapshot
 
+    def get_snapshot(self, t: float):
+        """Values held on the device for the snapshot at time t (exact, as float32)."""
+        shape = (self.ny, self.nx) if self.nz == 0 else (self.nz, self.ny, self.nx)
+        U, V = np.empty(shape, np.float32), np.empty(shape, np.float32)
+        W = np.empty(shape, np.float32) if self.nz else None
+        L.check(L.lib.fieldset_get_snapshot(self._h, float(t), _ptr(U), _ptr(V), _ptr(W)))
+        return U, V, W
+
     def resident(self):
         n = C.c_int32()
         t = np.zeros(1024)
@@ -118,6 +126,18 @@ class FieldSet:
             self.close()
         except Exception:
             pass
+
+
+def philox_normals(run_id: int, seed: int, pid, step):
+    """Philox4x32-10 words and Box-Muller normals computed on the device."""
+    pid = np.ascontiguousarray(pid, np.uint32)
+    step = np.ascontiguousarray(step, np.uint32)
+    n = pid.size
+    words = np.empty((n, 4), np.uint32)
+    normals = np.empty((n, 2), np.float64)
+    L.check(L.lib.lp_philox_normals(int(run_id), int(seed) & 0xFFFFFFFF, n, _ptr(pid),
+                                    _ptr(step), _ptr(words), _ptr(normals)))
+    return words, normals
 
 
 class ParticleSet:
@@ -140,13 +160,20 @@ class ParticleSet:
         self._h = h
         self.is3d = fieldset.nz > 0
 
+    @staticmethod
+    def opts(recovery: str = "delete", Kh: float = 0.0, run_id: int = 0, seed: int = SEED,
+             output_stride: int = 0, sort_every: int = 1, profile: bool = False,
+             stencil_cache: bool = True):
+        return L.lp_exec_opts(L.LP_KERNEL_RK4, _RECOVERY[recovery], float(Kh), int(run_id),
+                              int(seed) & 0xFFFFFFFF, int(output_stride), int(sort_every),
+                              int(bool(profile)), int(bool(stencil_cache)))
+
     def execute(self, runtime: float, dt: float, outputdt: float = 0.0,
                 recovery: str = "delete", Kh: float = 0.0, run_id: int = 0, seed: int = SEED,
                 output_stride: int = 0, sort_every: int = 1, profile: bool = False,
                 stencil_cache: bool = True, stream=None):
-        o = L.lp_exec_opts(L.LP_KERNEL_RK4, _RECOVERY[recovery], float(Kh), int(run_id),
-                           int(seed) & 0xFFFFFFFF, int(output_stride), int(sort_every),
-                           int(bool(profile)), int(bool(stencil_cache)))
+        o = self.opts(recovery, Kh, run_id, seed, output_stride, sort_every, profile,
+                      stencil_cache)
         L.check(L.lib.pset_execute(self._h, float(runtime), float(dt), float(outputdt),
                                    C.byref(o), _stream(stream)))
 
@@ -195,8 +222,36 @@ class ParticleSet:
             L.lib.pset_destroy(self._h)
             self._h = None
 
+    @property
+    def handle(self):
+        return self._h
+
     def __del__(self):
         try:
             self.close()
         except Exception:
             pass
+
+
+def execute_batch(psets, runtime: float, dt: float, outputdt: float = 0.0, opts=None,
+                  block: int = 256, stream=None):
+    """One persistent launch per output segment for many independent particle sets;
+    ``opts`` is a list of ParticleSet.opts(...) (one per set)."""
+    n = len(psets)
+    hs = (C.c_void_p * n)(*[p.handle for p in psets])
+    oa = (L.lp_exec_opts * n)(*(opts if opts is not None else [ParticleSet.opts()] * n))
+    L.check(L.lib.pset_execute_batch(hs, n, float(runtime), float(dt), float(outputdt), oa,
+                                     int(block), _stream(stream)))
+
+
+def autotune_batch(psets, dt: float, trial_steps: int, opts=None, cache_path=None):
+    """Time the batched launch shapes on the current state (restored afterwards) and
+    return the fastest as a dict; cached in the JSON file ``cache_path``."""
+    n = len(psets)
+    hs = (C.c_void_p * n)(*[p.handle for p in psets])
+    oa = (L.lp_exec_opts * n)(*(opts if opts is not None else [ParticleSet.opts()] * n))
+    t = L.lp_tune()
+    L.check(L.lib.pset_autotune_batch(hs, n, float(dt), int(trial_steps), oa,
+                                      None if cache_path is None else str(cache_path).encode(),
+                                      C.byref(t)))
+    return dict(block=t.block, stencil_cache=t.stencil_cache, sort_every=t.sort_every, ms=t.ms)

@@ -471,13 +471,12 @@ __device__ inline bool stage2(const AdvectParams &P, Cell2<typename Real<ST>::T>
     return true;
 }
 
+// One particle (position k of the processing order) for all steps of the launch;
+// returns the number of steps it started active.
 template <int ST, bool STEADY, bool SPH>
-__global__ __launch_bounds__(kBlock) void k_advect2d(AdvectParams P)
+__device__ inline long long advect_lane_2d(const AdvectParams &P, uint32_t k, uint32_t nact)
 {
     using R = typename Real<ST>::T;
-    const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
-    const uint32_t k = blk * kBlock + threadIdx.x;
-    const uint32_t nact = *P.n_active;
     long long steps = 0;
     if (k < nact) {
         const uint32_t id = P.order[k];
@@ -562,10 +561,75 @@ __global__ __launch_bounds__(kBlock) void k_advect2d(AdvectParams P)
                 P.status[id] = st;
         }
     }
+    return steps;
+}
+
+template <int ST, bool STEADY, bool SPH>
+__global__ __launch_bounds__(kBlock) void k_advect2d(AdvectParams P)
+{
+    const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const uint32_t k = blk * kBlock + threadIdx.x;
+    long long steps = advect_lane_2d<ST, STEADY, SPH>(P, k, *P.n_active);
     for (int off = 32; off > 0; off >>= 1)
         steps += __shfl_xor(steps, off, 64);
     if ((threadIdx.x & 63) == 0 && steps)
         atomicAdd(P.psteps, (unsigned long long)steps);
+}
+
+// Persistent batched launch over many independent runs (each with its own grid,
+// snapshots and particles).  The active particles of every run are cut into
+// chunks of blockDim particles; the chunk items are split into 8 contiguous
+// ranges, one per XCD, each with its own atomic counter.  A block takes items from
+// the range of the XCD it runs on and, when that is exhausted, from the others;
+// every block leaves once all 8 ranges are exhausted, so the grid always drains.
+template <int ST, bool STEADY, bool SPH>
+__global__ __launch_bounds__(512) void k_advect2d_batch(const AdvectParams *runs,
+                                                        const uint32_t *cstart, int nruns,
+                                                        uint32_t total, uint32_t *queues)
+{
+    __shared__ uint32_t item_s;
+    const uint32_t home = blockIdx.x & 7u;
+    uint32_t q = 0;  // queues tried so far
+    for (;;) {
+        if (threadIdx.x == 0) {
+            uint32_t it = 0xFFFFFFFFu;
+            while (q < 8) {
+                const uint32_t x = (home + q) & 7u;
+                const uint32_t lo = (uint32_t)(((uint64_t)total * x) >> 3);
+                const uint32_t hi = (uint32_t)(((uint64_t)total * (x + 1)) >> 3);
+                if (lo < hi) {
+                    const uint32_t t = atomicAdd(&queues[x], 1u);
+                    if (lo + t < hi) {
+                        it = lo + t;
+                        break;
+                    }
+                }
+                ++q;
+            }
+            item_s = it;
+        }
+        __syncthreads();
+        const uint32_t it = __builtin_amdgcn_readfirstlane(item_s);
+        __syncthreads();
+        if (it == 0xFFFFFFFFu)
+            break;
+        int lo = 0, hi = nruns - 1;  // run r: cstart[r] <= it < cstart[r + 1]
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (cstart[mid] <= it)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const int r = __builtin_amdgcn_readfirstlane(lo);
+        const AdvectParams &P = runs[r];
+        const uint32_t k = (it - cstart[r]) * blockDim.x + threadIdx.x;
+        long long steps = advect_lane_2d<ST, STEADY, SPH>(P, k, *P.n_active);
+        for (int off = 32; off > 0; off >>= 1)
+            steps += __shfl_xor(steps, off, 64);
+        if ((threadIdx.x & 63) == 0 && steps)
+            atomicAdd(P.psteps, (unsigned long long)steps);
+    }
 }
 
 // ---------------------------------------------------------------- 3D with a stencil cache
@@ -821,6 +885,48 @@ __global__ __launch_bounds__(kBlock) void k_advect3d(AdvectParams P)
         atomicAdd(P.psteps, (unsigned long long)steps);
 }
 
+__global__ void k_philox_normals(uint32_t run_id, uint32_t seed, int64_t n, const uint32_t *pid,
+                                 const uint32_t *step, uint32_t *words, double *normals)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    uint32_t w[4] = {pid[i], step[i], 0u, 0u};
+    philox4x32_10(w, run_id, seed);
+    if (words) {
+        words[4 * i] = w[0];
+        words[4 * i + 1] = w[1];
+        words[4 * i + 2] = w[2];
+        words[4 * i + 3] = w[3];
+    }
+    if (normals) {
+        const double u1 = unit53(w[0], w[1]), u2 = unit53(w[2], w[3]);
+        const double r = sqrt(-2.0 * log(u1));
+        double sn, cs;
+        sincos((2.0 * 3.141592653589793) * u2, &sn, &cs);
+        normals[2 * i] = r * cs;
+        normals[2 * i + 1] = r * sn;
+    }
+}
+
+template <int ST, bool IS3D>
+__global__ void k_slot_values(const char *slot, const float *scales, size_t plane, int nzl,
+                              float *U, float *V, float *W)
+{
+    using R = typename Real<ST>::T;
+    const size_t total = plane * (size_t)nzl;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const float *sc = ST == kF16S ? scales + (i / plane) * 3 : nullptr;
+        R v[3];
+        load_node<ST, IS3D>(slot, i, sc, v);
+        U[i] = (float)v[0];
+        V[i] = (float)v[1];
+        if (W)
+            W[i] = (float)v[2];
+    }
+}
+
 __global__ void k_lat_tables(const double *lat, int ny, double *cl, double *sl)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -923,12 +1029,88 @@ hipError_t launch_advect(int store, bool is3d, const AdvectParams &p, uint32_t n
     return hipErrorInvalidValue;
 }
 
+hipError_t launch_philox_normals(uint32_t run_id, uint32_t seed, int64_t n, const uint32_t *pid,
+                                 const uint32_t *step, uint32_t *words, double *normals,
+                                 hipStream_t s)
+{
+    if (n <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_philox_normals, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s,
+                       run_id, seed, n, pid, step, words, normals);
+    return hipGetLastError();
+}
+
+hipError_t launch_slot_values(int store, bool is3d, const void *slot, const float *scales,
+                              size_t plane, int nzl, float *U, float *V, float *W, hipStream_t s)
+{
+    const size_t total = plane * (size_t)nzl;
+    size_t nb = (total + 255) / 256;
+    const dim3 g((uint32_t)(nb > 32768 ? 32768 : nb)), b(256);
+    const char *sl = static_cast<const char *>(slot);
+#define LP_SV(ST, D3) hipLaunchKernelGGL((k_slot_values<ST, D3>), g, b, 0, s, sl, scales, plane, nzl, U, V, W)
+    switch (store) {
+    case kF64: if (is3d) LP_SV(kF64, true); else LP_SV(kF64, false); break;
+    case kF32: if (is3d) LP_SV(kF32, true); else LP_SV(kF32, false); break;
+    case kBF16: if (is3d) LP_SV(kBF16, true); else LP_SV(kBF16, false); break;
+    case kF16S: if (is3d) LP_SV(kF16S, true); else LP_SV(kF16S, false); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef LP_SV
+    return hipGetLastError();
+}
+
 hipError_t launch_lat_tables(const double *lat, int ny, double *coslat, double *sinlat,
                               hipStream_t s)
 {
     hipLaunchKernelGGL(k_lat_tables, dim3((ny + 255) / 256), dim3(256), 0, s, lat, ny, coslat,
                        sinlat);
     return hipGetLastError();
+}
+
+template <int ST, bool STEADY, bool SPH>
+hipError_t batch3(const AdvectParams *runs, const uint32_t *cstart, int nruns, uint32_t total,
+                  uint32_t *queues, int block, hipStream_t s, int *grid_out)
+{
+    auto kern = k_advect2d_batch<ST, STEADY, SPH>;
+    int per_cu = 0, cus = 0, dev = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, 0);
+    if (e != hipSuccess)
+        return e;
+    if ((e = hipGetDevice(&dev)) != hipSuccess ||
+        (e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+        return e;
+    int grid = per_cu * cus;
+    if (grid < 1)
+        grid = 1;
+    if ((uint32_t)grid > total)
+        grid = (int)(total ? total : 1);
+    if (grid_out)
+        *grid_out = grid;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, s, runs, cstart, nruns, total, queues);
+    return hipGetLastError();
+}
+
+hipError_t launch_advect_batch(int store, bool steady, bool spherical, const AdvectParams *runs,
+                               const uint32_t *cstart, int nruns, uint32_t total,
+                               uint32_t *queues, int block, hipStream_t s, int *grid_out)
+{
+    hipError_t e = launch_fill_u32(queues, 0u, 8, s);
+    if (e != hipSuccess || total == 0)
+        return e;
+#define LP_B(ST)                                                                                \
+    if (spherical)                                                                              \
+        return steady ? batch3<ST, true, true>(runs, cstart, nruns, total, queues, block, s, grid_out)  \
+                      : batch3<ST, false, true>(runs, cstart, nruns, total, queues, block, s, grid_out); \
+    return steady ? batch3<ST, true, false>(runs, cstart, nruns, total, queues, block, s, grid_out)     \
+                  : batch3<ST, false, false>(runs, cstart, nruns, total, queues, block, s, grid_out);
+    switch (store) {
+    case kF64: { LP_B(kF64) }
+    case kF32: { LP_B(kF32) }
+    case kBF16: { LP_B(kBF16) }
+    case kF16S: { LP_B(kF16S) }
+    }
+#undef LP_B
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_record(const RecordParams &p, hipStream_t s)

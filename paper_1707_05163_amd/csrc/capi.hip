@@ -487,6 +487,61 @@ int bracket(const lp_fieldset *fs, const std::vector<Resident> &r, double t, Tim
 
 }  // namespace
 
+extern "C" int fieldset_get_snapshot(lp_fieldset *fs, double t, float *U, float *V, float *W)
+{
+    if (!fs || !U || !V)
+        return fail(LP_EINVAL, "null argument");
+    int slot = -1;
+    for (int s = 0; s < fs->capacity; ++s)
+        if (fs->slot_seq[s] >= 0 && fs->slot_t[s] == t)
+            slot = s;
+    if (slot < 0)
+        return fail(LP_ETIME, "no resident snapshot at time %.17g", t);
+    const size_t nvals = fs->plane() * fs->nzl;
+    float *d = nullptr;
+    int rc = dalloc(&d, nvals * 3);
+    if (rc)
+        return rc;
+    HIPCHECK(hipStreamSynchronize(fs->up));
+    hipError_t e = lp::launch_slot_values(fs->dtype, fs->is3d, fs->dslots + (size_t)slot * fs->slot_bytes,
+                                          fs->dscales + (size_t)slot * fs->nzl * 3, fs->plane(),
+                                          fs->nzl, d, d + nvals, fs->is3d ? d + 2 * nvals : nullptr,
+                                          nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy(U, d, nvals * 4, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(V, d + nvals, nvals * 4, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && W && fs->is3d) e = hipMemcpy(W, d + 2 * nvals, nvals * 4, hipMemcpyDeviceToHost);
+    dfree(d);
+    HIPCHECK(e);
+    return LP_OK;
+}
+
+extern "C" int lp_philox_normals(uint32_t run_id, uint32_t seed, int64_t n, const uint32_t *pid,
+                                 const uint32_t *step, uint32_t *words, double *normals)
+{
+    if (n < 0 || (n > 0 && (!pid || !step)))
+        return fail(LP_EINVAL, "bad arguments");
+    if (n == 0)
+        return LP_OK;
+    uint32_t *dp = nullptr, *dsn = nullptr, *dw = nullptr;
+    double *dn = nullptr;
+    int rc;
+    if ((rc = dalloc(&dp, (size_t)n)) || (rc = dalloc(&dsn, (size_t)n)) ||
+        (rc = dalloc(&dw, 4 * (size_t)n)) || (rc = dalloc(&dn, 2 * (size_t)n))) {
+        dfree(dp); dfree(dsn); dfree(dw); dfree(dn);
+        return rc;
+    }
+    hipError_t e = hipMemcpy(dp, pid, (size_t)n * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dsn, step, (size_t)n * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = lp::launch_philox_normals(run_id, seed, n, dp, dsn, dw, dn, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e == hipSuccess && words) e = hipMemcpy(words, dw, (size_t)n * 16, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && normals) e = hipMemcpy(normals, dn, (size_t)n * 16, hipMemcpyDeviceToHost);
+    dfree(dp); dfree(dsn); dfree(dw); dfree(dn);
+    HIPCHECK(e);
+    return LP_OK;
+}
+
 extern "C" int fieldset_resident(const lp_fieldset *fs, int32_t *count, double *times)
 {
     if (!fs || !count)
@@ -683,13 +738,27 @@ int take_record(lp_pset *ps, hipStream_t s)
 
 }  // namespace
 
-extern "C" int pset_execute(lp_pset *ps, double runtime, double dt, double outputdt,
-                            const lp_exec_opts *o, void *stream_)
+namespace {
+
+// One execute call split into its output segments.
+struct ExecPlan {
+    int64_t nsteps = 0, per = 0;
+    std::vector<std::pair<int64_t, int64_t>> segs;  // (first step, steps)
+    std::vector<char> used;                         // snapshot slots read
+    lp::AdvectParams P{};                           // per-call part of the kernel arguments
+    size_t toff = 0;                                // time-table offset of the next segment
+    bool records = false;
+};
+
+// Validate, rebase the time origin, build and upload the stage-time table, order
+// the stream after the snapshot uploads and take the first record.  Nothing is
+// launched if a stage time is not covered (LP_ETIME) or an argument is bad.
+int exec_prepare(lp_pset *ps, double runtime, double dt, double outputdt, const lp_exec_opts *o,
+                 hipStream_t stream, bool allow_records, ExecPlan &plan)
 {
     if (!ps || !o)
         return fail(LP_EINVAL, "null argument");
     lp_fieldset *fs = ps->fs;
-    hipStream_t stream = (hipStream_t)stream_;
     if (o->kernel != LP_KERNEL_RK4)
         return fail(LP_EINVAL, "unknown kernel %d", o->kernel);
     if (o->recovery != LP_DELETE && o->recovery != LP_FREEZE)
@@ -700,8 +769,7 @@ extern "C" int pset_execute(lp_pset *ps, double runtime, double dt, double outpu
         return fail(LP_EINVAL, "runtime and outputdt must be >= 0");
     if (!(o->Kh >= 0.0) || o->output_stride < 0 || o->sort_every < 0)
         return fail(LP_EINVAL, "bad options");
-    const double fsteps = runtime / dt;
-    const int64_t nsteps = (int64_t)std::llround(fsteps);
+    const int64_t nsteps = (int64_t)std::llround(runtime / dt);
     if (std::fabs((double)nsteps * dt - runtime) > 1e-9 * std::max(runtime, dt))
         return fail(LP_EINVAL, "dt %g does not divide runtime %g", dt, runtime);
     int64_t per = nsteps;
@@ -712,7 +780,7 @@ extern "C" int pset_execute(lp_pset *ps, double runtime, double dt, double outpu
     }
     if (nsteps > 0x3FFFFFFF || per > 0x3FFFFFFF)
         return fail(LP_EINVAL, "too many steps in one call");
-    if (o->output_stride > 0) {
+    if (allow_records && o->output_stride > 0) {
         const int64_t nper = (ps->n + o->output_stride - 1) / o->output_stride;
         if (ps->stride && ps->stride != o->output_stride)
             return fail(LP_EINVAL, "output_stride changed between calls (%lld then %d)",
@@ -720,19 +788,19 @@ extern "C" int pset_execute(lp_pset *ps, double runtime, double dt, double outpu
         ps->stride = o->output_stride;
         ps->nper = nper;
     }
+    plan = ExecPlan();
+    plan.nsteps = nsteps;
+    plan.per = per;
+    plan.records = allow_records && ps->stride > 0;
     if (nsteps == 0)
         return LP_OK;
-    // time origin: t = t0 + step*dt for the current dt
-    if (ps->dt != 0.0 && dt != ps->dt)
-        ps->t0 = (ps->t0 + (double)ps->step * ps->dt) - (double)ps->step * dt;
-    const double t0 = ps->t0;
-
-    // stage-time table for every segment: t_n, t_n + dt/2, t_n + dt, ...
-    std::vector<std::pair<int64_t, int64_t>> segs;  // (first step, steps)
+    double t0 = ps->t0;
+    if (ps->dt != 0.0 && dt != ps->dt)  // keep t = t0 + step * dt at the current step
+        t0 = (ps->t0 + (double)ps->step * ps->dt) - (double)ps->step * dt;
     for (int64_t a = 0; a < nsteps; a += per)
-        segs.emplace_back(ps->step + a, std::min(per, nsteps - a));
+        plan.segs.emplace_back(ps->step + a, std::min(per, nsteps - a));
     size_t ntab = 0;
-    for (auto &sg : segs)
+    for (auto &sg : plan.segs)
         ntab += 2 * (size_t)sg.second + 1;
     if (ps->tab_pending) {
         HIPCHECK(hipEventSynchronize(ps->tab_ev));
@@ -753,43 +821,42 @@ extern "C" int pset_execute(lp_pset *ps, double runtime, double dt, double outpu
         ps->tab_cap = ntab;
     }
     const auto res = resident(fs);
-    std::vector<char> used(fs->capacity, 0);
+    plan.used.assign(fs->capacity, 0);
     {
         size_t q = 0;
-        for (auto &sg : segs) {
+        for (auto &sg : plan.segs) {
             for (int64_t h = 0; h <= 2 * sg.second; ++h) {
                 const int64_t nn = sg.first + h / 2;
                 const double t = (h & 1) ? t0 + ((double)nn + 0.5) * dt : t0 + (double)nn * dt;
                 int rc = bracket(fs, res, t, ps->htab[q]);
                 if (rc)
                     return rc;
-                used[ps->htab[q].sa] = used[ps->htab[q].sb] = 1;
+                plan.used[ps->htab[q].sa] = plan.used[ps->htab[q].sb] = 1;
                 ++q;
             }
         }
     }
+    ps->t0 = t0;
     HIPCHECK(hipMemcpyAsync(ps->dtab, ps->htab, ntab * sizeof(TimeEntry), hipMemcpyHostToDevice,
                             stream));
     HIPCHECK(hipEventRecord(ps->tab_ev, stream));
     ps->tab_pending = true;
     for (int s = 0; s < fs->capacity; ++s)
-        if (used[s])
+        if (plan.used[s])
             HIPCHECK(hipStreamWaitEvent(stream, fs->ready[s], 0));
-    // learn the active count of the previous call if it has arrived
     if (ps->count_pending && hipEventQuery(ps->count_ev) == hipSuccess) {
         ps->n_launch = std::min<uint32_t>(ps->n_launch, *ps->hcount);
         ps->count_pending = false;
     }
     ps->dt = dt;
-    if (ps->stride > 0) {
-        int rc = grow_records(ps, ps->nrec + (int64_t)segs.size() + 1);
+    if (plan.records) {
+        int rc = grow_records(ps, ps->nrec + (int64_t)plan.segs.size() + 1);
         if (rc)
             return rc;
         if (ps->nrec == 0 && (rc = take_record(ps, stream)))
             return rc;
     }
-
-    lp::AdvectParams P{};
+    lp::AdvectParams &P = plan.P;
     P.g = fs->g;
     P.f.slots = fs->dslots;
     P.f.slot_bytes = fs->slot_bytes;
@@ -807,53 +874,445 @@ extern "C" int pset_execute(lp_pset *ps, double runtime, double dt, double outpu
     P.z = ps->dz;
     P.status = ps->dst;
     P.psteps = ps->dpsteps;
-    size_t toff = 0;
-    for (auto &sg : segs) {
-        if (o->sort_every > 0 && ps->segs_since_sort >= o->sort_every) {
-            HIPCHECK(lp::launch_sort(fs->g, ps->dx, ps->dy, ps->dz, ps->dst, ps->dorder[ps->cur],
-                                     ps->dcount + ps->cur, ps->n_launch, ps->dkeys, ps->dhist,
-                                     ps->nbins, ps->dblk, ps->dorder[1 - ps->cur],
-                                     ps->dcount + (1 - ps->cur), stream));
-            ps->cur = 1 - ps->cur;
-            ps->segs_since_sort = 0;
-        }
-        P.tab = ps->dtab + toff;
-        P.step0 = sg.first;
-        P.nsteps = (int32_t)sg.second;
-        P.order = ps->dorder[ps->cur];
-        P.n_active = ps->dcount + ps->cur;
+    return LP_OK;
+}
+
+// Sort if due and fill the per-segment kernel arguments of segment k.
+int exec_segment_pre(lp_pset *ps, const lp_exec_opts *o, ExecPlan &plan, size_t k,
+                     hipStream_t stream)
+{
+    lp_fieldset *fs = ps->fs;
+    if (o->sort_every > 0 && ps->segs_since_sort >= o->sort_every) {
+        HIPCHECK(lp::launch_sort(fs->g, ps->dx, ps->dy, ps->dz, ps->dst, ps->dorder[ps->cur],
+                                 ps->dcount + ps->cur, ps->n_launch, ps->dkeys, ps->dhist,
+                                 ps->nbins, ps->dblk, ps->dorder[1 - ps->cur],
+                                 ps->dcount + (1 - ps->cur), stream));
+        ps->cur = 1 - ps->cur;
+        ps->segs_since_sort = 0;
+    }
+    const auto &sg = plan.segs[k];
+    plan.P.tab = ps->dtab + plan.toff;
+    plan.P.step0 = sg.first;
+    plan.P.nsteps = (int32_t)sg.second;
+    plan.P.order = ps->dorder[ps->cur];
+    plan.P.n_active = ps->dcount + ps->cur;
+    return LP_OK;
+}
+
+// Compact the active list and take the output record after segment k.
+int exec_segment_post(lp_pset *ps, ExecPlan &plan, size_t k, hipStream_t stream)
+{
+    HIPCHECK(lp::launch_compact(ps->dorder[ps->cur], ps->dcount + ps->cur, ps->dst,
+                                ps->dorder[1 - ps->cur], ps->dcount + (1 - ps->cur),
+                                ps->n_launch, stream));
+    ps->cur = 1 - ps->cur;
+    ps->segs_since_sort++;
+    if (plan.records) {
+        int rc = take_record(ps, stream);
+        if (rc)
+            return rc;
+    }
+    plan.toff += 2 * (size_t)plan.segs[k].second + 1;
+    return LP_OK;
+}
+
+int exec_finish(lp_pset *ps, ExecPlan &plan, hipStream_t stream)
+{
+    lp_fieldset *fs = ps->fs;
+    for (int s = 0; s < fs->capacity; ++s)
+        if (plan.used[s])
+            HIPCHECK(hipEventRecord(fs->release[s], stream));
+    HIPCHECK(hipMemcpyAsync(ps->hcount, ps->dcount + ps->cur, sizeof(uint32_t),
+                            hipMemcpyDeviceToHost, stream));
+    HIPCHECK(hipEventRecord(ps->count_ev, stream));
+    ps->count_pending = true;
+    ps->step += plan.nsteps;
+    ps->last_stream = stream;
+    return LP_OK;
+}
+
+}  // namespace
+
+extern "C" int pset_execute(lp_pset *ps, double runtime, double dt, double outputdt,
+                            const lp_exec_opts *o, void *stream_)
+{
+    hipStream_t stream = (hipStream_t)stream_;
+    ExecPlan plan;
+    int rc = exec_prepare(ps, runtime, dt, outputdt, o, stream, true, plan);
+    if (rc || plan.nsteps == 0)
+        return rc;
+    for (size_t k = 0; k < plan.segs.size(); ++k) {
+        if ((rc = exec_segment_pre(ps, o, plan, k, stream)))
+            return rc;
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (o->profile) {
             HIPCHECK(hipEventCreate(&e0));
             HIPCHECK(hipEventCreate(&e1));
             HIPCHECK(hipEventRecord(e0, stream));
         }
-        HIPCHECK(lp::launch_advect(fs->dtype, fs->is3d, P, ps->n_launch, stream));
+        HIPCHECK(lp::launch_advect(ps->fs->dtype, ps->fs->is3d, plan.P, ps->n_launch, stream));
         if (o->profile) {
             HIPCHECK(hipEventRecord(e1, stream));
             ps->prof.emplace_back(e0, e1);
         }
-        HIPCHECK(lp::launch_compact(ps->dorder[ps->cur], ps->dcount + ps->cur, ps->dst,
-                                    ps->dorder[1 - ps->cur], ps->dcount + (1 - ps->cur),
-                                    ps->n_launch, stream));
-        ps->cur = 1 - ps->cur;
-        ps->segs_since_sort++;
-        if (ps->stride > 0) {
-            int rc = take_record(ps, stream);
-            if (rc)
-                return rc;
-        }
-        toff += 2 * (size_t)sg.second + 1;
+        if ((rc = exec_segment_post(ps, plan, k, stream)))
+            return rc;
     }
-    for (int s = 0; s < fs->capacity; ++s)
-        if (used[s])
-            HIPCHECK(hipEventRecord(fs->release[s], stream));
-    HIPCHECK(hipMemcpyAsync(ps->hcount, ps->dcount + ps->cur, sizeof(uint32_t),
-                            hipMemcpyDeviceToHost, stream));
-    HIPCHECK(hipEventRecord(ps->count_ev, stream));
-    ps->count_pending = true;
-    ps->step += nsteps;
-    ps->last_stream = stream;
+    return exec_finish(ps, plan, stream);
+}
+
+namespace {
+
+// Device descriptors of a batched launch, reused from call to call once the
+// previous launch that read them has completed.
+struct BatchScratch {
+    lp::AdvectParams *druns = nullptr, *hruns = nullptr;
+    uint32_t *dcstart = nullptr, *hcstart = nullptr, *dqueues = nullptr;
+    size_t cap_runs = 0;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+};
+thread_local BatchScratch g_batch;
+
+int batch_reserve(size_t nruns)
+{
+    BatchScratch &b = g_batch;
+    if (b.pending) {
+        HIPCHECK(hipEventSynchronize(b.done));
+        b.pending = false;
+    }
+    if (!b.done)
+        HIPCHECK(hipEventCreateWithFlags(&b.done, hipEventDisableTiming));
+    if (!b.dqueues) {
+        int rc = dalloc(&b.dqueues, 8);
+        if (rc)
+            return rc;
+    }
+    if (nruns <= b.cap_runs)
+        return LP_OK;
+    dfree(b.druns);
+    dfree(b.dcstart);
+    if (b.hruns) (void)hipHostFree(b.hruns);
+    if (b.hcstart) (void)hipHostFree(b.hcstart);
+    b.hruns = nullptr;
+    b.hcstart = nullptr;
+    b.cap_runs = 0;
+    int rc;
+    if ((rc = dalloc(&b.druns, nruns)) || (rc = dalloc(&b.dcstart, nruns + 1)))
+        return rc;
+    if (hipHostMalloc((void **)&b.hruns, nruns * sizeof(lp::AdvectParams), hipHostMallocDefault) !=
+            hipSuccess ||
+        hipHostMalloc((void **)&b.hcstart, (nruns + 1) * sizeof(uint32_t), hipHostMallocDefault) !=
+            hipSuccess)
+        return fail(LP_ENOMEM, "pinned allocation of batch descriptors failed");
+    b.cap_runs = nruns;
+    return LP_OK;
+}
+
+int execute_batch(lp_pset **ps, int32_t nruns, double runtime, double dt, double outputdt,
+                  const lp_exec_opts *opts, hipStream_t stream, int block, bool allow_records,
+                  double *kernel_ms)
+{
+    if (!ps || !opts || nruns < 1)
+        return fail(LP_EINVAL, "null argument or no runs");
+    if (block != 64 && block != 128 && block != 256 && block != 512)
+        return fail(LP_EINVAL, "batch block size must be 64, 128, 256 or 512");
+    const lp_fieldset *f0 = ps[0] ? ps[0]->fs : nullptr;
+    if (!f0)
+        return fail(LP_EINVAL, "null particle set");
+    for (int r = 0; r < nruns; ++r) {
+        if (!ps[r])
+            return fail(LP_EINVAL, "null particle set %d", r);
+        const lp_fieldset *f = ps[r]->fs;
+        if (f->is3d || f->dtype != f0->dtype || f->g.spherical != f0->g.spherical ||
+            (f->npushed == 1) != (f0->npushed == 1))
+            return fail(LP_EINVAL, "batched runs must be 2D with one storage type, one mesh kind "
+                                   "and all steady or all time-varying (run %d differs)", r);
+        if (opts[r].stencil_cache != opts[0].stencil_cache)
+            return fail(LP_EINVAL, "batched runs share the stencil_cache setting");
+        for (int q = 0; q < r; ++q)
+            if (ps[q] == ps[r])
+                return fail(LP_EINVAL, "particle set %d appears twice", r);
+    }
+    std::vector<ExecPlan> plans(nruns);
+    for (int r = 0; r < nruns; ++r) {
+        int rc = exec_prepare(ps[r], runtime, dt, outputdt, &opts[r], stream, allow_records,
+                              plans[r]);
+        if (rc)
+            return rc;
+    }
+    if (plans[0].nsteps == 0)
+        return LP_OK;
+    const size_t nseg = plans[0].segs.size();
+    for (size_t k = 0; k < nseg; ++k) {
+        int rc = batch_reserve((size_t)nruns);
+        if (rc)
+            return rc;
+        BatchScratch &b = g_batch;
+        uint32_t total = 0;
+        for (int r = 0; r < nruns; ++r) {
+            if ((rc = exec_segment_pre(ps[r], &opts[r], plans[r], k, stream)))
+                return rc;
+            b.hruns[r] = plans[r].P;
+            b.hcstart[r] = total;
+            total += (ps[r]->n_launch + block - 1) / block;
+        }
+        b.hcstart[nruns] = total;
+        HIPCHECK(hipMemcpyAsync(b.druns, b.hruns, nruns * sizeof(lp::AdvectParams),
+                                hipMemcpyHostToDevice, stream));
+        HIPCHECK(hipMemcpyAsync(b.dcstart, b.hcstart, (nruns + 1) * sizeof(uint32_t),
+                                hipMemcpyHostToDevice, stream));
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        const bool prof = opts[0].profile || kernel_ms;
+        if (prof) {
+            HIPCHECK(hipEventCreate(&e0));
+            HIPCHECK(hipEventCreate(&e1));
+            HIPCHECK(hipEventRecord(e0, stream));
+        }
+        HIPCHECK(lp::launch_advect_batch(f0->dtype, f0->npushed == 1, f0->g.spherical != 0,
+                                         b.druns, b.dcstart, nruns, total, b.dqueues, block,
+                                         stream, nullptr));
+        if (prof) {
+            HIPCHECK(hipEventRecord(e1, stream));
+            if (kernel_ms) {
+                HIPCHECK(hipEventSynchronize(e1));
+                float ms = 0.f;
+                HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+                *kernel_ms += ms;
+                (void)hipEventDestroy(e0);
+                (void)hipEventDestroy(e1);
+            } else {
+                ps[0]->prof.emplace_back(e0, e1);
+            }
+        }
+        HIPCHECK(hipEventRecord(b.done, stream));
+        b.pending = true;
+        for (int r = 0; r < nruns; ++r)
+            if ((rc = exec_segment_post(ps[r], plans[r], k, stream)))
+                return rc;
+    }
+    for (int r = 0; r < nruns; ++r) {
+        int rc = exec_finish(ps[r], plans[r], stream);
+        if (rc)
+            return rc;
+    }
+    return LP_OK;
+}
+
+}  // namespace
+
+extern "C" int pset_execute_batch(lp_pset **ps, int32_t nruns, double runtime, double dt,
+                                  double outputdt, const lp_exec_opts *opts, int32_t block,
+                                  void *stream)
+{
+    return execute_batch(ps, nruns, runtime, dt, outputdt, opts, (hipStream_t)stream,
+                         block ? block : 256, true, nullptr);
+}
+
+namespace {
+
+// Copy of the mutable state of a particle set, for autotuning trials.
+struct Snapshot {
+    double *x = nullptr, *y = nullptr, *z = nullptr;
+    uint8_t *st = nullptr;
+    uint32_t *order = nullptr, count = 0;
+    unsigned long long psteps = 0;
+    int cur = 0, segs_since_sort = 0;
+    uint32_t n_launch = 0;
+    int64_t step = 0, stride = 0;
+    double t0 = 0.0, dt = 0.0;
+};
+
+int save_state(lp_pset *ps, Snapshot &s)
+{
+    const size_t N = (size_t)ps->n;
+    int rc;
+    if ((rc = dalloc(&s.x, N)) || (rc = dalloc(&s.y, N)) || (ps->dz && (rc = dalloc(&s.z, N))) ||
+        (rc = dalloc(&s.st, N)) || (rc = dalloc(&s.order, N)))
+        return rc;
+    HIPCHECK(hipDeviceSynchronize());
+    HIPCHECK(hipMemcpy(s.x, ps->dx, N * 8, hipMemcpyDeviceToDevice));
+    HIPCHECK(hipMemcpy(s.y, ps->dy, N * 8, hipMemcpyDeviceToDevice));
+    if (ps->dz) HIPCHECK(hipMemcpy(s.z, ps->dz, N * 8, hipMemcpyDeviceToDevice));
+    HIPCHECK(hipMemcpy(s.st, ps->dst, N, hipMemcpyDeviceToDevice));
+    HIPCHECK(hipMemcpy(s.order, ps->dorder[ps->cur], N * 4, hipMemcpyDeviceToDevice));
+    HIPCHECK(hipMemcpy(&s.count, ps->dcount + ps->cur, 4, hipMemcpyDeviceToHost));
+    HIPCHECK(hipMemcpy(&s.psteps, ps->dpsteps, 8, hipMemcpyDeviceToHost));
+    s.cur = ps->cur;
+    s.segs_since_sort = ps->segs_since_sort;
+    s.n_launch = ps->n_launch;
+    s.step = ps->step;
+    s.stride = ps->stride;
+    s.t0 = ps->t0;
+    s.dt = ps->dt;
+    return LP_OK;
+}
+
+int restore_state(lp_pset *ps, Snapshot &s)
+{
+    const size_t N = (size_t)ps->n;
+    HIPCHECK(hipDeviceSynchronize());
+    ps->cur = s.cur;
+    HIPCHECK(hipMemcpy(ps->dx, s.x, N * 8, hipMemcpyDeviceToDevice));
+    HIPCHECK(hipMemcpy(ps->dy, s.y, N * 8, hipMemcpyDeviceToDevice));
+    if (ps->dz) HIPCHECK(hipMemcpy(ps->dz, s.z, N * 8, hipMemcpyDeviceToDevice));
+    HIPCHECK(hipMemcpy(ps->dst, s.st, N, hipMemcpyDeviceToDevice));
+    HIPCHECK(hipMemcpy(ps->dorder[ps->cur], s.order, N * 4, hipMemcpyDeviceToDevice));
+    HIPCHECK(hipMemcpy(ps->dcount + ps->cur, &s.count, 4, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(ps->dpsteps, &s.psteps, 8, hipMemcpyHostToDevice));
+    ps->segs_since_sort = s.segs_since_sort;
+    ps->n_launch = s.n_launch;
+    ps->step = s.step;
+    ps->stride = s.stride;
+    ps->t0 = s.t0;
+    ps->dt = s.dt;
+    ps->count_pending = false;
+    return LP_OK;
+}
+
+void free_state(Snapshot &s)
+{
+    dfree(s.x);
+    dfree(s.y);
+    dfree(s.z);
+    dfree(s.st);
+    dfree(s.order);
+}
+
+std::string tune_key(lp_pset **ps, int nruns)
+{
+    double nodes = 0.0, parts = 0.0;
+    for (int r = 0; r < nruns; ++r) {
+        nodes += (double)ps[r]->fs->plane();
+        parts += (double)ps[r]->n;
+    }
+    const int g = (int)std::lround(std::log2(std::max(1.0, nodes / nruns)));
+    const int n = (int)std::lround(std::log2(std::max(1.0, parts)));
+    static const char *dt[] = {"f64", "f32", "bf16", "f16s"};
+    char buf[96];
+    snprintf(buf, sizeof buf, "%s:%s:2d:runs%d:g%d:n%d", dt[ps[0]->fs->dtype],
+             ps[0]->fs->g.spherical ? "sph" : "flat", nruns, g, n);
+    return buf;
+}
+
+// The cache is a JSON object with one entry per line:
+//   "key": {"block": B, "stencil_cache": C, "sort_every": S, "ms": T},
+bool cache_lookup(const char *path, const std::string &key, lp_tune *t)
+{
+    if (!path)
+        return false;
+    FILE *f = fopen(path, "r");
+    if (!f)
+        return false;
+    char line[512];
+    bool found = false;
+    const std::string pat = "\"" + key + "\"";
+    while (fgets(line, sizeof line, f)) {
+        const char *p = strstr(line, pat.c_str());
+        if (!p)
+            continue;
+        lp_tune r{};
+        if (sscanf(p + pat.size(), " : {\"block\": %d, \"stencil_cache\": %d, \"sort_every\": %d, "
+                                   "\"ms\": %lf}", &r.block, &r.stencil_cache, &r.sort_every,
+                   &r.ms) == 4) {
+            *t = r;
+            found = true;
+        }
+    }
+    fclose(f);
+    return found;
+}
+
+void cache_store(const char *path, const std::string &key, const lp_tune &t)
+{
+    if (!path)
+        return;
+    std::vector<std::string> lines;
+    if (FILE *f = fopen(path, "r")) {
+        char line[512];
+        const std::string pat = "\"" + key + "\"";
+        while (fgets(line, sizeof line, f)) {
+            std::string l(line);
+            while (!l.empty() && (l.back() == '\n' || l.back() == ','))
+                l.pop_back();
+            if (l.find("\": {") != std::string::npos && l.find(pat) == std::string::npos)
+                lines.push_back(l);
+        }
+        fclose(f);
+    }
+    char buf[512];
+    snprintf(buf, sizeof buf,
+             "  \"%s\": {\"block\": %d, \"stencil_cache\": %d, \"sort_every\": %d, \"ms\": %.4f}",
+             key.c_str(), t.block, t.stencil_cache, t.sort_every, t.ms);
+    lines.push_back(buf);
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *f = fopen(tmp.c_str(), "w");
+    if (!f)
+        return;
+    fprintf(f, "{\n");
+    for (size_t k = 0; k < lines.size(); ++k)
+        fprintf(f, "%s%s\n", lines[k].c_str(), k + 1 < lines.size() ? "," : "");
+    fprintf(f, "}\n");
+    fclose(f);
+    rename(tmp.c_str(), path);
+}
+
+}  // namespace
+
+extern "C" int pset_autotune_batch(lp_pset **ps, int32_t nruns, double dt, int32_t trial_steps,
+                                   const lp_exec_opts *opts, const char *cache_path,
+                                   lp_tune *best)
+{
+    if (!ps || !opts || !best || nruns < 1 || trial_steps < 1 || !(dt > 0.0))
+        return fail(LP_EINVAL, "bad autotune arguments");
+    const std::string key = tune_key(ps, nruns);
+    if (cache_lookup(cache_path, key, best))
+        return LP_OK;
+    std::vector<Snapshot> saved(nruns);
+    for (int r = 0; r < nruns; ++r) {
+        int rc = save_state(ps[r], saved[r]);
+        if (rc) {
+            for (auto &s : saved) free_state(s);
+            return rc;
+        }
+    }
+    std::vector<lp_exec_opts> o(opts, opts + nruns);
+    lp_tune b{};
+    b.ms = 1e300;
+    int rc = LP_OK;
+    const int blocks[] = {128, 256, 512};
+    for (int cache = 1; cache >= 0 && rc == LP_OK; --cache)
+        for (int sort = 0; sort <= 1 && rc == LP_OK; ++sort)
+            for (int blk : blocks) {
+                for (auto &x : o) {
+                    x.stencil_cache = cache;
+                    x.sort_every = sort;
+                    x.output_stride = 0;
+                    x.profile = 0;
+                }
+                double ms = 0.0;
+                // sorting before the trial counts: the trial is one segment
+                for (int r = 0; r < nruns; ++r)
+                    ps[r]->segs_since_sort = sort ? 1 << 30 : 0;
+                rc = execute_batch(ps, nruns, trial_steps * dt, dt, 0.0, o.data(), nullptr, blk,
+                                   false, &ms);
+                for (int r = 0; r < nruns && rc == LP_OK; ++r)
+                    rc = restore_state(ps[r], saved[r]);
+                if (rc)
+                    break;
+                if (ms < b.ms) {
+                    b.ms = ms;
+                    b.block = blk;
+                    b.stencil_cache = cache;
+                    b.sort_every = sort;
+                }
+            }
+    for (auto &s : saved)
+        free_state(s);
+    if (rc)
+        return rc;
+    *best = b;
+    cache_store(cache_path, key, b);
     return LP_OK;
 }
 

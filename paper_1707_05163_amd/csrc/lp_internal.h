@@ -81,6 +81,9 @@ struct RecordParams {
 hipError_t launch_advect(int store, bool is3d, const AdvectParams &p, uint32_t n_launch,
                          hipStream_t s);
 hipError_t launch_record(const RecordParams &p, hipStream_t s);
+hipError_t launch_advect_batch(int store, bool steady, bool spherical, const AdvectParams *runs,
+                               const uint32_t *cstart, int nruns, uint32_t total,
+                               uint32_t *queues, int block, hipStream_t s, int *grid_out);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
 hipError_t launch_iota(uint32_t *p, size_t n, hipStream_t s);
 hipError_t launch_compact(const uint32_t *order_in, const uint32_t *n_in, const uint8_t *status,
@@ -97,6 +100,11 @@ hipError_t launch_convert_snapshot(int store, bool is3d, const float *U, const f
                                    const float *W, const double *U64, const double *V64,
                                    const double *W64, size_t plane, int nzl, void *slot,
                                    float *scales, float *tmp, hipStream_t s);
+hipError_t launch_philox_normals(uint32_t run_id, uint32_t seed, int64_t n, const uint32_t *pid,
+                                 const uint32_t *step, uint32_t *words, double *normals,
+                                 hipStream_t s);
+hipError_t launch_slot_values(int store, bool is3d, const void *slot, const float *scales,
+                              size_t plane, int nzl, float *U, float *V, float *W, hipStream_t s);
 hipError_t launch_lat_tables(const double *lat, int ny, double *coslat, double *sinlat,
                               hipStream_t s);
 hipError_t launch_level_absmax(const float *F, size_t plane, int nzl, float *out,

@@ -1,0 +1,115 @@
+"""GPU parity of the Brownian term (Philox4x32-10 words bit-equal with the oracle)
+and of reduced-precision field storage (bfloat16 / scaled float16 values bit-equal
+with the reference quantisers; FP32 interpolation within its derived bound)."""
+
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from oracle import quantize as Q
+from synthetic import configs as SC
+from synthetic import idealised as SI
+
+from parity import compare_record, log, slice_record
+
+pytestmark = pytest.mark.gpu
+
+
+def test_philox_words_bit_equal_and_normals():
+    from paper_1707_05163_amd import philox_normals
+    rng = np.random.default_rng(9)
+    n = 4096
+    pid = rng.integers(0, 2 ** 32, n, dtype=np.uint64).astype(np.uint32)
+    step = rng.integers(0, 2 ** 32, n, dtype=np.uint64).astype(np.uint32)
+    for run_id, seed in ((0, O.SEED), (63, O.SEED), (0xFFFFFFFF, 0xDEADBEEF)):
+        words, normals = philox_normals(run_id, seed, pid, step)
+        for i in range(0, n, 7):
+            ref = O.philox4x32_10([pid[i], step[i], 0, 0], [run_id, seed])
+            assert list(words[i]) == list(ref)
+            nr = O.normals(run_id, seed, int(pid[i]), int(step[i]))
+            assert np.allclose(normals[i], nr, rtol=4e-15, atol=4e-15)
+    # the known-answer vector with a zero counter and key
+    w, _ = philox_normals(0, 0, np.zeros(1, np.uint32), np.zeros(1, np.uint32))
+    assert list(w[0]) == [0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8]
+
+
+def test_paper_brownian_on_gpu():
+    w = SI.brownian_uniform_kh()
+    log(f"brownian: {w.n} particles x {w.nsteps} steps")
+    from paper_1707_05163_amd import FieldSet, ParticleSet
+    fs = FieldSet.from_workload(w, dtype="f64")
+    ps = ParticleSet(fs, w.lon0, w.lat0)
+    ps.execute(w.nsteps * w.dt, w.dt, Kh=w.Kh, run_id=0)
+    g = ps.get()
+    ofs = O.OracleFieldSet.from_workload(w)
+    st = O.make_state(w.lon0, w.lat0)
+    assert O.advance(ofs, st, w.dt, w.nsteps, Kh=w.Kh) == 0
+    tol = 1e-9 * 6e4
+    assert np.abs(g["lon"] - st.x).max() <= tol and np.abs(g["lat"] - st.y).max() <= tol
+    sig = np.sqrt(2 * w.Kh * w.nsteps * w.dt)
+    assert abs(g["lon"].var() / sig ** 2 - 1) < 4 * np.sqrt(2.0 / w.n)
+    assert np.sqrt(0.5 * (g["lon"].var() + g["lat"].var())) == pytest.approx(4160.0, rel=0.01)
+
+
+def test_brownian_in_eddy_field_with_edge_deletion():
+    runs = SC.cfg3_ensemble(n_runs=3, np_min=2000, np_max=4000, nsteps=288)
+    from paper_1707_05163_amd import FieldSet, ParticleSet
+    for w in runs:
+        fs = FieldSet.from_workload(w)
+        ps = ParticleSet(fs, w.lon0, w.lat0)
+        ps.execute(w.nsteps * w.dt, w.dt, 6 * 3600.0, Kh=w.Kh, run_id=w.run_id, output_stride=1)
+        recs = ps.records()
+        ofs = O.OracleFieldSet.from_workload(w)
+        st = O.make_state(w.lon0, w.lat0)
+        orecs = O.run(ofs, st, w.dt, w.nsteps * w.dt, 6 * 3600.0, Kh=w.Kh, run_id=w.run_id)
+        ext = float(w.grid.lon[-1])
+        for m, o in enumerate(orecs):
+            compare_record(slice_record(recs, m), o, w.grid, ext, label=f"{w.name} rec {m}",
+                           ofs=ofs)
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f16s"])
+def test_quantised_storage_bit_equal_to_reference(dtype):
+    from paper_1707_05163_amd import FieldSet
+    q = Q.bf16_round if dtype == "bf16" else Q.f16_scaled_round
+    w2 = SC.cfg1_global_eddies(nx=144, ny=72, nt=3, n_particles=10)
+    fs = FieldSet.from_workload(w2, dtype=dtype)
+    for s in range(3):
+        U, V, _ = fs.get_snapshot(w2.fields.times[s])
+        assert np.array_equal(U, q(w2.fields.U[s])) and np.array_equal(V, q(w2.fields.V[s]))
+    w3 = SC.cfg2_global_3d(nx=120, ny=60, nz=12, nt=2, n_particles=10)
+    fs3 = FieldSet.from_workload(w3, dtype=dtype, capacity=2)
+    for s in range(2):
+        U0, V0, W0 = w3.fields.snapshot(s)
+        U, V, W = fs3.get_snapshot(w3.fields.times[s])
+        assert np.array_equal(U, q(U0)) and np.array_equal(V, q(V0)) and np.array_equal(W, q(W0))
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f16s"])
+def test_fp32_interpolation_matches_oracle_on_stored_values(dtype):
+    """The oracle runs in FP64 on the values the reduced storage holds; the GPU
+    interpolates them in FP32.  FP32 interpolation of |v| <= 1 m/s errs by at most
+    a few 2^-24 m/s per stage, i.e. <= 1e-6 m/s; over one day that is <= 0.1 m,
+    here bounded by 2 m (1.8e-5 degree) to leave room for the flow's strain."""
+    q = Q.bf16_round if dtype == "bf16" else Q.f16_scaled_round
+    w = SC.cfg1_global_eddies(nx=360, ny=180, nt=30, n_particles=5000, nsteps=288)
+    from paper_1707_05163_amd import FieldSet, ParticleSet
+    fs = FieldSet.from_workload(w, dtype=dtype)
+    ps = ParticleSet(fs, w.lon0, w.lat0)
+    ps.execute(w.nsteps * w.dt, w.dt)
+    g = ps.get()
+    _, gst = ps.status()
+    Uq = np.stack([q(u) for u in w.fields.U])
+    Vq = np.stack([q(v) for v in w.fields.V])
+    ofs = O.OracleFieldSet(w.grid.lon, w.grid.lat, None, w.fields.times, Uq, Vq,
+                           spherical=True, period=w.fields.period, land=w.grid.land)
+    st = O.make_state(w.lon0, w.lat0)
+    assert O.advance(ofs, st, w.dt, w.nsteps) == 0
+    both = (gst == 0) & (st.status == 0)
+    assert (gst != st.status).sum() <= 2
+    M = 111120.0
+    dx = (g["lon"][both] - st.x[both]) * np.cos(np.deg2rad(st.y[both])) * M
+    dy = (g["lat"][both] - st.y[both]) * M
+    assert np.sqrt(dx * dx + dy * dy).max() <= 2.0
