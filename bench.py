@@ -37,6 +37,7 @@ STENCIL_BYTES_2D_F32 = 4 * 2 * 2 * 4     # 64 B
 STATE_BYTES_2D = 8 + 8 + 8 + 8 + 4 + 1 + 1  # lon, lat read + write, order id, status r/w
 FLOPS_2D_STEP = 230
 FLOPS_3D_STEP = 567
+FLOPS_BROWNIAN = 9  # sqrt(2 Kh dt), two kicks, -2 ln u1 scaling, 2 pi u2 (transcendentals excluded)
 
 
 def parse():
@@ -51,7 +52,7 @@ def parse():
     p.add_argument("--sort-every", type=int, default=1)
     p.add_argument("--cpu-baseline", type=int, default=1)
     p.add_argument("--cpu-sample-stride", type=int, default=100)
-    p.add_argument("--config", default="cfg1", choices=["cfg1", "cfg2"])
+    p.add_argument("--config", default="cfg1", choices=["cfg1", "cfg2", "cfg3"])
     p.add_argument("--stencil-cache", type=int, default=1)
     p.add_argument("--calibrate-copy", type=float, default=0.0,
                    help="first copy this many GB device-to-device (a plain copy kernel of "
@@ -210,6 +211,86 @@ def main_cfg2(a):
     print(json.dumps(out), flush=True)
 
 
+def main_cfg3(a):
+    """64 uneven 2D runs (grids 64^2..1024^2, 1k..2M particles) with the Brownian
+    term, advanced together by the batched persistent launch; the launch shape
+    comes from the autotuner.  Also times the runs one after the other."""
+    import torch
+    from paper_1707_05163_amd import ParticleSet, FieldSet, autotune_batch, execute_batch
+    from synthetic import configs as SC
+
+    torch.cuda.set_device(0)
+    ws = SC.cfg3_ensemble()
+    ntot = sum(w.n for w in ws)
+    print(f"[bench] cfg3: {len(ws)} runs, {ntot} particles, grids "
+          f"{min(w.grid.nx for w in ws)}..{max(w.grid.nx for w in ws)}", file=sys.stderr,
+          flush=True)
+    fss = [FieldSet.from_workload(w) for w in ws]
+    dev0 = [(torch.from_numpy(w.lon0).cuda(), torch.from_numpy(w.lat0).cuda()) for w in ws]
+    stream = torch.cuda.current_stream()
+    runtime = ws[0].nsteps * ws[0].dt
+
+    def fresh():
+        ps = [ParticleSet(f, x, y, stream=stream) for f, (x, y) in zip(fss, dev0)]
+        torch.cuda.synchronize()
+        return ps
+
+    opts = [ParticleSet.opts(Kh=w.Kh, run_id=w.run_id, profile=True) for w in ws]
+    cache = os.environ.get("LP_AUTOTUNE_CACHE", "/tmp/lp_autotune.json")
+    ps = fresh()
+    t = time.perf_counter()
+    best = autotune_batch(ps, ws[0].dt, 24, opts, cache)
+    tune_s = time.perf_counter() - t
+    for o in opts:
+        o.stencil_cache, o.sort_every = best["stencil_cache"], best["sort_every"]
+    total = 0.0
+    psteps = 0
+    kms = 0.0
+    launches = 0
+    for it in range(a.warmup + a.steps):
+        ps = fresh()
+        t0 = time.perf_counter()
+        execute_batch(ps, runtime, ws[0].dt, 86400.0, opts, block=best["block"], stream=stream)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        print(f"[bench] step {it}: {el * 1e3:.1f} ms", file=sys.stderr, flush=True)
+        if it >= a.warmup:
+            total += el
+            psteps += sum(p.status()[0]["particle_steps"] for p in ps)
+            ms, k = ps[0].timing()
+            kms += ms
+            launches += k
+    # the same runs one after the other, each with its own launches
+    ps = fresh()
+    standalone = 0.0
+    for p, w in zip(ps, ws):
+        t0 = time.perf_counter()
+        p.execute(runtime, w.dt, 86400.0, Kh=w.Kh, run_id=w.run_id, stream=stream)
+        torch.cuda.synchronize()
+        standalone += time.perf_counter() - t0
+    rate = psteps / total
+    avg_launch_s = kms / 1e3 / launches
+    spl = psteps / launches
+    roof, other = roofline(spl, avg_launch_s, STENCIL_BYTES_2D_F32 + STATE_BYTES_2D / 288.0,
+                           FLOPS_2D_STEP + FLOPS_BROWNIAN)
+    out = {
+        "metric": "RK4 particle-steps/s", "value": rate, "unit": "particle-steps/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": total / a.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "cfg3_ensemble_64_runs", "runs": len(ws), "particles": ntot,
+                   "rk4_steps": ws[0].nsteps, "dt_s": ws[0].dt, "Kh": ws[0].Kh,
+                   "autotuned": best, "autotune_s": round(tune_s, 3)},
+        "roofline": roof, "roofline_other": other,
+        "kernel": {"name": "k_advect2d_batch", "launches": launches,
+                   "avg_launch_ms": round(avg_launch_s * 1e3, 4),
+                   "particle_steps_per_launch": spl},
+        "batched_makespan_ms": total / a.steps * 1e3,
+        "standalone_sum_ms": standalone * 1e3,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -228,6 +309,8 @@ def main():
         del src, dst
     if a.config == "cfg2":
         return main_cfg2(a)
+    if a.config == "cfg3":
+        return main_cfg3(a)
     import torch
     from paper_1707_05163_amd import FieldSet, ParticleSet
     from synthetic import configs as SC

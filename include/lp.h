@@ -211,6 +211,29 @@ void pset_destroy(lp_pset *ps);
 int lp_philox_normals(uint32_t run_id, uint32_t seed, int64_t n, const uint32_t *pid,
                       const uint32_t *step, uint32_t *words, double *normals);
 
+/* ------------------------------------------------------------ flow-map surrogate
+ * A learned stand-in for a fixed number of RK4 steps: a fully connected network
+ * 64 -> 256 -> 256 -> 256 -> 256 -> 2 with tanh-form GELU after each hidden layer,
+ * bfloat16 weights and activations, FP32 accumulation on the matrix cores, FP32
+ * master weights and Adam.  Parameters travel as one float array, layer by layer:
+ * W_l (fan_in x fan_out, row-major) then b_l (fan_out). */
+typedef struct lp_model lp_model;
+int64_t surrogate_param_count(void);
+/* He-normal initialisation (std sqrt(2 / fan_in)) from `seed`, zero biases. */
+int surrogate_create(uint32_t seed, lp_model **out);
+int surrogate_get_params(lp_model *m, float *params);
+int surrogate_set_params(lp_model *m, const float *params);
+/* Network output for B host rows X [B x 64] (rounded to bf16) -> Y [B x 2]. */
+int surrogate_forward(lp_model *m, int64_t B, const float *X, float *Y);
+/* Gradients (parameter layout) of L = (1/2B) sum (y - t)^2 over a batch of B rows
+ * (B a multiple of 128), without updating; loss may be NULL. */
+int surrogate_gradients(lp_model *m, int64_t B, const float *X, const float *T, float *grads,
+                        float *loss);
+/* One Adam step (b1 0.9, b2 0.999, eps 1e-8) on that batch; loss may be NULL. */
+int surrogate_train_step(lp_model *m, int64_t B, const float *X, const float *T, double lr,
+                         float *loss);
+void surrogate_destroy(lp_model *m);
+
 const char *lp_last_error(void);
 /* Library version string. */
 const char *lp_version(void);

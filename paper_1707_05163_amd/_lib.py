@@ -27,6 +27,8 @@ EXPORTS = (
     "pset_create", "pset_create_device", "pset_execute", "pset_status", "pset_get",
     "pset_records", "pset_timing", "pset_destroy", "lp_last_error", "lp_version",
     "pset_execute_batch", "pset_autotune_batch",
+    "surrogate_param_count", "surrogate_create", "surrogate_get_params", "surrogate_set_params",
+    "surrogate_forward", "surrogate_gradients", "surrogate_train_step", "surrogate_destroy",
 )
 
 
@@ -86,6 +88,14 @@ def _declare(L):
         "pset_autotune_batch": ([C.POINTER(C.c_void_p), C.c_int32, C.c_double, C.c_int32,
                                  C.POINTER(lp_exec_opts), C.c_char_p, C.POINTER(lp_tune)], I),
         "pset_destroy": ([P], None),
+        "surrogate_param_count": ([], C.c_int64),
+        "surrogate_create": ([C.c_uint32, pp], I),
+        "surrogate_get_params": ([P, P], I),
+        "surrogate_set_params": ([P, P], I),
+        "surrogate_forward": ([P, C.c_int64, P, P], I),
+        "surrogate_gradients": ([P, C.c_int64, P, P, P, P], I),
+        "surrogate_train_step": ([P, C.c_int64, P, P, C.c_double, P], I),
+        "surrogate_destroy": ([P], None),
         "lp_last_error": ([], C.c_char_p),
         "lp_version": ([], C.c_char_p),
     }

@@ -255,3 +255,80 @@ def autotune_batch(psets, dt: float, trial_steps: int, opts=None, cache_path=Non
                                       None if cache_path is None else str(cache_path).encode(),
                                       C.byref(t)))
     return dict(block=t.block, stencil_cache=t.stencil_cache, sort_every=t.sort_every, ms=t.ms)
+
+
+SIZES = (64, 256, 256, 256, 256, 2)
+
+
+class Surrogate:
+    """The flow-map network on the device (weights, optimiser state, kernels)."""
+
+    def __init__(self, seed: int = 0):
+        h = C.c_void_p()
+        L.check(L.lib.surrogate_create(int(seed) & 0xFFFFFFFF, C.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    @staticmethod
+    def param_count() -> int:
+        return int(L.lib.surrogate_param_count())
+
+    def get_params(self):
+        """List of (W, b) per layer, float32, W shaped (fan_in, fan_out)."""
+        flat = np.empty(self.param_count(), np.float32)
+        L.check(L.lib.surrogate_get_params(self._h, flat.ctypes.data))
+        return _unflatten(flat)
+
+    def set_params(self, layers):
+        flat = np.concatenate([np.concatenate([np.asarray(W, np.float32).ravel(),
+                                               np.asarray(b, np.float32).ravel()])
+                               for W, b in layers]).astype(np.float32)
+        L.check(L.lib.surrogate_set_params(self._h, flat.ctypes.data))
+
+    def forward(self, X):
+        X = np.ascontiguousarray(X, np.float32)
+        Y = np.empty((X.shape[0], 2), np.float32)
+        L.check(L.lib.surrogate_forward(self._h, X.shape[0], X.ctypes.data, Y.ctypes.data))
+        return Y
+
+    def gradients(self, X, T):
+        X = np.ascontiguousarray(X, np.float32)
+        T = np.ascontiguousarray(T, np.float32)
+        g = np.empty(self.param_count(), np.float32)
+        loss = np.zeros(1, np.float32)
+        L.check(L.lib.surrogate_gradients(self._h, X.shape[0], X.ctypes.data, T.ctypes.data,
+                                          g.ctypes.data, loss.ctypes.data))
+        return _unflatten(g), float(loss[0])
+
+    def train_step(self, X, T, lr: float):
+        X = np.ascontiguousarray(X, np.float32)
+        T = np.ascontiguousarray(T, np.float32)
+        loss = np.zeros(1, np.float32)
+        L.check(L.lib.surrogate_train_step(self._h, X.shape[0], X.ctypes.data, T.ctypes.data,
+                                           float(lr), loss.ctypes.data))
+        return float(loss[0])
+
+    def close(self):
+        if getattr(self, "_h", None):
+            L.lib.surrogate_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _unflatten(flat):
+    out, q = [], 0
+    for a, b in zip(SIZES[:-1], SIZES[1:]):
+        W = flat[q:q + a * b].reshape(a, b)
+        q += a * b
+        bb = flat[q:q + b]
+        q += b
+        out.append((W.copy(), bb.copy()))
+    return out

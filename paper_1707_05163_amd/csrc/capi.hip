@@ -18,6 +18,7 @@
 
 #include "../../include/lp.h"
 #include "lp_internal.h"
+#include "lp_objects.h"
 
 using lp::AxisDev;
 using lp::GridDev;
@@ -106,11 +107,6 @@ int build_axis(const double *src, int n, const char *name, HostAxis &h)
     return LP_OK;
 }
 
-struct DevAxis {
-    double *c = nullptr, *rw = nullptr;
-    int32_t *guess = nullptr;
-};
-
 int upload_axis(const HostAxis &h, DevAxis &d, AxisDev &a)
 {
     int rc;
@@ -152,65 +148,6 @@ size_t node_bytes(int dtype, bool is3d)
 }
 
 }  // namespace
-
-struct lp_fieldset {
-    int device = 0;
-    int nx = 0, ny = 0, nz = 0, nzl = 1;
-    bool is3d = false;
-    int mesh = 0, dtype = 0, capacity = 0;
-    double period = 0.0;
-    DevAxis dx_, dy_, dz_;
-    GridDev g{};
-    uint8_t *dland = nullptr;
-    double *dcoslat = nullptr, *dsinlat = nullptr;
-    char *dslots = nullptr;
-    size_t slot_bytes = 0;
-    float *dscales = nullptr;
-    float *dtmp = nullptr;
-    float *dstage = nullptr;
-    double *dstage64 = nullptr;
-    hipStream_t up = nullptr;
-    std::vector<hipEvent_t> ready, release;
-    std::vector<double> slot_t;
-    std::vector<int64_t> slot_seq;  // push index held by each slot, -1 = empty
-    int64_t npushed = 0;
-    double first_t = 0.0, last_t = 0.0;
-
-    size_t plane() const { return (size_t)nx * (size_t)ny; }
-};
-
-struct lp_pset {
-    lp_fieldset *fs = nullptr;
-    int64_t n = 0;
-    double *dx = nullptr, *dy = nullptr, *dz = nullptr;
-    uint8_t *dst = nullptr;
-    uint32_t *dorder[2] = {nullptr, nullptr};
-    uint32_t *dcount = nullptr;  // [2]
-    int cur = 0;
-    uint32_t n_launch = 0;       // host upper bound of the active count
-    uint32_t *hcount = nullptr;  // pinned copy of the device count
-    hipEvent_t count_ev = nullptr;
-    bool count_pending = false;
-    uint32_t *dkeys = nullptr, *dhist = nullptr, *dblk = nullptr;
-    uint32_t nbins = 0;
-    unsigned long long *dpsteps = nullptr;
-    double t0 = 0.0, dt = 0.0;
-    int64_t step = 0;
-    // output records (record-major)
-    int64_t stride = 0, nper = 0, nrec = 0, rec_cap = 0;
-    double *rx = nullptr, *ry = nullptr, *rz = nullptr;
-    uint8_t *rst = nullptr;
-    int32_t *rci = nullptr, *rcj = nullptr, *rck = nullptr;
-    // time table
-    TimeEntry *dtab = nullptr, *htab = nullptr;
-    size_t tab_cap = 0;
-    hipEvent_t tab_ev = nullptr;
-    bool tab_pending = false;
-    // profiling
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof;
-    int segs_since_sort = 1 << 30;
-    hipStream_t last_stream = nullptr;
-};
 
 // ---------------------------------------------------------------- field sets
 extern "C" int fieldset_create(const lp_grid_desc *g, lp_fieldset **out)
@@ -290,6 +227,11 @@ extern "C" int fieldset_create(const lp_grid_desc *g, lp_fieldset **out)
         if (hipMemcpy(fs->dland, cell.data(), cell.size(), hipMemcpyHostToDevice) != hipSuccess)
             return bail(fail(LP_EDEVICE, "land mask upload failed"));
         fs->g.landcell = fs->dland;
+        if ((rc = dalloc(&fs->dlandnode, (size_t)g->nx * g->ny)))
+            return bail(rc);
+        if (hipMemcpy(fs->dlandnode, g->land, (size_t)g->nx * g->ny, hipMemcpyHostToDevice) !=
+            hipSuccess)
+            return bail(fail(LP_EDEVICE, "land mask upload failed"));
     }
     fs->slot_bytes = node_bytes(fs->dtype, fs->is3d) * fs->plane() * fs->nzl;
     fs->slot_bytes = (fs->slot_bytes + 255) & ~(size_t)255;
@@ -323,6 +265,7 @@ extern "C" void fieldset_destroy(lp_fieldset *fs)
     free_axis(fs->dy_);
     free_axis(fs->dz_);
     dfree(fs->dland);
+    dfree(fs->dlandnode);
     dfree(fs->dcoslat);
     dfree(fs->dsinlat);
     dfree(fs->dslots);
@@ -1428,3 +1371,33 @@ extern "C" int pset_timing(lp_pset *ps, double *kernel_ms, int64_t *launches)
 extern "C" const char *lp_last_error(void) { return g_err.c_str(); }
 
 extern "C" const char *lp_version(void) { return "lp-mi355x 0.1 (gfx950)"; }
+
+// ---------------------------------------------------------------- internal helpers
+// Reset a particle set to n <= capacity particles at device positions (x, y), time
+// t0 and step 0, with every particle active; used for the surrogate's training
+// rounds so one set serves every round.
+int lp_pset_reset_device(lp_pset *ps, int64_t n, const double *x, const double *y, double t0,
+                         hipStream_t stream)
+{
+    if (!ps || n < 1 || n > ps->n)
+        return fail(LP_EINVAL, "bad reset");
+    HIPCHECK(hipMemcpyAsync(ps->dx, x, (size_t)n * 8, hipMemcpyDeviceToDevice, stream));
+    HIPCHECK(hipMemcpyAsync(ps->dy, y, (size_t)n * 8, hipMemcpyDeviceToDevice, stream));
+    HIPCHECK(hipMemsetAsync(ps->dst, 0, (size_t)ps->n, stream));
+    if (n < ps->n)  // the unused tail is never advanced
+        HIPCHECK(hipMemsetAsync(ps->dst + n, LP_ST_DELETED, (size_t)(ps->n - n), stream));
+    HIPCHECK(hipMemsetAsync(ps->dpsteps, 0, sizeof(unsigned long long), stream));
+    HIPCHECK(lp::launch_iota(ps->dorder[0], (size_t)n, stream));
+    HIPCHECK(lp::launch_fill_u32(ps->dcount, (uint32_t)n, 1, stream));
+    ps->cur = 0;
+    ps->n_launch = (uint32_t)n;
+    ps->count_pending = false;
+    ps->t0 = t0;
+    ps->dt = 0.0;
+    ps->step = 0;
+    ps->segs_since_sort = 1 << 30;
+    ps->last_stream = stream;
+    return LP_OK;
+}
+
+void lp_set_error(const char *msg) { g_err = msg; }

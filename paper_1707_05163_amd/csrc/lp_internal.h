@@ -77,6 +77,24 @@ struct RecordParams {
     int32_t *ci, *cj, *ck;
 };
 
+// GEMM of the surrogate network: C[M x N] = sum_k A(i, k) B(k, j) on bf16 operands
+// with FP32 accumulation, A(i, k) = A[i*sai + k*sak], B(k, j) = B[k*sbk + j*sbj].
+enum : int { kEpiHidden = 0, kEpiOut = 1, kEpiBackData = 2, kEpiAccum = 3 };
+struct GemmArgs {
+    const uint16_t *A, *B;
+    int64_t M, N, K, kchunk;   // M % 32 == 0, N % 32 == 0 (% 128 if N >= 128), K % 16 == 0
+    int64_t sai, sak, sbk, sbj;
+    const float *bias;         // hidden / output: per column
+    float *Z;                  // hidden: FP32 pre-activation out (may be null)
+    uint16_t *H;               // hidden: bf16 GELU(z) out; back-data: bf16 dz out
+    int64_t ldc;               // row stride of Z, H, Zin, dZ
+    float *Y;                  // output: FP32 out; accumulate: FP32 += C
+    int64_t ldy;
+    int32_t nvalid;            // output: columns actually stored
+    const float *Zin;          // back-data: pre-activation of the layer below
+    float *dZ;                 // back-data: FP32 dz out
+};
+
 // launchers (return hipError_t of the launch)
 hipError_t launch_advect(int store, bool is3d, const AdvectParams &p, uint32_t n_launch,
                          hipStream_t s);
@@ -107,6 +125,15 @@ hipError_t launch_slot_values(int store, bool is3d, const void *slot, const floa
                               size_t plane, int nzl, float *U, float *V, float *W, hipStream_t s);
 hipError_t launch_lat_tables(const double *lat, int ny, double *coslat, double *sinlat,
                               hipStream_t s);
+hipError_t launch_gemm(int epi, const GemmArgs &g, hipStream_t s);
+hipError_t launch_loss_grad(const float *Y, const float *T, int64_t B, int ldy, float *dZ,
+                            uint16_t *dZq, float *loss, hipStream_t s);
+hipError_t launch_colsum(const float *dZ, int64_t B, int N, float *db, hipStream_t s);
+hipError_t launch_adam(float *W, const float *G, float *m, float *v, int K, int N, int nvalid,
+                       float lr, float b1, float b2, float eps, int t, uint16_t *Wb, uint16_t *WT,
+                       hipStream_t s);
+hipError_t launch_fill_f32(float *p, float v, int64_t n, hipStream_t s);
+hipError_t launch_to_bf16(const float *x, int64_t n, uint16_t *y, hipStream_t s);
 hipError_t launch_level_absmax(const float *F, size_t plane, int nzl, float *out,
                                hipStream_t s);
 

@@ -1,0 +1,742 @@
+// surrogate.hip -- learned flow map: an MLP that predicts the displacement of a
+// particle over one segment of fine RK4 steps, trained on segments that the RK4
+// advection itself produces, and used with plain RK4 as the judge: a particle whose
+// prediction disagrees with a coarse RK4 estimate by more than a threshold (or
+// whose predicted end point is outside the grid or on land) is re-integrated with
+// the fine RK4 steps.
+//
+// Network input (64 values, bf16): lon/180, lat/90, sin and cos of the phase of the
+// periodic field, the 5 x 5 patch of U and V (m/s) around the nearest node,
+// interpolated linearly in time, and 10 zeros.  Output: the segment displacement in
+// metres (east, north) divided by kOutScale.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <random>
+#include <vector>
+
+#include "../../include/lp.h"
+#include "lp_internal.h"
+#include "lp_objects.h"
+
+using lp::GemmArgs;
+using lp::TimeEntry;
+
+namespace {
+
+constexpr int kIn = 64, kHid = 256, kOut = 2, kOutPad = 32, kLayers = 5;
+constexpr double kOutScale = 7200.0;  // metres: 1 m/s over 2 h
+const int kFanIn[kLayers] = {kIn, kHid, kHid, kHid, kHid};
+const int kFanOut[kLayers] = {kHid, kHid, kHid, kHid, kOut};
+const int kPadOut[kLayers] = {kHid, kHid, kHid, kHid, kOutPad};
+
+#define SCHECK(expr)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess) {                                                               \
+            char b_[384];                                                                     \
+            snprintf(b_, sizeof b_, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
+                     __LINE__);                                                               \
+            lp_set_error(b_);                                                                 \
+            return e_ == hipErrorOutOfMemory ? LP_ENOMEM : LP_EDEVICE;                        \
+        }                                                                                     \
+    } while (0)
+
+template <class T>
+hipError_t dmalloc(T **p, size_t n)
+{
+    *p = nullptr;
+    return n ? hipMalloc((void **)p, n * sizeof(T)) : hipSuccess;
+}
+
+template <class T>
+void dfree(T *&p)
+{
+    if (p)
+        (void)hipFree((void *)p);
+    p = nullptr;
+}
+
+// ------------------------------------------------------------------ device kernels
+__device__ inline uint16_t to_bf16(float f)
+{
+    uint32_t b = __float_as_uint(f);
+    if ((b & 0x7F800000u) == 0x7F800000u && (b & 0x007FFFFFu))
+        return (uint16_t)((b >> 16) | 0x40u);
+    b += 0x7FFFu + ((b >> 16) & 1u);
+    return (uint16_t)(b >> 16);
+}
+
+__device__ inline int nearest_node(const lp::AxisDev &a, double x)
+{
+    if (!(x >= a.lo))
+        return 0;
+    if (!(x <= a.hi))
+        return a.n - 1;
+    int g = a.uniform ? (int)((x - a.lo) * a.ginv) : 0;
+    if (!a.uniform) {
+        int b = (int)((x - a.lo) * a.ginv);
+        b = b < lp::kGuessBins - 1 ? b : lp::kGuessBins - 1;
+        g = a.guess[b];
+    }
+    g = g < 0 ? 0 : (g > a.n - 2 ? a.n - 2 : g);
+    while (g > 0 && a.c[g] > x)
+        --g;
+    while (g < a.n - 2 && a.c[g + 1] <= x)
+        ++g;
+    return (x - a.c[g]) * a.rw[g] < 0.5 ? g : g + 1;
+}
+
+__device__ inline void node_uv(const lp::FieldDev &f, int slot, size_t node, float &u, float &v,
+                               int store)
+{
+    const char *p = static_cast<const char *>(f.slots) + (size_t)slot * f.slot_bytes;
+    if (store == lp::kF32) {
+        const float2 q = reinterpret_cast<const float2 *>(p)[node];
+        u = q.x;
+        v = q.y;
+    } else if (store == lp::kF64) {
+        const double2 q = reinterpret_cast<const double2 *>(p)[node];
+        u = (float)q.x;
+        v = (float)q.y;
+    } else if (store == lp::kBF16) {
+        const uint32_t q = reinterpret_cast<const uint32_t *>(p)[node];
+        u = __uint_as_float(q << 16);
+        v = __uint_as_float(q & 0xFFFF0000u);
+    } else {
+        const uint32_t q = reinterpret_cast<const uint32_t *>(p)[node];
+        const float *sc = f.scales + (size_t)slot * f.nzl * 3;
+        u = (float)__builtin_bit_cast(_Float16, (uint16_t)(q & 0xFFFFu)) * sc[0];
+        v = (float)__builtin_bit_cast(_Float16, (uint16_t)(q >> 16)) * sc[1];
+    }
+}
+
+struct FeatArgs {
+    lp::GridDev g;
+    lp::FieldDev f;
+    int32_t store;
+    const double *x, *y;      // positions (sample- or id-indexed)
+    const uint32_t *sel;      // row r reads sample/id sel[r] (null: r)
+    const uint32_t *round;    // per sample round (null: round 0)
+    const TimeEntry *tab;     // time bracket per round
+    const float *phase;       // sin, cos per round
+    const uint32_t *n_dev;    // number of rows with data (device), or null
+    int64_t n, npad;          // rows with data (if n_dev is null), padded rows
+    uint16_t *X;              // [npad x 64]
+    const float *tgt;         // per sample targets (2 floats), or null
+    float *T;                 // [npad x 2]
+};
+
+__global__ void k_features(FeatArgs a)
+{
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= a.npad)
+        return;
+    const int64_t n = a.n_dev ? (int64_t)*a.n_dev : a.n;
+    uint16_t *row = a.X + r * kIn;
+    if (r >= n) {
+        for (int q = 0; q < kIn; ++q)
+            row[q] = 0;
+        if (a.T) {
+            a.T[2 * r] = 0.f;
+            a.T[2 * r + 1] = 0.f;
+        }
+        return;
+    }
+    const uint32_t s = a.sel ? a.sel[r] : (uint32_t)r;
+    const uint32_t rd = a.round ? a.round[s] : 0u;
+    const TimeEntry e = a.tab[rd];
+    const double x = a.x[s], y = a.y[s];
+    row[0] = to_bf16((float)(x / 180.0));
+    row[1] = to_bf16((float)(y / 90.0));
+    row[2] = to_bf16(a.phase[2 * rd]);
+    row[3] = to_bf16(a.phase[2 * rd + 1]);
+    const int i0 = nearest_node(a.g.ax, x), j0 = nearest_node(a.g.ay, y);
+    const int nx = a.g.ax.n, ny = a.g.ay.n;
+    int q = 4;
+    for (int dj = -2; dj <= 2; ++dj) {
+        int jj = j0 + dj;
+        jj = jj < 0 ? 0 : (jj > ny - 1 ? ny - 1 : jj);
+        for (int di = -2; di <= 2; ++di) {
+            int ii = i0 + di;
+            ii = ii < 0 ? 0 : (ii > nx - 1 ? nx - 1 : ii);
+            const size_t node = (size_t)jj * nx + ii;
+            float ua, va, ub, vb;
+            node_uv(a.f, e.sa, node, ua, va, a.store);
+            node_uv(a.f, e.sb, node, ub, vb, a.store);
+            const float t = (float)e.tau;
+            row[q++] = to_bf16(ua + t * (ub - ua));
+            row[q++] = to_bf16(va + t * (vb - va));
+        }
+    }
+    for (; q < kIn; ++q)
+        row[q] = 0;
+    if (a.T) {
+        a.T[2 * r] = a.tgt[2 * s];
+        a.T[2 * r + 1] = a.tgt[2 * s + 1];
+    }
+}
+
+// Philox4x32-10 (Salmon et al., SC'11), for seeding and batch sampling
+__device__ inline void philox(uint32_t c[4], uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t lo0 = 0xD2511F53u * c[0], hi0 = __umulhi(0xD2511F53u, c[0]);
+        const uint32_t lo1 = 0xCD9E8D57u * c[2], hi1 = __umulhi(0xCD9E8D57u, c[2]);
+        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+    }
+}
+
+// n start positions uniform inside cells whose four corner nodes are ocean
+__global__ void k_seed(lp::GridDev g, const uint8_t *landnode, int64_t n, uint32_t seed,
+                       uint32_t round, double *x, double *y)
+{
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= n)
+        return;
+    const int nx = g.ax.n, ny = g.ay.n;
+    for (uint32_t attempt = 0; attempt < 256; ++attempt) {
+        uint32_t c[4] = {(uint32_t)p, attempt, round, 0x5EEDu};
+        philox(c, seed, 0xC0FFEEu);
+        const int i = (int)(((uint64_t)c[0] * (uint64_t)(nx - 1)) >> 32);
+        const int j = (int)(((uint64_t)c[1] * (uint64_t)(ny - 1)) >> 32);
+        const size_t n00 = (size_t)j * nx + i;
+        if (landnode && (landnode[n00] || landnode[n00 + 1] || landnode[n00 + nx] ||
+                         landnode[n00 + nx + 1]))
+            continue;
+        const double fx = (double)c[2] * 0x1p-32, fy = (double)c[3] * 0x1p-32;
+        x[p] = g.ax.c[i] + fx * (g.ax.c[i + 1] - g.ax.c[i]);
+        y[p] = g.ay.c[j] + fy * (g.ay.c[j + 1] - g.ay.c[j]);
+        return;
+    }
+    x[p] = g.ax.c[0] - 1.0;  // no ocean cell found: outside, dropped as OOB
+    y[p] = g.ay.c[0];
+}
+
+// Training targets from one round: keep the segments that stayed active, append
+// (x0, y0, round, displacement in metres / kOutScale) to the data set.
+__global__ void k_targets(const double *x0, const double *y0, const double *x1, const double *y1,
+                          const uint8_t *st, int64_t n, int spherical, uint32_t round,
+                          double *dx0, double *dy0, uint32_t *dround, float *dtgt,
+                          unsigned long long *count, int64_t cap)
+{
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const bool keep = p < n && st[p] == 0;
+    const uint64_t mask = __ballot(keep);
+    const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+    unsigned long long base = 0;
+    if (keep && rank == 0)
+        base = atomicAdd(count, (unsigned long long)__popcll(mask));
+    const int src = mask ? __ffsll((unsigned long long)mask) - 1 : 0;
+    base = __shfl(base, src, 64);
+    if (!keep)
+        return;
+    const int64_t o = (int64_t)base + rank;
+    if (o >= cap)
+        return;
+    double ex = x1[p] - x0[p], ey = y1[p] - y0[p];
+    if (spherical) {
+        ex *= lp::kMetresPerDegree * cos(y0[p] * lp::kDegToRad);
+        ey *= lp::kMetresPerDegree;
+    }
+    dx0[o] = x0[p];
+    dy0[o] = y0[p];
+    dround[o] = round;
+    dtgt[2 * o] = (float)(ex / kOutScale);
+    dtgt[2 * o + 1] = (float)(ey / kOutScale);
+}
+
+__global__ void k_sample_batch(uint32_t seed, uint32_t iter, int64_t nsamples, int64_t B,
+                               uint32_t *idx)
+{
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= B)
+        return;
+    uint32_t c[4] = {(uint32_t)r, iter, 0xBA7C4u, 0u};
+    philox(c, seed, 0x5A3Bu);
+    idx[r] = (uint32_t)((((uint64_t)c[0] << 32 | c[1]) % (uint64_t)nsamples));
+}
+
+__device__ inline bool locate_in(const lp::AxisDev &a, double x, int &i)
+{
+    if (!(x >= a.lo && x <= a.hi))
+        return false;
+    int g = a.uniform ? (int)((x - a.lo) * a.ginv) : 0;
+    if (!a.uniform) {
+        int b = (int)((x - a.lo) * a.ginv);
+        b = b < lp::kGuessBins - 1 ? b : lp::kGuessBins - 1;
+        g = a.guess[b];
+    }
+    g = g < 0 ? 0 : (g > a.n - 2 ? a.n - 2 : g);
+    while (g > 0 && a.c[g] > x)
+        --g;
+    while (g < a.n - 2 && a.c[g + 1] <= x)
+        ++g;
+    i = g;
+    return true;
+}
+
+// Residual check: accept the network's displacement where it agrees with the
+// coarse RK4 displacement to within thr metres and ends in an ocean cell inside the
+// grid; otherwise queue the particle for the fine RK4 steps.
+__global__ void k_check(lp::GridDev g, const uint32_t *order, const uint32_t *n_act, double *x,
+                        double *y, const double *xc, const double *yc, const uint8_t *stc,
+                        const float *Y, double thr, uint32_t *fall, uint32_t *nfall,
+                        unsigned long long *accepted)
+{
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    bool back = false, ok = false;
+    uint32_t id = 0;
+    if (k < *n_act) {
+        id = order[k];
+        const double x0 = x[id], y0 = y[id];
+        const double mx = (double)Y[2 * k] * kOutScale, my = (double)Y[2 * k + 1] * kOutScale;
+        double ex = xc[id] - x0, ey = yc[id] - y0, nx1 = x0 + mx, ny1 = y0 + my;
+        if (g.spherical) {
+            const double m = lp::kMetresPerDegree * cos(y0 * lp::kDegToRad);
+            ex *= m;
+            ey *= lp::kMetresPerDegree;
+            nx1 = x0 + mx / m;
+            ny1 = y0 + my / lp::kMetresPerDegree;
+        }
+        const double r = sqrt((mx - ex) * (mx - ex) + (my - ey) * (my - ey));
+        int ci, cj;
+        ok = stc[id] == 0 && r <= thr && locate_in(g.ax, nx1, ci) && locate_in(g.ay, ny1, cj) &&
+             !(g.landcell && g.landcell[(size_t)cj * (g.ax.n - 1) + ci]);
+        if (ok) {
+            x[id] = nx1;
+            y[id] = ny1;
+        } else {
+            back = true;
+        }
+    }
+    const uint64_t mb = __ballot(back);
+    const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(mb >> 32),
+                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)mb, 0u));
+    uint32_t base = 0;
+    if (back && rank == 0)
+        base = atomicAdd(nfall, (uint32_t)__popcll(mb));
+    const int src = mb ? __ffsll((unsigned long long)mb) - 1 : 0;
+    base = __shfl(base, src, 64);
+    if (back)
+        fall[base + rank] = id;
+    const uint64_t ma = __ballot(ok);
+    if ((threadIdx.x & 63) == 0 && ma)
+        atomicAdd(accepted, (unsigned long long)__popcll(ma));
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ model object
+struct lp_model {
+    float *W[kLayers] = {}, *b[kLayers] = {};  // FP32 master [fan_in x pad_out], [pad_out]
+    float *mW[kLayers] = {}, *vW[kLayers] = {}, *mb[kLayers] = {}, *vb[kLayers] = {};
+    float *gW[kLayers] = {}, *gb[kLayers] = {};
+    uint16_t *Wb[kLayers] = {}, *WT[kLayers] = {};  // bf16 [fan_in x pad], [pad x fan_in]
+    int adam_t = 0;
+    // work buffers for `cap` rows
+    int64_t cap = 0;
+    uint16_t *X = nullptr, *H[kLayers - 1] = {}, *dzq[2] = {}, *pad = nullptr;
+    float *Z[kLayers - 1] = {}, *Y = nullptr, *T = nullptr, *dz = nullptr, *dz2 = nullptr;
+    float *loss = nullptr;
+};
+
+namespace {
+
+int model_alloc(lp_model *m)
+{
+    for (int l = 0; l < kLayers; ++l) {
+        const size_t n = (size_t)kFanIn[l] * kPadOut[l], nb = (size_t)kPadOut[l];
+        SCHECK(dmalloc(&m->W[l], n));
+        SCHECK(dmalloc(&m->b[l], nb));
+        SCHECK(dmalloc(&m->mW[l], n));
+        SCHECK(dmalloc(&m->vW[l], n));
+        SCHECK(dmalloc(&m->mb[l], nb));
+        SCHECK(dmalloc(&m->vb[l], nb));
+        SCHECK(dmalloc(&m->gW[l], n));
+        SCHECK(dmalloc(&m->gb[l], nb));
+        SCHECK(dmalloc(&m->Wb[l], n));
+        SCHECK(dmalloc(&m->WT[l], n));
+        SCHECK(hipMemset(m->mW[l], 0, n * 4));
+        SCHECK(hipMemset(m->vW[l], 0, n * 4));
+        SCHECK(hipMemset(m->mb[l], 0, nb * 4));
+        SCHECK(hipMemset(m->vb[l], 0, nb * 4));
+        SCHECK(hipMemset(m->gW[l], 0, n * 4));
+        SCHECK(hipMemset(m->gb[l], 0, nb * 4));
+    }
+    SCHECK(dmalloc(&m->loss, 1));
+    return LP_OK;
+}
+
+void model_free_work(lp_model *m)
+{
+    dfree(m->X);
+    dfree(m->pad);
+    dfree(m->Y);
+    dfree(m->T);
+    dfree(m->dz);
+    dfree(m->dz2);
+    dfree(m->dzq[0]);
+    dfree(m->dzq[1]);
+    for (int l = 0; l < kLayers - 1; ++l) {
+        dfree(m->H[l]);
+        dfree(m->Z[l]);
+    }
+    m->cap = 0;
+}
+
+int model_work(lp_model *m, int64_t rows)
+{
+    if (rows <= m->cap)
+        return LP_OK;
+    model_free_work(m);
+    SCHECK(dmalloc(&m->X, (size_t)rows * kIn));
+    for (int l = 0; l < kLayers - 1; ++l) {
+        SCHECK(dmalloc(&m->H[l], (size_t)rows * kHid));
+        SCHECK(dmalloc(&m->Z[l], (size_t)rows * kHid));
+    }
+    SCHECK(dmalloc(&m->pad, (size_t)rows * kOutPad));
+    SCHECK(dmalloc(&m->dzq[0], (size_t)rows * kHid));
+    SCHECK(dmalloc(&m->dzq[1], (size_t)rows * kHid));
+    SCHECK(dmalloc(&m->Y, (size_t)rows * kOut));
+    SCHECK(dmalloc(&m->T, (size_t)rows * kOut));
+    SCHECK(dmalloc(&m->dz, (size_t)rows * kHid));
+    SCHECK(dmalloc(&m->dz2, (size_t)rows * kOut));
+    m->cap = rows;
+    return LP_OK;
+}
+
+// bf16 copies of the master weights
+int refresh_bf16(lp_model *m, hipStream_t s)
+{
+    for (int l = 0; l < kLayers; ++l)
+        SCHECK(lp::launch_adam(m->W[l], nullptr, nullptr, nullptr, kFanIn[l], kPadOut[l],
+                               kFanOut[l], 0.f, 0.9f, 0.999f, 1e-8f, 1, m->Wb[l], m->WT[l], s));
+    return LP_OK;
+}
+
+// forward over `rows` (multiple of 128) rows of m->X; keeps pre-activations if train
+int forward(lp_model *m, int64_t rows, bool train, hipStream_t s)
+{
+    const uint16_t *in = m->X;
+    for (int l = 0; l < kLayers; ++l) {
+        GemmArgs g{};
+        g.A = in;
+        g.B = m->WT[l];
+        g.M = rows;
+        g.N = kPadOut[l];
+        g.K = kFanIn[l];
+        g.kchunk = g.K;
+        g.sai = kFanIn[l];
+        g.sak = 1;
+        g.sbk = 1;
+        g.sbj = kFanIn[l];
+        g.bias = m->b[l];
+        g.ldc = kPadOut[l];
+        if (l < kLayers - 1) {
+            g.Z = train ? m->Z[l] : nullptr;
+            g.H = m->H[l];
+            SCHECK(lp::launch_gemm(lp::kEpiHidden, g, s));
+            in = m->H[l];
+        } else {
+            g.Y = m->Y;
+            g.ldy = kOut;
+            g.nvalid = kOut;
+            SCHECK(lp::launch_gemm(lp::kEpiOut, g, s));
+        }
+    }
+    return LP_OK;
+}
+
+__global__ void k_pad_out(const float *dz2, int64_t rows, uint16_t *pad)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= rows * kOutPad)
+        return;
+    const int64_t r = i / kOutPad;
+    const int c = (int)(i % kOutPad);
+    pad[i] = c < kOut ? to_bf16(dz2[r * kOut + c]) : (uint16_t)0;
+}
+
+int64_t split_of(int64_t rows)
+{
+    // split the batch dimension of the weight gradients over more blocks
+    int64_t c = rows;
+    while (c > 512 && c % 2 == 0 && (c / 2) % 16 == 0)
+        c /= 2;
+    return c;
+}
+
+// gradients of L = (1/2B) sum (y - t)^2 for the batch in m->X / m->T (after forward)
+int backward(lp_model *m, int64_t rows, hipStream_t s)
+{
+    SCHECK(lp::launch_fill_f32(m->loss, 0.f, 1, s));
+    uint16_t *scratch = m->dzq[0];  // the loss kernel's bf16 output is not used
+    SCHECK(lp::launch_loss_grad(m->Y, m->T, rows, kOut, m->dz2, scratch, m->loss, s));
+    hipLaunchKernelGGL(k_pad_out, dim3((uint32_t)((rows * kOutPad + 255) / 256)), dim3(256), 0,
+                       s, m->dz2, rows, m->pad);
+    SCHECK(hipGetLastError());
+    int cur = 0;
+    for (int l = kLayers - 1; l >= 0; --l) {
+        const int K = kFanIn[l], N = kPadOut[l];
+        const bool out = l == kLayers - 1;
+        const uint16_t *dzq = out ? m->pad : m->dzq[cur];
+        const uint16_t *hin = l == 0 ? m->X : m->H[l - 1];
+        // gW[l] [K x N] = H_in^T dzq
+        SCHECK(lp::launch_fill_f32(m->gW[l], 0.f, (int64_t)K * N, s));
+        GemmArgs gw{};
+        gw.A = hin;
+        gw.B = dzq;
+        gw.M = K;
+        gw.N = N;
+        gw.K = rows;
+        gw.kchunk = split_of(rows);
+        gw.sai = 1;
+        gw.sak = K;
+        gw.sbk = N;
+        gw.sbj = 1;
+        gw.Y = m->gW[l];
+        gw.ldy = N;
+        SCHECK(lp::launch_gemm(lp::kEpiAccum, gw, s));
+        if (out) {
+            SCHECK(lp::launch_colsum(m->dz2, rows, kOut, m->gb[l], s));
+            SCHECK(lp::launch_fill_f32(m->gb[l] + kOut, 0.f, N - kOut, s));
+        } else {
+            SCHECK(lp::launch_colsum(m->dz, rows, N, m->gb[l], s));
+        }
+        if (l > 0) {
+            // dH = dzq W_l^T, then dz = dH * gelu'(z_{l-1}) -> m->dz, bf16 -> other buffer
+            const int nxt = out ? 0 : 1 - cur;
+            GemmArgs g{};
+            g.A = dzq;
+            g.B = m->Wb[l];
+            g.M = rows;
+            g.N = K;
+            g.K = N;
+            g.kchunk = N;
+            g.sai = N;
+            g.sak = 1;
+            g.sbk = 1;
+            g.sbj = N;
+            g.Zin = m->Z[l - 1];
+            g.ldc = K;
+            g.dZ = m->dz;
+            g.H = m->dzq[nxt];
+            SCHECK(lp::launch_gemm(lp::kEpiBackData, g, s));
+            cur = nxt;
+        }
+    }
+    return LP_OK;
+}
+
+int adam(lp_model *m, float lr, hipStream_t s)
+{
+    m->adam_t++;
+    for (int l = 0; l < kLayers; ++l) {
+        SCHECK(lp::launch_adam(m->W[l], m->gW[l], m->mW[l], m->vW[l], kFanIn[l], kPadOut[l],
+                               kFanOut[l], lr, 0.9f, 0.999f, 1e-8f, m->adam_t, m->Wb[l], m->WT[l],
+                               s));
+        SCHECK(lp::launch_adam(m->b[l], m->gb[l], m->mb[l], m->vb[l], 1, kPadOut[l], kFanOut[l],
+                               lr, 0.9f, 0.999f, 1e-8f, m->adam_t, nullptr, nullptr, s));
+    }
+    return LP_OK;
+}
+
+// host fp32 rows [B x 64] -> padded bf16 m->X (and targets [B x 2] -> m->T)
+int upload_batch(lp_model *m, int64_t B, int64_t rows, const float *X, const float *T,
+                 hipStream_t s)
+{
+    float *tmp = nullptr;
+    SCHECK(dmalloc(&tmp, (size_t)rows * kIn));
+    hipError_t e = hipMemset(tmp, 0, (size_t)rows * kIn * 4);
+    if (e == hipSuccess) e = hipMemcpy(tmp, X, (size_t)B * kIn * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = lp::launch_to_bf16(tmp, rows * kIn, m->X, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess && T) {
+        e = hipMemset(m->T, 0, (size_t)rows * kOut * 4);
+        if (e == hipSuccess) e = hipMemcpy(m->T, T, (size_t)B * kOut * 4, hipMemcpyHostToDevice);
+    }
+    dfree(tmp);
+    SCHECK(e);
+    return LP_OK;
+}
+
+int64_t round128(int64_t n) { return (n + 127) / 128 * 128; }
+
+}  // namespace
+
+// ------------------------------------------------------------------ C ABI
+extern "C" int64_t surrogate_param_count(void)
+{
+    int64_t n = 0;
+    for (int l = 0; l < kLayers; ++l)
+        n += (int64_t)kFanIn[l] * kFanOut[l] + kFanOut[l];
+    return n;
+}
+
+extern "C" void surrogate_destroy(lp_model *m)
+{
+    if (!m)
+        return;
+    (void)hipDeviceSynchronize();
+    for (int l = 0; l < kLayers; ++l) {
+        dfree(m->W[l]);
+        dfree(m->b[l]);
+        dfree(m->mW[l]);
+        dfree(m->vW[l]);
+        dfree(m->mb[l]);
+        dfree(m->vb[l]);
+        dfree(m->gW[l]);
+        dfree(m->gb[l]);
+        dfree(m->Wb[l]);
+        dfree(m->WT[l]);
+    }
+    dfree(m->loss);
+    model_free_work(m);
+    delete m;
+}
+
+extern "C" int surrogate_set_params(lp_model *m, const float *params)
+{
+    if (!m || !params) {
+        lp_set_error("null argument");
+        return LP_EINVAL;
+    }
+    const float *p = params;
+    for (int l = 0; l < kLayers; ++l) {
+        std::vector<float> w((size_t)kFanIn[l] * kPadOut[l], 0.f), b((size_t)kPadOut[l], 0.f);
+        for (int k = 0; k < kFanIn[l]; ++k)
+            for (int j = 0; j < kFanOut[l]; ++j)
+                w[(size_t)k * kPadOut[l] + j] = *p++;
+        for (int j = 0; j < kFanOut[l]; ++j)
+            b[j] = *p++;
+        SCHECK(hipMemcpy(m->W[l], w.data(), w.size() * 4, hipMemcpyHostToDevice));
+        SCHECK(hipMemcpy(m->b[l], b.data(), b.size() * 4, hipMemcpyHostToDevice));
+    }
+    int rc = refresh_bf16(m, nullptr);
+    if (rc)
+        return rc;
+    SCHECK(hipDeviceSynchronize());
+    return LP_OK;
+}
+
+static int copy_out(lp_model *m, float *const *W, float *const *b, float *out)
+{
+    (void)m;
+    float *p = out;
+    for (int l = 0; l < kLayers; ++l) {
+        std::vector<float> w((size_t)kFanIn[l] * kPadOut[l]), bb((size_t)kPadOut[l]);
+        SCHECK(hipMemcpy(w.data(), W[l], w.size() * 4, hipMemcpyDeviceToHost));
+        SCHECK(hipMemcpy(bb.data(), b[l], bb.size() * 4, hipMemcpyDeviceToHost));
+        for (int k = 0; k < kFanIn[l]; ++k)
+            for (int j = 0; j < kFanOut[l]; ++j)
+                *p++ = w[(size_t)k * kPadOut[l] + j];
+        for (int j = 0; j < kFanOut[l]; ++j)
+            *p++ = bb[j];
+    }
+    return LP_OK;
+}
+
+extern "C" int surrogate_get_params(lp_model *m, float *params)
+{
+    if (!m || !params) {
+        lp_set_error("null argument");
+        return LP_EINVAL;
+    }
+    SCHECK(hipDeviceSynchronize());
+    return copy_out(m, m->W, m->b, params);
+}
+
+extern "C" int surrogate_create(uint32_t seed, lp_model **out)
+{
+    if (!out) {
+        lp_set_error("null argument");
+        return LP_EINVAL;
+    }
+    *out = nullptr;
+    lp_model *m = new lp_model();
+    int rc = model_alloc(m);
+    if (rc) {
+        surrogate_destroy(m);
+        return rc;
+    }
+    // He-normal initialisation, std sqrt(2 / fan_in), zero biases
+    std::mt19937_64 gen(seed);
+    std::normal_distribution<double> nd(0.0, 1.0);
+    std::vector<float> p((size_t)surrogate_param_count());
+    size_t q = 0;
+    for (int l = 0; l < kLayers; ++l) {
+        const double sd = std::sqrt(2.0 / kFanIn[l]);
+        for (int k = 0; k < kFanIn[l] * kFanOut[l]; ++k)
+            p[q++] = (float)(nd(gen) * sd);
+        for (int j = 0; j < kFanOut[l]; ++j)
+            p[q++] = 0.f;
+    }
+    if ((rc = surrogate_set_params(m, p.data()))) {
+        surrogate_destroy(m);
+        return rc;
+    }
+    *out = m;
+    return LP_OK;
+}
+
+extern "C" int surrogate_forward(lp_model *m, int64_t B, const float *X, float *Y)
+{
+    if (!m || B < 1 || !X || !Y) {
+        lp_set_error("bad arguments");
+        return LP_EINVAL;
+    }
+    const int64_t rows = round128(B);
+    int rc;
+    if ((rc = model_work(m, rows)) || (rc = upload_batch(m, B, rows, X, nullptr, nullptr)) ||
+        (rc = forward(m, rows, false, nullptr)))
+        return rc;
+    SCHECK(hipDeviceSynchronize());
+    SCHECK(hipMemcpy(Y, m->Y, (size_t)B * kOut * 4, hipMemcpyDeviceToHost));
+    return LP_OK;
+}
+
+extern "C" int surrogate_gradients(lp_model *m, int64_t B, const float *X, const float *T,
+                                   float *grads, float *loss)
+{
+    if (!m || B < 1 || B % 128 || !X || !T || !grads) {
+        lp_set_error("bad arguments (B must be a multiple of 128)");
+        return LP_EINVAL;
+    }
+    int rc;
+    if ((rc = model_work(m, B)) || (rc = upload_batch(m, B, B, X, T, nullptr)) ||
+        (rc = forward(m, B, true, nullptr)) || (rc = backward(m, B, nullptr)))
+        return rc;
+    SCHECK(hipDeviceSynchronize());
+    if (loss)
+        SCHECK(hipMemcpy(loss, m->loss, 4, hipMemcpyDeviceToHost));
+    return copy_out(m, m->gW, m->gb, grads);
+}
+
+extern "C" int surrogate_train_step(lp_model *m, int64_t B, const float *X, const float *T,
+                                    double lr, float *loss)
+{
+    if (!m || B < 1 || B % 128 || !X || !T) {
+        lp_set_error("bad arguments (B must be a multiple of 128)");
+        return LP_EINVAL;
+    }
+    int rc;
+    if ((rc = model_work(m, B)) || (rc = upload_batch(m, B, B, X, T, nullptr)) ||
+        (rc = forward(m, B, true, nullptr)) || (rc = backward(m, B, nullptr)) ||
+        (rc = adam(m, (float)lr, nullptr)))
+        return rc;
+    SCHECK(hipDeviceSynchronize());
+    if (loss)
+        SCHECK(hipMemcpy(loss, m->loss, 4, hipMemcpyDeviceToHost));
+    return LP_OK;
+}
