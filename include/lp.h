@@ -234,6 +234,47 @@ int surrogate_train_step(lp_model *m, int64_t B, const float *X, const float *T,
                          float *loss);
 void surrogate_destroy(lp_model *m);
 
+typedef struct {
+    int64_t n_segments;         /* training segments to generate with RK4 */
+    int32_t steps_per_segment;  /* fine RK4 steps per segment (24) */
+    double dt;                  /* fine RK4 step (300 s) */
+    int32_t round_size;         /* segments per generation round; a round starts all
+                                   its particles at one time on the dt grid */
+    int32_t batch;              /* training batch, a multiple of 128 */
+    int64_t iterations;         /* Adam steps */
+    double lr;                  /* initial learning rate, cosine-decayed to lr / 20 */
+    uint32_t seed;
+} lp_surrogate_cfg;
+
+typedef struct {
+    int64_t segments_kept, segments_dropped, iterations;
+    double first_loss, final_loss; /* mean batch loss of the first / last 100 steps */
+    double gen_ms, train_ms;
+} lp_train_stats;
+
+/* Train the network on the field set (2D; all snapshots resident).  Data: segments
+ * of steps_per_segment RK4 steps of dt started uniformly inside cells whose four
+ * corners are ocean, at start times uniform on the dt grid over the snapshot period
+ * (or span); segments that leave the grid or reach land are dropped.  Features are
+ * gathered from the snapshots on the fly; target: the segment displacement in
+ * metres east and north.  Everything runs on the device.  Synchronises. */
+int surrogate_train(lp_fieldset *fs, lp_model *m, const lp_surrogate_cfg *cfg,
+                    lp_train_stats *st, void *stream);
+
+typedef struct {
+    int64_t segments, evaluated, accepted, fallback;
+    double mlp_ms, coarse_ms, fine_ms, total_ms;
+} lp_surrogate_stats;
+
+/* Advance a 2D particle set by runtime in segments of steps_per_segment steps of dt,
+ * taking the network's displacement where it agrees with RK4 over the segment in
+ * two steps to within residual_m metres and ends inside the grid off land, and
+ * re-integrating every other particle with the fine RK4 steps (plain RK4 is the
+ * fallback and the judge).  Synchronises. */
+int pset_execute_surrogate(lp_pset *ps, lp_model *m, double runtime, double dt,
+                           int32_t steps_per_segment, double residual_m,
+                           lp_surrogate_stats *st, void *stream);
+
 const char *lp_last_error(void);
 /* Library version string. */
 const char *lp_version(void);

@@ -29,6 +29,7 @@ EXPORTS = (
     "pset_execute_batch", "pset_autotune_batch",
     "surrogate_param_count", "surrogate_create", "surrogate_get_params", "surrogate_set_params",
     "surrogate_forward", "surrogate_gradients", "surrogate_train_step", "surrogate_destroy",
+    "surrogate_train", "pset_execute_surrogate",
 )
 
 
@@ -55,6 +56,24 @@ class lp_counts(C.Structure):
 class lp_tune(C.Structure):
     _fields_ = [("block", C.c_int32), ("stencil_cache", C.c_int32), ("sort_every", C.c_int32),
                 ("ms", C.c_double)]
+
+
+class lp_surrogate_cfg(C.Structure):
+    _fields_ = [("n_segments", C.c_int64), ("steps_per_segment", C.c_int32), ("dt", C.c_double),
+                ("round_size", C.c_int32), ("batch", C.c_int32), ("iterations", C.c_int64),
+                ("lr", C.c_double), ("seed", C.c_uint32)]
+
+
+class lp_train_stats(C.Structure):
+    _fields_ = [("segments_kept", C.c_int64), ("segments_dropped", C.c_int64),
+                ("iterations", C.c_int64), ("first_loss", C.c_double),
+                ("final_loss", C.c_double), ("gen_ms", C.c_double), ("train_ms", C.c_double)]
+
+
+class lp_surrogate_stats(C.Structure):
+    _fields_ = [("segments", C.c_int64), ("evaluated", C.c_int64), ("accepted", C.c_int64),
+                ("fallback", C.c_int64), ("mlp_ms", C.c_double), ("coarse_ms", C.c_double),
+                ("fine_ms", C.c_double), ("total_ms", C.c_double)]
 
 
 class LPError(RuntimeError):
@@ -96,6 +115,9 @@ def _declare(L):
         "surrogate_gradients": ([P, C.c_int64, P, P, P, P], I),
         "surrogate_train_step": ([P, C.c_int64, P, P, C.c_double, P], I),
         "surrogate_destroy": ([P], None),
+        "surrogate_train": ([P, P, C.POINTER(lp_surrogate_cfg), C.POINTER(lp_train_stats), P], I),
+        "pset_execute_surrogate": ([P, P, C.c_double, C.c_double, C.c_int32, C.c_double,
+                                    C.POINTER(lp_surrogate_stats), P], I),
         "lp_last_error": ([], C.c_char_p),
         "lp_version": ([], C.c_char_p),
     }

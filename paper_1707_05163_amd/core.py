@@ -212,6 +212,15 @@ class ParticleSet:
                                    _ptr(out.get("ck"))))
         return out
 
+    def execute_surrogate(self, model: "Surrogate", runtime: float, dt: float = 300.0,
+                          steps_per_segment: int = 24, residual_m: float = 50.0, stream=None):
+        """Advance with the network where it passes the residual check, RK4 elsewhere."""
+        st = L.lp_surrogate_stats()
+        L.check(L.lib.pset_execute_surrogate(self._h, model.handle, float(runtime), float(dt),
+                                             int(steps_per_segment), float(residual_m),
+                                             C.byref(st), _stream(stream)))
+        return {k: getattr(st, k) for k, _ in L.lp_surrogate_stats._fields_}
+
     def timing(self):
         ms, k = C.c_double(), C.c_int64()
         L.check(L.lib.pset_timing(self._h, C.byref(ms), C.byref(k)))
@@ -310,6 +319,18 @@ class Surrogate:
         L.check(L.lib.surrogate_train_step(self._h, X.shape[0], X.ctypes.data, T.ctypes.data,
                                            float(lr), loss.ctypes.data))
         return float(loss[0])
+
+    def train(self, fieldset: "FieldSet", n_segments: int, iterations: int,
+              steps_per_segment: int = 24, dt: float = 300.0, round_size: int = 100_000,
+              batch: int = 4096, lr: float = 1e-3, seed: int = 1, stream=None):
+        """Generate RK4 segments on the field set and train on them (all on device)."""
+        cfg = L.lp_surrogate_cfg(int(n_segments), int(steps_per_segment), float(dt),
+                                 int(round_size), int(batch), int(iterations), float(lr),
+                                 int(seed) & 0xFFFFFFFF)
+        st = L.lp_train_stats()
+        L.check(L.lib.surrogate_train(fieldset.handle, self._h, C.byref(cfg), C.byref(st),
+                                      _stream(stream)))
+        return {k: getattr(st, k) for k, _ in L.lp_train_stats._fields_}
 
     def close(self):
         if getattr(self, "_h", None):

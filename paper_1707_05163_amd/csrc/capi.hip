@@ -1401,3 +1401,8 @@ int lp_pset_reset_device(lp_pset *ps, int64_t n, const double *x, const double *
 }
 
 void lp_set_error(const char *msg) { g_err = msg; }
+
+int lp_time_entry(const lp_fieldset *fs, double t, lp::TimeEntry *e)
+{
+    return bracket(fs, resident(fs), t, *e);
+}

@@ -78,3 +78,5 @@ struct lp_pset {
 int lp_pset_reset_device(lp_pset *ps, int64_t n, const double *x, const double *y, double t0,
                          hipStream_t stream);
 void lp_set_error(const char *msg);
+// bracketing resident snapshots of time t (LP_ETIME if not covered)
+int lp_time_entry(const lp_fieldset *fs, double t, lp::TimeEntry *e);

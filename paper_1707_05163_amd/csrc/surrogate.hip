@@ -7,7 +7,8 @@
 //
 // Network input (64 values, bf16): lon/180, lat/90, sin and cos of the phase of the
 // periodic field, the 5 x 5 patch of U and V (m/s) around the nearest node,
-// interpolated linearly in time, and 10 zeros.  Output: the segment displacement in
+// interpolated linearly in time, the particle's offset from that node, U and V at the
+// particle and the cell size (see k_features).  Output: the segment displacement in
 // metres (east, north) divided by kOutScale.
 #include <chrono>
 #include <cmath>
@@ -127,6 +128,29 @@ struct FeatArgs {
     float *T;                 // [npad x 2]
 };
 
+__device__ inline int cell_frac(const lp::AxisDev &a, double x, double &f)
+{
+    double xc = x < a.lo ? a.lo : (x > a.hi ? a.hi : x);
+    int g = a.uniform ? (int)((xc - a.lo) * a.ginv) : 0;
+    if (!a.uniform) {
+        int b = (int)((xc - a.lo) * a.ginv);
+        b = b < lp::kGuessBins - 1 ? b : lp::kGuessBins - 1;
+        g = a.guess[b];
+    }
+    g = g < 0 ? 0 : (g > a.n - 2 ? a.n - 2 : g);
+    while (g > 0 && a.c[g] > xc)
+        --g;
+    while (g < a.n - 2 && a.c[g + 1] <= xc)
+        ++g;
+    f = (xc - a.c[g]) * a.rw[g];
+    return g;
+}
+
+// Network input row: [0..3] lon/180, lat/90, sin and cos of the phase; [4..53] the
+// 5 x 5 patch of (U, V) around the nearest node, linear in time; [54..55] the offset
+// of the particle from that node in cell widths; [56..57] U, V interpolated
+// bilinearly at the particle; [58..59] the cell width and height in units of 30 km;
+// [60..63] zero.
 __global__ void k_features(FeatArgs a)
 {
     const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -147,11 +171,14 @@ __global__ void k_features(FeatArgs a)
     const uint32_t rd = a.round ? a.round[s] : 0u;
     const TimeEntry e = a.tab[rd];
     const double x = a.x[s], y = a.y[s];
+    const float t = (float)e.tau;
     row[0] = to_bf16((float)(x / 180.0));
     row[1] = to_bf16((float)(y / 90.0));
     row[2] = to_bf16(a.phase[2 * rd]);
     row[3] = to_bf16(a.phase[2 * rd + 1]);
-    const int i0 = nearest_node(a.g.ax, x), j0 = nearest_node(a.g.ay, y);
+    double fx, fy;
+    const int ci = cell_frac(a.g.ax, x, fx), cj = cell_frac(a.g.ay, y, fy);
+    const int i0 = fx < 0.5 ? ci : ci + 1, j0 = fy < 0.5 ? cj : cj + 1;
     const int nx = a.g.ax.n, ny = a.g.ay.n;
     int q = 4;
     for (int dj = -2; dj <= 2; ++dj) {
@@ -164,12 +191,34 @@ __global__ void k_features(FeatArgs a)
             float ua, va, ub, vb;
             node_uv(a.f, e.sa, node, ua, va, a.store);
             node_uv(a.f, e.sb, node, ub, vb, a.store);
-            const float t = (float)e.tau;
             row[q++] = to_bf16(ua + t * (ub - ua));
             row[q++] = to_bf16(va + t * (vb - va));
         }
     }
-    for (; q < kIn; ++q)
+    row[54] = to_bf16((float)(fx < 0.5 ? fx : fx - 1.0));
+    row[55] = to_bf16((float)(fy < 0.5 ? fy : fy - 1.0));
+    float up = 0.f, vp = 0.f;
+    const float w[4] = {(float)((1 - fx) * (1 - fy)), (float)(fx * (1 - fy)),
+                        (float)((1 - fx) * fy), (float)(fx * fy)};
+    const size_t c00 = (size_t)cj * nx + ci;
+    const size_t cn[4] = {c00, c00 + 1, c00 + nx, c00 + nx + 1};
+    for (int k = 0; k < 4; ++k) {
+        float ua, va, ub, vb;
+        node_uv(a.f, e.sa, cn[k], ua, va, a.store);
+        node_uv(a.f, e.sb, cn[k], ub, vb, a.store);
+        up += w[k] * (ua + t * (ub - ua));
+        vp += w[k] * (va + t * (vb - va));
+    }
+    row[56] = to_bf16(up);
+    row[57] = to_bf16(vp);
+    double hx = a.g.ax.c[ci + 1] - a.g.ax.c[ci], hy = a.g.ay.c[cj + 1] - a.g.ay.c[cj];
+    if (a.g.spherical) {
+        hx *= lp::kMetresPerDegree * cos(y * lp::kDegToRad);
+        hy *= lp::kMetresPerDegree;
+    }
+    row[58] = to_bf16((float)(hx / 30000.0));
+    row[59] = to_bf16((float)(hy / 30000.0));
+    for (q = 60; q < kIn; ++q)
         row[q] = 0;
     if (a.T) {
         a.T[2 * r] = a.tgt[2 * s];
@@ -738,5 +787,370 @@ extern "C" int surrogate_train_step(lp_model *m, int64_t B, const float *X, cons
     SCHECK(hipDeviceSynchronize());
     if (loss)
         SCHECK(hipMemcpy(loss, m->loss, 4, hipMemcpyDeviceToHost));
+    return LP_OK;
+}
+
+// ------------------------------------------------------------------ training
+namespace {
+
+struct Timer {
+    hipEvent_t a = nullptr, b = nullptr;
+    Timer() {
+        (void)hipEventCreate(&a);
+        (void)hipEventCreate(&b);
+    }
+    ~Timer() {
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+    }
+    void start(hipStream_t s) { (void)hipEventRecord(a, s); }
+    double stop_ms(hipStream_t s) {
+        (void)hipEventRecord(b, s);
+        (void)hipEventSynchronize(b);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, a, b);
+        return ms;
+    }
+};
+
+struct DeviceBuf {
+    std::vector<void *> p;
+    ~DeviceBuf() {
+        for (void *q : p)
+            if (q) (void)hipFree(q);
+    }
+    template <class T>
+    hipError_t get(T **out, size_t n) {
+        hipError_t e = dmalloc(out, n);
+        if (e == hipSuccess)
+            p.push_back((void *)*out);
+        return e;
+    }
+};
+
+double field_period(const lp_fieldset *fs, double &t_lo)
+{
+    std::vector<double> t;
+    for (int s = 0; s < fs->capacity; ++s)
+        if (fs->slot_seq[s] >= 0)
+            t.push_back(fs->slot_t[s]);
+    double lo = t.empty() ? 0.0 : t[0], hi = lo;
+    for (double x : t) {
+        lo = std::min(lo, x);
+        hi = std::max(hi, x);
+    }
+    t_lo = lo;
+    return fs->period > 0.0 ? fs->period : hi - lo;
+}
+
+int make_feat(const lp_fieldset *fs, FeatArgs &a)
+{
+    a.g = fs->g;
+    a.f.slots = fs->dslots;
+    a.f.slot_bytes = fs->slot_bytes;
+    a.f.scales = fs->dscales;
+    a.f.nzl = fs->nzl;
+    a.f.steady = fs->npushed == 1;
+    a.store = fs->dtype;
+    return LP_OK;
+}
+
+}  // namespace
+
+extern "C" int surrogate_train(lp_fieldset *fs, lp_model *m, const lp_surrogate_cfg *cfg,
+                               lp_train_stats *st, void *stream_)
+{
+    hipStream_t stream = (hipStream_t)stream_;
+    if (!fs || !m || !cfg || !st || cfg->n_segments < 1 || cfg->steps_per_segment < 1 ||
+        !(cfg->dt > 0.0) || cfg->round_size < 1 || cfg->batch < 128 || cfg->batch % 128 ||
+        cfg->iterations < 1 || !(cfg->lr > 0.0)) {
+        lp_set_error("bad surrogate training arguments");
+        return LP_EINVAL;
+    }
+    if (fs->is3d) {
+        lp_set_error("the surrogate works on 2D field sets");
+        return LP_EINVAL;
+    }
+    *st = lp_train_stats{};
+    double t_lo = 0.0;
+    const double P = field_period(fs, t_lo);
+    const double seg_t = cfg->steps_per_segment * cfg->dt;
+    const int64_t nslots = (int64_t)std::floor((fs->period > 0.0 ? P : P - seg_t) / cfg->dt);
+    if (nslots < 1) {
+        lp_set_error("the resident snapshots do not span one segment");
+        return LP_ETIME;
+    }
+    DeviceBuf mem;
+    const int64_t cap = cfg->n_segments, R = cfg->round_size;
+    double *dx0, *dy0, *sx, *sy;
+    uint32_t *dround, *idx;
+    float *dtgt, *loss_hist;
+    unsigned long long *count;
+    SCHECK(mem.get(&dx0, cap));
+    SCHECK(mem.get(&dy0, cap));
+    SCHECK(mem.get(&dround, cap));
+    SCHECK(mem.get(&dtgt, 2 * cap));
+    SCHECK(mem.get(&sx, R));
+    SCHECK(mem.get(&sy, R));
+    SCHECK(mem.get(&count, 1));
+    SCHECK(mem.get(&idx, (size_t)cfg->batch));
+    SCHECK(mem.get(&loss_hist, (size_t)cfg->iterations));
+    SCHECK(hipMemsetAsync(count, 0, 8, stream));
+    // seeds for the work set (overwritten every round)
+    hipLaunchKernelGGL(k_seed, dim3((uint32_t)((R + 255) / 256)), dim3(256), 0, stream, fs->g,
+                       fs->dlandnode, R, cfg->seed, 0xFFFFFFFFu, sx, sy);
+    SCHECK(hipGetLastError());
+    lp_pset *ps = nullptr;
+    int rc = pset_create_device(fs, R, sx, sy, nullptr, 0.0, 0, stream, &ps);
+    if (rc)
+        return rc;
+    lp_exec_opts o{};
+    o.kernel = LP_KERNEL_RK4;
+    o.recovery = LP_DELETE;
+    o.stencil_cache = 1;
+    std::mt19937_64 gen(cfg->seed);
+    std::vector<TimeEntry> tabs;
+    std::vector<float> phases;
+    Timer tg;
+    tg.start(stream);
+    int64_t kept = 0, generated = 0;
+    uint32_t round = 0;
+    const int64_t max_rounds = 3 * ((cap + R - 1) / R) + 4;
+    while (kept < cap && (int64_t)round < max_rounds) {
+        const int64_t slot = (int64_t)(gen() % (uint64_t)nslots);
+        const double t0 = t_lo + (double)slot * cfg->dt;
+        TimeEntry e{};
+        if ((rc = lp_time_entry(fs, t0, &e))) {
+            pset_destroy(ps);
+            return rc;
+        }
+        const double ph = 2.0 * M_PI * std::fmod(t0 - t_lo, P) / P;
+        tabs.push_back(e);
+        phases.push_back((float)std::sin(ph));
+        phases.push_back((float)std::cos(ph));
+        hipLaunchKernelGGL(k_seed, dim3((uint32_t)((R + 255) / 256)), dim3(256), 0, stream,
+                           fs->g, fs->dlandnode, R, cfg->seed, round, sx, sy);
+        SCHECK(hipGetLastError());
+        if ((rc = lp_pset_reset_device(ps, R, sx, sy, t0, stream)) ||
+            (rc = pset_execute(ps, seg_t, cfg->dt, 0.0, &o, stream))) {
+            pset_destroy(ps);
+            return rc;
+        }
+        hipLaunchKernelGGL(k_targets, dim3((uint32_t)((R + 255) / 256)), dim3(256), 0, stream,
+                           sx, sy, ps->dx, ps->dy, ps->dst, R, fs->g.spherical, round, dx0, dy0,
+                           dround, dtgt, count, cap);
+        SCHECK(hipGetLastError());
+        generated += R;
+        ++round;
+        if (round % 16 == 0 || generated >= cap) {
+            unsigned long long c = 0;
+            SCHECK(hipMemcpyAsync(&c, count, 8, hipMemcpyDeviceToHost, stream));
+            SCHECK(hipStreamSynchronize(stream));
+            kept = (int64_t)std::min<unsigned long long>(c, (unsigned long long)cap);
+        }
+    }
+    pset_destroy(ps);
+    {
+        unsigned long long c = 0;
+        SCHECK(hipMemcpyAsync(&c, count, 8, hipMemcpyDeviceToHost, stream));
+        SCHECK(hipStreamSynchronize(stream));
+        kept = (int64_t)std::min<unsigned long long>(c, (unsigned long long)cap);
+        st->segments_dropped = generated - (int64_t)c;
+    }
+    st->segments_kept = kept;
+    st->gen_ms = tg.stop_ms(stream);
+    if (kept < 1) {
+        lp_set_error("no segment stayed in the ocean");
+        return LP_ESTATE;
+    }
+    TimeEntry *dtab;
+    float *dphase;
+    SCHECK(mem.get(&dtab, tabs.size()));
+    SCHECK(mem.get(&dphase, phases.size()));
+    SCHECK(hipMemcpy(dtab, tabs.data(), tabs.size() * sizeof(TimeEntry), hipMemcpyHostToDevice));
+    SCHECK(hipMemcpy(dphase, phases.data(), phases.size() * 4, hipMemcpyHostToDevice));
+    const int64_t B = cfg->batch;
+    if ((rc = model_work(m, B)))
+        return rc;
+    FeatArgs fa{};
+    make_feat(fs, fa);
+    fa.x = dx0;
+    fa.y = dy0;
+    fa.sel = idx;
+    fa.round = dround;
+    fa.tab = dtab;
+    fa.phase = dphase;
+    fa.n = B;
+    fa.npad = B;
+    fa.X = m->X;
+    fa.tgt = dtgt;
+    fa.T = m->T;
+    Timer tt;
+    tt.start(stream);
+    for (int64_t it = 0; it < cfg->iterations; ++it) {
+        hipLaunchKernelGGL(k_sample_batch, dim3((uint32_t)((B + 255) / 256)), dim3(256), 0,
+                           stream, cfg->seed ^ 0xA5A5A5A5u, (uint32_t)it, kept, B, idx);
+        hipLaunchKernelGGL(k_features, dim3((uint32_t)((B + 127) / 128)), dim3(128), 0, stream,
+                           fa);
+        SCHECK(hipGetLastError());
+        const double frac = (double)it / (double)cfg->iterations;
+        const double lr = cfg->lr * (0.05 + 0.95 * 0.5 * (1.0 + std::cos(M_PI * frac)));
+        if ((rc = forward(m, B, true, stream)) || (rc = backward(m, B, stream)) ||
+            (rc = adam(m, (float)lr, stream)))
+            return rc;
+        SCHECK(hipMemcpyAsync(loss_hist + it, m->loss, 4, hipMemcpyDeviceToDevice, stream));
+    }
+    st->train_ms = tt.stop_ms(stream);
+    std::vector<float> lh((size_t)cfg->iterations);
+    SCHECK(hipMemcpy(lh.data(), loss_hist, lh.size() * 4, hipMemcpyDeviceToHost));
+    const int64_t w = std::min<int64_t>(100, cfg->iterations);
+    double a = 0.0, b = 0.0;
+    for (int64_t k = 0; k < w; ++k) {
+        a += lh[(size_t)k];
+        b += lh[(size_t)(cfg->iterations - 1 - k)];
+    }
+    st->first_loss = a / w;
+    st->final_loss = b / w;
+    st->iterations = cfg->iterations;
+    return LP_OK;
+}
+
+// ------------------------------------------------------------------ inference
+extern "C" int pset_execute_surrogate(lp_pset *ps, lp_model *m, double runtime, double dt,
+                                      int32_t steps_per_segment, double residual_m,
+                                      lp_surrogate_stats *st, void *stream_)
+{
+    hipStream_t stream = (hipStream_t)stream_;
+    if (!ps || !m || !st || !(dt > 0.0) || steps_per_segment < 2 || !(residual_m >= 0.0) ||
+        !(runtime >= 0.0)) {
+        lp_set_error("bad surrogate execute arguments");
+        return LP_EINVAL;
+    }
+    lp_fieldset *fs = ps->fs;
+    if (fs->is3d) {
+        lp_set_error("the surrogate works on 2D field sets");
+        return LP_EINVAL;
+    }
+    const double seg_t = steps_per_segment * dt;
+    const int64_t nseg = (int64_t)std::llround(runtime / seg_t);
+    if (std::fabs((double)nseg * seg_t - runtime) > 1e-9 * std::max(runtime, seg_t)) {
+        lp_set_error("runtime must be a whole number of segments");
+        return LP_EINVAL;
+    }
+    *st = lp_surrogate_stats{};
+    if (ps->dt != 0.0 && ps->dt != dt) {
+        lp_set_error("the particle set already runs with another dt");
+        return LP_EINVAL;
+    }
+    double t_lo = 0.0;
+    const double P = field_period(fs, t_lo);
+    const int64_t n = ps->n, rows = round128(n);
+    DeviceBuf mem;
+    uint32_t *fall, *nfall, *saved_count;
+    unsigned long long *accepted;
+    TimeEntry *dtab;
+    float *dphase;
+    SCHECK(mem.get(&fall, (size_t)n));
+    SCHECK(mem.get(&nfall, 1));
+    SCHECK(mem.get(&saved_count, 1));
+    SCHECK(mem.get(&accepted, 1));
+    SCHECK(mem.get(&dtab, 1));
+    SCHECK(mem.get(&dphase, 2));
+    SCHECK(hipMemsetAsync(accepted, 0, 8, stream));
+    int rc = model_work(m, rows);
+    if (rc)
+        return rc;
+    // coarse-RK4 twin of the set
+    lp_pset *cs = nullptr;
+    if ((rc = pset_create_device(fs, n, ps->dx, ps->dy, nullptr, 0.0, 0, stream, &cs)))
+        return rc;
+    lp_exec_opts o{};
+    o.kernel = LP_KERNEL_RK4;
+    o.recovery = LP_DELETE;
+    o.stencil_cache = 1;
+    o.sort_every = 0;
+    Timer ttot, tm;
+    ttot.start(stream);
+    for (int64_t q = 0; q < nseg && rc == LP_OK; ++q) {
+        const double t = ps->t0 + (double)ps->step * dt;
+        TimeEntry e{};
+        if ((rc = lp_time_entry(fs, t, &e)))
+            break;
+        const double ph = 2.0 * M_PI * std::fmod(t - t_lo, P) / P;
+        const float phs[2] = {(float)std::sin(ph), (float)std::cos(ph)};
+        SCHECK(hipMemcpyAsync(dtab, &e, sizeof e, hipMemcpyHostToDevice, stream));
+        SCHECK(hipMemcpyAsync(dphase, phs, 8, hipMemcpyHostToDevice, stream));
+        const int c0 = ps->cur;
+        // network on every active particle
+        tm.start(stream);
+        FeatArgs fa{};
+        make_feat(fs, fa);
+        fa.x = ps->dx;
+        fa.y = ps->dy;
+        fa.sel = ps->dorder[c0];
+        fa.tab = dtab;
+        fa.phase = dphase;
+        fa.n_dev = ps->dcount + c0;
+        fa.npad = rows;
+        fa.X = m->X;
+        hipLaunchKernelGGL(k_features, dim3((uint32_t)((rows + 127) / 128)), dim3(128), 0,
+                           stream, fa);
+        SCHECK(hipGetLastError());
+        if ((rc = forward(m, rows, false, stream)))
+            break;
+        st->mlp_ms += tm.stop_ms(stream);
+        // coarse RK4: two steps over the segment from the same state
+        tm.start(stream);
+        SCHECK(hipMemcpyAsync(cs->dx, ps->dx, (size_t)n * 8, hipMemcpyDeviceToDevice, stream));
+        SCHECK(hipMemcpyAsync(cs->dy, ps->dy, (size_t)n * 8, hipMemcpyDeviceToDevice, stream));
+        SCHECK(hipMemcpyAsync(cs->dst, ps->dst, (size_t)n, hipMemcpyDeviceToDevice, stream));
+        SCHECK(hipMemcpyAsync(cs->dorder[0], ps->dorder[c0], (size_t)n * 4,
+                              hipMemcpyDeviceToDevice, stream));
+        SCHECK(hipMemcpyAsync(cs->dcount, ps->dcount + c0, 4, hipMemcpyDeviceToDevice, stream));
+        cs->cur = 0;
+        cs->n_launch = ps->n_launch;
+        cs->count_pending = false;
+        cs->t0 = t;
+        cs->dt = 0.0;
+        cs->step = 0;
+        if ((rc = pset_execute(cs, seg_t, seg_t / 2, 0.0, &o, stream)))
+            break;
+        st->coarse_ms += tm.stop_ms(stream);
+        // residual check; the rest goes to the fine RK4 steps
+        tm.start(stream);
+        SCHECK(hipMemsetAsync(nfall, 0, 4, stream));
+        hipLaunchKernelGGL(k_check, dim3((ps->n_launch + 255) / 256), dim3(256), 0, stream,
+                           fs->g, ps->dorder[c0], ps->dcount + c0, ps->dx, ps->dy, cs->dx,
+                           cs->dy, cs->dst, m->Y, residual_m, fall, nfall, accepted);
+        SCHECK(hipGetLastError());
+        uint32_t *full = ps->dorder[c0];
+        SCHECK(hipMemcpyAsync(saved_count, ps->dcount + c0, 4, hipMemcpyDeviceToDevice, stream));
+        SCHECK(hipMemcpyAsync(ps->dcount + c0, nfall, 4, hipMemcpyDeviceToDevice, stream));
+        ps->dorder[c0] = fall;
+        rc = pset_execute(ps, seg_t, dt, 0.0, &o, stream);
+        ps->dorder[c0] = full;
+        ps->count_pending = false;  // its count is the fallback list's, not the set's
+        if (rc)
+            break;
+        // the new active list: every particle of the full list still active
+        SCHECK(lp::launch_compact(full, saved_count, ps->dst, ps->dorder[1 - c0],
+                                  ps->dcount + (1 - c0), ps->n_launch, stream));
+        ps->cur = 1 - c0;
+        uint32_t nf = 0;
+        SCHECK(hipMemcpyAsync(&nf, nfall, 4, hipMemcpyDeviceToHost, stream));
+        st->fine_ms += tm.stop_ms(stream);
+        uint32_t na = 0;
+        SCHECK(hipMemcpy(&na, saved_count, 4, hipMemcpyDeviceToHost));
+        st->evaluated += na;
+        st->fallback += nf;
+        st->segments++;
+    }
+    pset_destroy(cs);
+    if (rc)
+        return rc;
+    st->total_ms = ttot.stop_ms(stream);
+    unsigned long long acc = 0;
+    SCHECK(hipMemcpy(&acc, accepted, 8, hipMemcpyDeviceToHost));
+    st->accepted = (int64_t)acc;
     return LP_OK;
 }
