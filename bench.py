@@ -52,7 +52,11 @@ def parse():
     p.add_argument("--sort-every", type=int, default=1)
     p.add_argument("--cpu-baseline", type=int, default=1)
     p.add_argument("--cpu-sample-stride", type=int, default=100)
-    p.add_argument("--config", default="cfg1", choices=["cfg1", "cfg2", "cfg3"])
+    p.add_argument("--config", default="cfg1", choices=["cfg1", "cfg2", "cfg3", "cfg4"])
+    p.add_argument("--train-segments", type=int, default=50_000_000)
+    p.add_argument("--train-iters", type=int, default=12_000)
+    p.add_argument("--residual-m", default="50",
+                   help="comma-separated residual thresholds in metres (cfg4)")
     p.add_argument("--stencil-cache", type=int, default=1)
     p.add_argument("--calibrate-copy", type=float, default=0.0,
                    help="first copy this many GB device-to-device (a plain copy kernel of "
@@ -291,6 +295,86 @@ def main_cfg3(a):
     print(json.dumps(out), flush=True)
 
 
+def main_cfg4(a):
+    """Learned flow map on the 10-day periodic 0.25 degree field: train on RK4
+    segments, then advance 4M particles for 30 days with the network where it passes
+    the residual check and RK4 elsewhere; compare with fine (300 s) and coarse
+    (3600 s) RK4, and measure every final position against the FP64 oracle."""
+    import torch
+    from paper_1707_05163_amd import FieldSet, ParticleSet, Surrogate
+    from synthetic import configs as SC
+    from oracle import oracle as O
+
+    torch.cuda.set_device(0)
+    n = a.particles if a.particles != 1_000_000 else 4_000_000
+    w = SC.cfg4_surrogate_field(n_particles=n)
+    fs = FieldSet.from_workload(w)
+    lon0 = torch.from_numpy(w.lon0).cuda()
+    lat0 = torch.from_numpy(w.lat0).cuda()
+    stream = torch.cuda.current_stream()
+    runtime = a.days * 86400.0
+    print(f"[bench] cfg4: training on {a.train_segments} segments, {a.train_iters} steps",
+          file=sys.stderr, flush=True)
+    model = Surrogate(seed=1)
+    tr = model.train(fs, n_segments=a.train_segments, iterations=a.train_iters,
+                     round_size=1_000_000, batch=4096, lr=1e-3, stream=stream)
+    print(f"[bench] train: {tr}", file=sys.stderr, flush=True)
+
+    def timed(fn):
+        ps = ParticleSet(fs, lon0, lat0, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        extra = fn(ps)
+        torch.cuda.synchronize()
+        return ps, time.perf_counter() - t0, extra
+
+    fine_ps, fine_s, _ = timed(lambda p: p.execute(runtime, w.dt, stream=stream))
+    coarse_ps, coarse_s, _ = timed(lambda p: p.execute(runtime, 3600.0, stream=stream))
+    thresholds = [float(x) for x in str(a.residual_m).split(",")]
+    surr = []
+    for thr in thresholds:
+        ps_, s_, st_ = timed(lambda p: p.execute_surrogate(model, runtime, dt=w.dt,
+                                                           residual_m=thr, stream=stream))
+        surr.append((thr, ps_, s_, st_))
+        print(f"[bench] residual {thr} m: {s_:.3f} s {st_}", file=sys.stderr, flush=True)
+    print(f"[bench] fine {fine_s:.3f} s, coarse {coarse_s:.3f} s", file=sys.stderr, flush=True)
+    # errors against the FP64 oracle on a subset
+    ids = np.arange(0, n, a.cpu_sample_stride * 4)
+    ofs = O.OracleFieldSet.from_workload(w)
+    st = O.make_state(w.lon0[ids], w.lat0[ids], pid=ids.astype(np.uint32))
+    t0 = time.perf_counter()
+    assert O.advance(ofs, st, w.dt, int(round(runtime / w.dt)), nthreads=O.max_threads()) == 0
+    ot = time.perf_counter() - t0
+    errs = {}
+    runs = [("fine_rk4", fine_ps), ("coarse_rk4", coarse_ps)]
+    runs += [(f"surrogate_{thr:g}m", p) for thr, p, _, _ in surr]
+    for name, ps in runs:
+        g = ps.get()
+        _, stt = ps.status()
+        both = (stt[ids] == 0) & (st.status == 0)
+        km = great_circle_km(g["lon"][ids][both], g["lat"][ids][both], st.x[both], st.y[both])
+        errs[name] = {"median_km": float(np.median(km)), "p95_km": float(np.percentile(km, 95)),
+                      "max_km": float(km.max()), "compared": int(both.sum()),
+                      "status_mismatch": int((stt[ids] != st.status).sum())}
+    steps = n * int(round(runtime / w.dt))
+    out = {
+        "metric": "surrogate speedup over plain FP32-field RK4 at equal particle count",
+        "value": fine_s / surr[0][2], "unit": "x", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16-mfma+f64", "data": "synthetic",
+        "config": {"workload": w.name, "particles": n, "days": a.days, "segment_steps": 24,
+                   "dt_s": w.dt, "residual_m": thresholds},
+        "times_s": dict({"fine_rk4": fine_s, "coarse_rk4": coarse_s},
+                        **{f"surrogate_{thr:g}m": s_ for thr, _, s_, _ in surr}),
+        "fine_rk4_particle_steps_per_s": steps / fine_s,
+        "surrogate_stats": {f"{thr:g}m": st_ for thr, _, _, st_ in surr}, "training": tr,
+        "error_vs_fp64_oracle": errs,
+        "oracle_sample": f"every {a.cpu_sample_stride * 4}th particle ({ids.size}) for "
+                         f"{int(round(runtime / w.dt))} steps in {ot:.1f} s",
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -311,6 +395,8 @@ def main():
         return main_cfg2(a)
     if a.config == "cfg3":
         return main_cfg3(a)
+    if a.config == "cfg4":
+        return main_cfg4(a)
     import torch
     from paper_1707_05163_amd import FieldSet, ParticleSet
     from synthetic import configs as SC
