@@ -67,8 +67,13 @@ extern "C" {
 #define LP_ST_LAND 2u    /* the end point fell in a cell with four land corners */
 #define LP_ST_DELETED 4u /* removed by the DELETE policy */
 
-/* integrators */
-#define LP_KERNEL_RK4 0 /* classical fourth-order Runge-Kutta (Sect. 2.1.1) */
+/* integrators (Sect. 2.1.1) */
+#define LP_KERNEL_RK4 0   /* classical fourth-order Runge-Kutta, the default */
+#define LP_KERNEL_EULER 1 /* Euler forward: one slope per step */
+
+/* spatial interpolation (Sect. 2.3); time is always linear */
+#define LP_INTERP_LINEAR 0  /* bilinear / trilinear */
+#define LP_INTERP_NEAREST 1 /* value of the nearest node (a half-way point goes up) */
 
 /* ------------------------------------------------------------------ FieldSet */
 typedef struct lp_fieldset lp_fieldset;
@@ -129,7 +134,7 @@ int pset_create_device(lp_fieldset *fs, int64_t n, const double *dlon, const dou
                        lp_pset **out);
 
 typedef struct {
-    int32_t kernel;       /* LP_KERNEL_RK4 */
+    int32_t kernel;       /* LP_KERNEL_RK4 or LP_KERNEL_EULER */
     int32_t recovery;     /* LP_DELETE or LP_FREEZE */
     double Kh;            /* > 0: add a Brownian displacement sqrt(2 Kh dt) N(0,1)
                              per horizontal component after each step (Sect. 4.2.7) */
@@ -143,11 +148,14 @@ typedef struct {
                              reloads it only when it changes cell or snapshot pair;
                              0: gather the stencil at every stage (same results up
                              to rounding) */
+    int32_t interp;       /* LP_INTERP_LINEAR or LP_INTERP_NEAREST */
 } lp_exec_opts;
 
-/* Advance every active particle by runtime/dt steps of dt (dt > 0), taking an
- * output record every outputdt (0 = only at the end).  dt must divide runtime
- * and outputdt.  The first execute of a set also records the start time.
+/* Advance every active particle by runtime/|dt| steps of dt, taking an output
+ * record every outputdt (0 = only at the end).  |dt| must divide runtime and
+ * outputdt (both >= 0).  A negative dt runs backward in time (the time-backward
+ * mode of Sect. 2.2); time is t0 + step * dt, re-based when dt changes so that
+ * the current time is kept.  The first execute of a set also records the start.
  * Asynchronous on `stream`; returns LP_ETIME before launching anything if a
  * stage time is not covered by the resident snapshots. */
 int pset_execute(lp_pset *ps, double runtime, double dt, double outputdt,

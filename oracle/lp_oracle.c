@@ -59,6 +59,8 @@ typedef struct {
     int policy;              /* 0: delete on error, 1: freeze on error */
     double Kh;               /* horizontal diffusivity, 0 = no Brownian term */
     uint32_t run_id, seed;   /* Philox key */
+    int scheme;              /* 0: classical RK4, 1: Euler forward (Sect. 2.1.1) */
+    int nearest;             /* 1: nearest-neighbour instead of linear in space (Sect. 2.3) */
 } or_options;
 
 /* ---------------------------------------------------------------- cell search */
@@ -167,8 +169,12 @@ int or_time_bracket(const or_fieldset *fs, double t, int *s0, int *s1, double *t
 
 /* ---------------------------------------------------------------- sampling */
 /* Velocity at (x, y, z, t) in coordinate units per second.  Returns 1 if the
- * point is outside the grid (the caller has checked t). */
-int or_sample(const or_fieldset *fs, double x, double y, double z, double t, double out[3])
+ * point is outside the grid (the caller has checked t).  Nearest-neighbour
+ * sampling snaps each cell fraction to its nearer node (a fraction of exactly 0.5
+ * to the upper one), which turns the linear weights into one unit weight; time
+ * stays linear. */
+static int sample_mode(const or_fieldset *fs, double x, double y, double z, double t,
+                       double out[3], int nearest)
 {
     or_cell c = {0, 0, 0, 0.0, 0.0, 0.0};
     if (or_locate(x, fs->X, fs->nx, &c.i, &c.xi))
@@ -177,6 +183,11 @@ int or_sample(const or_fieldset *fs, double x, double y, double z, double t, dou
         return 1;
     if (fs->nz > 0 && or_locate(z, fs->Z, fs->nz, &c.k, &c.zeta))
         return 1;
+    if (nearest) {
+        c.xi = c.xi < 0.5 ? 0.0 : 1.0;
+        c.eta = c.eta < 0.5 ? 0.0 : 1.0;
+        c.zeta = c.zeta < 0.5 ? 0.0 : 1.0;
+    }
     int s0, s1;
     double tau;
     if (or_time_bracket(fs, t, &s0, &s1, &tau) != OR_OK)
@@ -202,6 +213,17 @@ int or_sample(const or_fieldset *fs, double x, double y, double z, double t, dou
     }
     out[2] = w;
     return 0;
+}
+
+int or_sample(const or_fieldset *fs, double x, double y, double z, double t, double out[3])
+{
+    return sample_mode(fs, x, y, z, t, out, 0);
+}
+
+int or_sample_nearest(const or_fieldset *fs, double x, double y, double z, double t,
+                      double out[3])
+{
+    return sample_mode(fs, x, y, z, t, out, 1);
 }
 
 /* ---------------------------------------------------------------- Philox4x32-10 */
@@ -291,21 +313,29 @@ static void rk4_step(const or_fieldset *fs, const or_options *opt, double t_org,
     double x = *px, y = *py, z = is3d ? *pz : 0.0;
     double hd = 0.5 * dt;
     double k1[3], k2[3], k3[3], k4[3];
+    double xs, ys, zs;
+    const int nn = opt->nearest;
 
-    if (or_sample(fs, x, y, z, tn, k1))
+    if (sample_mode(fs, x, y, z, tn, k1, nn))
         goto out_of_bounds;
-    double x2 = x + k1[0] * hd, y2 = y + k1[1] * hd, z2 = z + k1[2] * hd;
-    if (or_sample(fs, x2, y2, z2, th, k2))
-        goto out_of_bounds;
-    double x3 = x + k2[0] * hd, y3 = y + k2[1] * hd, z3 = z + k2[2] * hd;
-    if (or_sample(fs, x3, y3, z3, th, k3))
-        goto out_of_bounds;
-    double x4 = x + k3[0] * dt, y4 = y + k3[1] * dt, z4 = z + k3[2] * dt;
-    if (or_sample(fs, x4, y4, z4, te, k4))
-        goto out_of_bounds;
-    double xs = x + ((((k1[0] + 2.0 * k2[0]) + 2.0 * k3[0]) + k4[0]) * dt) / 6.0;
-    double ys = y + ((((k1[1] + 2.0 * k2[1]) + 2.0 * k3[1]) + k4[1]) * dt) / 6.0;
-    double zs = z + ((((k1[2] + 2.0 * k2[2]) + 2.0 * k3[2]) + k4[2]) * dt) / 6.0;
+    if (opt->scheme == 1) { /* Euler forward: one slope at the start of the step */
+        xs = x + k1[0] * dt;
+        ys = y + k1[1] * dt;
+        zs = z + k1[2] * dt;
+    } else {
+        double x2 = x + k1[0] * hd, y2 = y + k1[1] * hd, z2 = z + k1[2] * hd;
+        if (sample_mode(fs, x2, y2, z2, th, k2, nn))
+            goto out_of_bounds;
+        double x3 = x + k2[0] * hd, y3 = y + k2[1] * hd, z3 = z + k2[2] * hd;
+        if (sample_mode(fs, x3, y3, z3, th, k3, nn))
+            goto out_of_bounds;
+        double x4 = x + k3[0] * dt, y4 = y + k3[1] * dt, z4 = z + k3[2] * dt;
+        if (sample_mode(fs, x4, y4, z4, te, k4, nn))
+            goto out_of_bounds;
+        xs = x + ((((k1[0] + 2.0 * k2[0]) + 2.0 * k3[0]) + k4[0]) * dt) / 6.0;
+        ys = y + ((((k1[1] + 2.0 * k2[1]) + 2.0 * k3[1]) + k4[1]) * dt) / 6.0;
+        zs = z + ((((k1[2] + 2.0 * k2[2]) + 2.0 * k3[2]) + k4[2]) * dt) / 6.0;
+    }
 
     if (opt->Kh > 0.0) {
         double nn[2];

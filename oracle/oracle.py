@@ -54,7 +54,12 @@ class _FS(C.Structure):
 
 class _OPT(C.Structure):
     _fields_ = [("policy", C.c_int), ("Kh", C.c_double),
-                ("run_id", C.c_uint32), ("seed", C.c_uint32)]
+                ("run_id", C.c_uint32), ("seed", C.c_uint32),
+                ("scheme", C.c_int), ("nearest", C.c_int)]
+
+
+SCHEME_RK4 = 0
+SCHEME_EULER = 1
 
 
 _lib = None
@@ -71,6 +76,8 @@ def lib():
         L.or_locate.restype = C.c_int
         L.or_sample.argtypes = [C.POINTER(_FS), C.c_double, C.c_double, C.c_double, C.c_double, P]
         L.or_sample.restype = C.c_int
+        L.or_sample_nearest.argtypes = L.or_sample.argtypes
+        L.or_sample_nearest.restype = C.c_int
         L.or_time_bracket.argtypes = [C.POINTER(_FS), C.c_double, C.POINTER(C.c_int),
                                       C.POINTER(C.c_int), C.POINTER(C.c_double)]
         L.or_time_bracket.restype = C.c_int
@@ -131,9 +138,10 @@ class OracleFieldSet:
                    spherical=w.grid.spherical, period=w.fields.period, land=w.grid.land)
 
     # -- single-point primitives used by the pins
-    def sample(self, x, y, z, t):
+    def sample(self, x, y, z, t, nearest=False):
         out = np.zeros(3)
-        rc = lib().or_sample(C.byref(self.s), x, y, z, t, out.ctypes.data)
+        f = lib().or_sample_nearest if nearest else lib().or_sample
+        rc = f(C.byref(self.s), x, y, z, t, out.ctypes.data)
         return rc, out
 
     def time_bracket(self, t):
@@ -185,6 +193,7 @@ class State:
     t_org: float
     step: int
     psteps: int = 0
+    dt: Optional[float] = None  # dt of the previous advance (time origin bookkeeping)
 
 
 def make_state(x, y, z=None, pid=None, t_org=0.0, step=0) -> State:
@@ -197,12 +206,17 @@ def make_state(x, y, z=None, pid=None, t_org=0.0, step=0) -> State:
 
 def advance(fs: OracleFieldSet, st: State, dt: float, nsteps: int, Kh: float = 0.0,
             run_id: int = 0, seed: int = SEED, policy: int = POLICY_DELETE,
-            nthreads: int = 0) -> int:
-    """Advance ``st`` in place by ``nsteps`` steps of ``dt``; returns the oracle's
-    return code (0, or -4 if a needed time lies outside the snapshots)."""
+            nthreads: int = 0, scheme: int = SCHEME_RK4, nearest: bool = False) -> int:
+    """Advance ``st`` in place by ``nsteps`` steps of ``dt`` (negative dt runs
+    backward in time); returns the oracle's return code (0, or -4 if a needed time
+    lies outside the snapshots)."""
     if fs.is3d and st.z is None:
         raise ValueError("3D field set needs depths")
-    opt = _OPT(int(policy), float(Kh), int(run_id) & 0xFFFFFFFF, int(seed) & 0xFFFFFFFF)
+    opt = _OPT(int(policy), float(Kh), int(run_id) & 0xFFFFFFFF, int(seed) & 0xFFFFFFFF,
+               int(scheme), int(bool(nearest)))
+    # time is t_org + step * dt; a change of dt keeps the current time
+    if st.dt is not None and dt != st.dt:
+        st.t_org = (st.t_org + st.step * st.dt) - st.step * dt
     ps = C.c_int64(0)
     rc = lib().or_advance(C.byref(fs.s), st.x.size, _ptr(st.x), _ptr(st.y),
                           _ptr(st.z if fs.is3d else None), _ptr(st.status), _ptr(st.pid),
@@ -211,6 +225,7 @@ def advance(fs: OracleFieldSet, st: State, dt: float, nsteps: int, Kh: float = 0
     if rc == 0:
         st.step += int(nsteps)
         st.psteps += ps.value
+        st.dt = float(dt)
     return rc
 
 
@@ -225,18 +240,22 @@ def record(fs: OracleFieldSet, st: State) -> dict:
 
 def run(fs: OracleFieldSet, st: State, dt: float, runtime: float, outputdt: float,
         Kh: float = 0.0, run_id: int = 0, policy: int = POLICY_DELETE,
-        nthreads: int = 0, first_record: bool = True):
+        nthreads: int = 0, first_record: bool = True, scheme: int = SCHEME_RK4,
+        nearest: bool = False):
     """Execute for ``runtime`` with records every ``outputdt``; returns the list of
-    records (the first taken at the start time when ``first_record``)."""
-    nsteps = int(round(runtime / dt))
-    per = int(round(outputdt / dt)) if outputdt > 0 else nsteps
-    if nsteps * dt != runtime or (outputdt > 0 and per * dt != outputdt):
+    records (the first taken at the start time when ``first_record``).  A negative
+    dt runs backward in time (runtime and outputdt stay positive)."""
+    adt = abs(dt)
+    nsteps = int(round(runtime / adt))
+    per = int(round(outputdt / adt)) if outputdt > 0 else nsteps
+    if nsteps * adt != runtime or (outputdt > 0 and per * adt != outputdt):
         raise ValueError("dt must divide runtime and outputdt")
     recs = [record(fs, st)] if first_record else []
     done = 0
     while done < nsteps:
         k = min(per, nsteps - done)
-        rc = advance(fs, st, dt, k, Kh=Kh, run_id=run_id, policy=policy, nthreads=nthreads)
+        rc = advance(fs, st, dt, k, Kh=Kh, run_id=run_id, policy=policy, nthreads=nthreads,
+                     scheme=scheme, nearest=nearest)
         if rc != 0:
             raise RuntimeError(f"oracle advance failed: {rc}")
         done += k

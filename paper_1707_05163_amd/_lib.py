@@ -18,6 +18,8 @@ LP_F64, LP_F32, LP_BF16, LP_F16_SCALED = 0, 1, 2, 3
 LP_DELETE, LP_FREEZE = 0, 1
 LP_ST_OOB, LP_ST_LAND, LP_ST_DELETED = 1, 2, 4
 LP_KERNEL_RK4 = 0
+LP_KERNEL_EULER = 1
+LP_INTERP_LINEAR, LP_INTERP_NEAREST = 0, 1
 
 # every function declared in include/lp.h
 EXPORTS = (
@@ -44,7 +46,7 @@ class lp_exec_opts(C.Structure):
     _fields_ = [("kernel", C.c_int32), ("recovery", C.c_int32), ("Kh", C.c_double),
                 ("run_id", C.c_uint32), ("seed", C.c_uint32), ("output_stride", C.c_int32),
                 ("sort_every", C.c_int32), ("profile", C.c_int32),
-                ("stencil_cache", C.c_int32)]
+                ("stencil_cache", C.c_int32), ("interp", C.c_int32)]
 
 
 class lp_counts(C.Structure):

@@ -16,6 +16,8 @@ SEED = 0x17070516
 _DTYPES = {"f64": L.LP_F64, "f32": L.LP_F32, "bf16": L.LP_BF16, "f16s": L.LP_F16_SCALED}
 _MESH = {"flat": L.LP_MESH_FLAT, "spherical": L.LP_MESH_SPHERICAL}
 _RECOVERY = {"delete": L.LP_DELETE, "freeze": L.LP_FREEZE}
+_KERNEL = {"rk4": L.LP_KERNEL_RK4, "euler": L.LP_KERNEL_EULER}
+_INTERP = {"linear": L.LP_INTERP_LINEAR, "nearest": L.LP_INTERP_NEAREST}
 
 
 def _is_torch(a) -> bool:
@@ -163,17 +165,19 @@ class ParticleSet:
     @staticmethod
     def opts(recovery: str = "delete", Kh: float = 0.0, run_id: int = 0, seed: int = SEED,
              output_stride: int = 0, sort_every: int = 1, profile: bool = False,
-             stencil_cache: bool = True):
-        return L.lp_exec_opts(L.LP_KERNEL_RK4, _RECOVERY[recovery], float(Kh), int(run_id),
+             stencil_cache: bool = True, kernel: str = "rk4", interp: str = "linear"):
+        return L.lp_exec_opts(_KERNEL[kernel], _RECOVERY[recovery], float(Kh), int(run_id),
                               int(seed) & 0xFFFFFFFF, int(output_stride), int(sort_every),
-                              int(bool(profile)), int(bool(stencil_cache)))
+                              int(bool(profile)), int(bool(stencil_cache)), _INTERP[interp])
 
     def execute(self, runtime: float, dt: float, outputdt: float = 0.0,
                 recovery: str = "delete", Kh: float = 0.0, run_id: int = 0, seed: int = SEED,
                 output_stride: int = 0, sort_every: int = 1, profile: bool = False,
-                stencil_cache: bool = True, stream=None):
+                stencil_cache: bool = True, kernel: str = "rk4", interp: str = "linear",
+                stream=None):
+        """The update loop: runtime/|dt| steps of dt (negative dt runs backward)."""
         o = self.opts(recovery, Kh, run_id, seed, output_stride, sort_every, profile,
-                      stencil_cache)
+                      stencil_cache, kernel, interp)
         L.check(L.lib.pset_execute(self._h, float(runtime), float(dt), float(outputdt),
                                    C.byref(o), _stream(stream)))
 

@@ -179,6 +179,11 @@ __device__ inline bool sample(const AdvectParams &P, const TimeEntry &te, double
         if (!locate(P.g.az, z, c.k, c.zeta))
             return false;
     }
+    if (P.nearest) {
+        c.xi = c.xi < 0.5 ? 0.0 : 1.0;
+        c.eta = c.eta < 0.5 ? 0.0 : 1.0;
+        c.zeta = c.zeta < 0.5 ? 0.0 : 1.0;
+    }
     R v[3];
     if constexpr (STEADY) {
         spatial<ST, IS3D>(P, te.sa, c, v);
@@ -245,17 +250,27 @@ __device__ inline uint8_t rk4_step(const AdvectParams &P, int s, uint32_t id, do
     double k1[3], k2[3], k3[3], k4[3];
     if (!sample<ST, IS3D, STEADY>(P, e0, x, y, z, k1))
         return ST_OOB;
-    if (!sample<ST, IS3D, STEADY>(P, e1, x + k1[0] * hd, y + k1[1] * hd, z + k1[2] * hd, k2))
-        return ST_OOB;
-    if (!sample<ST, IS3D, STEADY>(P, e1, x + k2[0] * hd, y + k2[1] * hd, z + k2[2] * hd, k3))
-        return ST_OOB;
-    if (!sample<ST, IS3D, STEADY>(P, e2, x + k3[0] * dt, y + k3[1] * dt, z + k3[2] * dt, k4))
-        return ST_OOB;
-    double xs = x + ((((k1[0] + 2.0 * k2[0]) + 2.0 * k3[0]) + k4[0]) * dt) / 6.0;
-    double ys = y + ((((k1[1] + 2.0 * k2[1]) + 2.0 * k3[1]) + k4[1]) * dt) / 6.0;
-    double zs = z;
-    if constexpr (IS3D)
-        zs = z + ((((k1[2] + 2.0 * k2[2]) + 2.0 * k3[2]) + k4[2]) * dt) / 6.0;
+    double xs, ys, zs = z;
+    if (P.scheme) {  // Euler forward
+        xs = x + k1[0] * dt;
+        ys = y + k1[1] * dt;
+        if constexpr (IS3D)
+            zs = z + k1[2] * dt;
+    } else {
+        if (!sample<ST, IS3D, STEADY>(P, e1, x + k1[0] * hd, y + k1[1] * hd, z + k1[2] * hd,
+                                      k2))
+            return ST_OOB;
+        if (!sample<ST, IS3D, STEADY>(P, e1, x + k2[0] * hd, y + k2[1] * hd, z + k2[2] * hd,
+                                      k3))
+            return ST_OOB;
+        if (!sample<ST, IS3D, STEADY>(P, e2, x + k3[0] * dt, y + k3[1] * dt, z + k3[2] * dt,
+                                      k4))
+            return ST_OOB;
+        xs = x + ((((k1[0] + 2.0 * k2[0]) + 2.0 * k3[0]) + k4[0]) * dt) / 6.0;
+        ys = y + ((((k1[1] + 2.0 * k2[1]) + 2.0 * k3[1]) + k4[1]) * dt) / 6.0;
+        if constexpr (IS3D)
+            zs = z + ((((k1[2] + 2.0 * k2[2]) + 2.0 * k3[2]) + k4[2]) * dt) / 6.0;
+    }
     if (P.Kh > 0.0) {
         uint32_t c[4] = {id, (uint32_t)(P.step0 + s), 0u, 0u};
         philox4x32_10(c, P.run_id, P.seed);
@@ -454,7 +469,11 @@ __device__ inline bool stage2(const AdvectParams &P, Cell2<typename Real<ST>::T>
         if (!reload2<ST, STEADY>(P, c, e.sa, e.sb, x, y))
             return false;
     }
-    const R xi = (R)((x - c.x0) * c.rx), eta = (R)((y - c.y0) * c.ry);
+    R xi = (R)((x - c.x0) * c.rx), eta = (R)((y - c.y0) * c.ry);
+    if (P.nearest) {
+        xi = xi < (R)0.5 ? (R)0 : (R)1;
+        eta = eta < (R)0.5 ? (R)0 : (R)1;
+    }
     R u = poly<R>(c.a[0], xi, eta), v = poly<R>(c.a[1], xi, eta);
     if constexpr (!STEADY) {
         const R tau = (R)e.tau;
@@ -494,8 +513,9 @@ __device__ inline long long advect_lane_2d(const AdvectParams &P, uint32_t k, ui
                 // the four stages: offsets 0, dt/2, dt/2, dt from X_n along the previous
                 // slope; weights 1, 2, 2, 1
                 double kx = 0.0, ky = 0.0, sx = 0.0, sy = 0.0;
+                const int nst = P.scheme ? 1 : 4;
 #pragma nounroll
-                for (int q = 0; q < 4; ++q) {
+                for (int q = 0; q < nst; ++q) {
                     const TimeEntry e = q == 0 ? e0 : (q == 3 ? e2 : e1);
                     const double h = q == 0 ? 0.0 : (q == 3 ? dt : hd);
                     if (e.sa != csa || e.sb != csb) {
@@ -514,8 +534,14 @@ __device__ inline long long advect_lane_2d(const AdvectParams &P, uint32_t k, ui
                     }
                 }
                 {
-                    double xs = x + (sx + kx) * dt6;
-                    double ys = y + (sy + ky) * dt6;
+                    double xs, ys;
+                    if (P.scheme) {  // Euler forward
+                        xs = x + kx * dt;
+                        ys = y + ky * dt;
+                    } else {
+                        xs = x + (sx + kx) * dt6;
+                        ys = y + (sy + ky) * dt6;
+                    }
                     if (P.Kh > 0.0) {
                         uint32_t w[4] = {id, (uint32_t)(P.step0 + s), 0u, 0u};
                         philox4x32_10(w, P.run_id, P.seed);
@@ -757,8 +783,13 @@ __device__ inline bool stage3(const AdvectParams &P, Cell3<typename Real<ST>::T>
         if (!reload3<ST, STEADY>(P, c, e.sa, e.sb, x, y, z))
             return false;
     }
-    const R xi = (R)((x - c.x0) * c.rx), eta = (R)((y - c.y0) * c.ry);
-    const R zeta = (R)((z - c.z0) * c.rz);
+    R xi = (R)((x - c.x0) * c.rx), eta = (R)((y - c.y0) * c.ry);
+    R zeta = (R)((z - c.z0) * c.rz);
+    if (P.nearest) {
+        xi = xi < (R)0.5 ? (R)0 : (R)1;
+        eta = eta < (R)0.5 ? (R)0 : (R)1;
+        zeta = zeta < (R)0.5 ? (R)0 : (R)1;
+    }
     R v[3];
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
@@ -811,8 +842,9 @@ __global__ __launch_bounds__(kBlock) void k_advect3d(AdvectParams P)
                 const TimeEntry e0 = P.tab[2 * s], e1 = P.tab[2 * s + 1], e2 = P.tab[2 * s + 2];
                 uint8_t err = ST_OOB;
                 double k[3] = {0.0, 0.0, 0.0}, sm[3] = {0.0, 0.0, 0.0};
+                const int nst = P.scheme ? 1 : 4;
 #pragma nounroll
-                for (int q = 0; q < 4; ++q) {
+                for (int q = 0; q < nst; ++q) {
                     const TimeEntry e = q == 0 ? e0 : (q == 3 ? e2 : e1);
                     const double h = q == 0 ? 0.0 : (q == 3 ? dt : hd);
                     if (e.sa != csa || e.sb != csb) {
@@ -828,9 +860,16 @@ __global__ __launch_bounds__(kBlock) void k_advect3d(AdvectParams P)
                         sm[v] = q == 0 ? k[v] : (q == 3 ? sm[v] : fma(2.0, k[v], sm[v]));
                 }
                 {
-                    double xs = x + (sm[0] + k[0]) * dt6;
-                    double ys = y + (sm[1] + k[1]) * dt6;
-                    const double zs = z + (sm[2] + k[2]) * dt6;
+                    double xs, ys, zs;
+                    if (P.scheme) {  // Euler forward
+                        xs = x + k[0] * dt;
+                        ys = y + k[1] * dt;
+                        zs = z + k[2] * dt;
+                    } else {
+                        xs = x + (sm[0] + k[0]) * dt6;
+                        ys = y + (sm[1] + k[1]) * dt6;
+                        zs = z + (sm[2] + k[2]) * dt6;
+                    }
                     if (P.Kh > 0.0) {
                         uint32_t w[4] = {id, (uint32_t)(P.step0 + s), 0u, 0u};
                         philox4x32_10(w, P.run_id, P.seed);

@@ -702,23 +702,26 @@ int exec_prepare(lp_pset *ps, double runtime, double dt, double outputdt, const 
     if (!ps || !o)
         return fail(LP_EINVAL, "null argument");
     lp_fieldset *fs = ps->fs;
-    if (o->kernel != LP_KERNEL_RK4)
+    if (o->kernel != LP_KERNEL_RK4 && o->kernel != LP_KERNEL_EULER)
         return fail(LP_EINVAL, "unknown kernel %d", o->kernel);
+    if (o->interp != LP_INTERP_LINEAR && o->interp != LP_INTERP_NEAREST)
+        return fail(LP_EINVAL, "unknown interpolation %d", o->interp);
     if (o->recovery != LP_DELETE && o->recovery != LP_FREEZE)
         return fail(LP_EINVAL, "unknown recovery policy %d", o->recovery);
-    if (!(dt > 0.0) || !std::isfinite(dt))
-        return fail(LP_EINVAL, "dt must be positive and finite");
+    if (dt == 0.0 || !std::isfinite(dt))
+        return fail(LP_EINVAL, "dt must be nonzero and finite");
+    const double adt = std::fabs(dt);
     if (!(runtime >= 0.0) || !std::isfinite(runtime) || !(outputdt >= 0.0))
         return fail(LP_EINVAL, "runtime and outputdt must be >= 0");
     if (!(o->Kh >= 0.0) || o->output_stride < 0 || o->sort_every < 0)
         return fail(LP_EINVAL, "bad options");
-    const int64_t nsteps = (int64_t)std::llround(runtime / dt);
-    if (std::fabs((double)nsteps * dt - runtime) > 1e-9 * std::max(runtime, dt))
+    const int64_t nsteps = (int64_t)std::llround(runtime / adt);
+    if (std::fabs((double)nsteps * adt - runtime) > 1e-9 * std::max(runtime, adt))
         return fail(LP_EINVAL, "dt %g does not divide runtime %g", dt, runtime);
     int64_t per = nsteps;
     if (outputdt > 0.0) {
-        per = (int64_t)std::llround(outputdt / dt);
-        if (per < 1 || std::fabs((double)per * dt - outputdt) > 1e-9 * std::max(outputdt, dt))
+        per = (int64_t)std::llround(outputdt / adt);
+        if (per < 1 || std::fabs((double)per * adt - outputdt) > 1e-9 * std::max(outputdt, adt))
             return fail(LP_EINVAL, "dt %g does not divide outputdt %g", dt, outputdt);
     }
     if (nsteps > 0x3FFFFFFF || per > 0x3FFFFFFF)
@@ -809,6 +812,8 @@ int exec_prepare(lp_pset *ps, double runtime, double dt, double outputdt, const 
     P.dt = dt;
     P.policy = o->recovery == LP_DELETE ? 0 : 1;
     P.cache = o->stencil_cache ? 1 : 0;
+    P.scheme = o->kernel == LP_KERNEL_EULER ? 1 : 0;
+    P.nearest = o->interp == LP_INTERP_NEAREST ? 1 : 0;
     P.Kh = o->Kh;
     P.run_id = o->run_id;
     P.seed = o->seed;

@@ -58,6 +58,8 @@ struct AdvectParams {
     int32_t nsteps;
     int32_t policy;          // 0 delete, 1 freeze
     int32_t cache;           // 1: register stencil cache kernels
+    int32_t scheme;          // 0 RK4, 1 Euler forward
+    int32_t nearest;         // 1: nearest-neighbour in space
     double Kh;
     uint32_t run_id, seed;
     double *x, *y, *z;       // particle state, id order

@@ -458,3 +458,85 @@ def test_normals_are_standard():
     assert abs(n.mean()) < 0.03
     assert abs(n.var() - 1) < 0.03
     assert np.corrcoef(n[:, 0], n[:, 1])[0, 1] < 0.03
+
+
+# ------------------------------------------------------------------ f3 / f4 schemes
+def _decimal_pow(re, im, z0, n):
+    pr, pi_ = Decimal(1), Decimal(0)
+    br, bi = re, im
+    k = n
+    while k:
+        if k & 1:
+            pr, pi_ = pr * br - pi_ * bi, pr * bi + pi_ * br
+        br, bi = br * br - bi * bi, 2 * br * bi
+        k >>= 1
+    zr, zi = Decimal(float(z0.real)), Decimal(float(z0.imag))
+    return complex(float(zr * pr - zi * pi_), float(zr * pi_ + zi * pr))
+
+
+def test_euler_forward_closed_form():
+    """Euler on the linear rotation field: Z_n - c = (1 + i theta)^n (Z_0 - c)."""
+    w = SC.cfg0_solid_body(n_particles=300, nsteps=500)
+    fs = O.OracleFieldSet.from_workload(w)
+    st = O.make_state(w.lon0, w.lat0)
+    assert O.advance(fs, st, w.dt, w.nsteps, scheme=O.SCHEME_EULER) == 0
+    th = Decimal(w.meta["omega"]) * Decimal(w.dt)
+    z0 = (w.lon0 - 5e4) + 1j * (w.lat0 - 5e4)
+    zc = np.array([_decimal_pow(Decimal(1), th, z, w.nsteps) for z in z0])
+    assert np.abs((st.x - 5e4 + 1j * (st.y - 5e4)) - zc).max() < 1e-8
+    # the radius grows by (1 + theta^2)^(n/2), the scheme's known drift
+    growth = (1 + float(th) ** 2) ** (w.nsteps / 2)
+    assert np.allclose(np.abs(st.x - 5e4 + 1j * (st.y - 5e4)), np.abs(z0) * growth, rtol=1e-12)
+
+
+def test_nearest_neighbour_picks_the_nearer_node():
+    rng = np.random.default_rng(21)
+    X = rand_axis(rng, 8, 0.0, 100.0)
+    Y = rand_axis(rng, 6, -20.0, 20.0)
+    U = rng.normal(size=(2, 6, 8))
+    V = rng.normal(size=(2, 6, 8))
+    T = np.array([0.0, 50.0])
+    fs = O.OracleFieldSet(X, Y, None, T, U, V)
+    for _ in range(400):
+        x, y, t = rng.uniform(X[0], X[-1]), rng.uniform(Y[0], Y[-1]), rng.uniform(0, 50)
+        rc, out = fs.sample(x, y, 0.0, t, nearest=True)
+        assert rc == 0
+        # brute force: the node whose coordinate is closest on each axis (ties up)
+        i = int(np.argmin(np.abs(X - x) - 1e-12 * (X >= x)))
+        j = int(np.argmin(np.abs(Y - y) - 1e-12 * (Y >= y)))
+        tau = t / 50.0
+        exp = (1 - tau) * U[0, j, i] + tau * U[1, j, i]
+        assert out[0] == pytest.approx(exp, abs=1e-14)
+    # a point at a cell centre goes to the upper node
+    xm = 0.5 * (X[2] + X[3])
+    rc, out = fs.sample(xm, Y[1], 0.0, 0.0, nearest=True)
+    assert out[0] == U[0, 1, 3] or abs((xm - X[2]) / (X[3] - X[2]) - 0.5) > 0
+
+
+def test_backward_in_time_returns_to_start():
+    """Forward n steps then backward n steps on the rotation field: the discrete map
+    is |R(i theta)|^(2n) (Z_0 - c), i.e. the start point to within theta^6 n r."""
+    w = SC.cfg0_solid_body(n_particles=200, nsteps=1440)
+    fs = O.OracleFieldSet.from_workload(w)
+    st = O.make_state(w.lon0, w.lat0)
+    assert O.advance(fs, st, w.dt, w.nsteps) == 0
+    assert O.advance(fs, st, -w.dt, w.nsteps) == 0
+    assert st.step == 2 * w.nsteps
+    z0 = (w.lon0 - 5e4) + 1j * (w.lat0 - 5e4)
+    back = st.x - 5e4 + 1j * (st.y - 5e4)
+    th = Decimal(w.meta["omega"]) * Decimal(w.dt)
+    re = 1 - th ** 2 / 2 + th ** 4 / 24
+    im = th - th ** 3 / 6
+    mod2 = re * re + im * im  # |R(i theta)|^2
+    zc = np.array([_decimal_pow(mod2, Decimal(0), z, w.nsteps) for z in z0])
+    assert np.abs(back - zc).max() < 1e-8
+    assert np.abs(back - z0).max() < 1e-6
+
+
+def test_backward_needs_snapshots_before_the_start():
+    X = np.arange(4.0)
+    U = np.zeros((2, 4, 4))
+    fs = O.OracleFieldSet(X, X, None, [0.0, 100.0], U, U)
+    st = O.make_state([1.0], [1.0], t_org=100.0)
+    assert O.advance(fs, st, -10.0, 10) == 0
+    assert O.advance(fs, st, -10.0, 1) == -4
