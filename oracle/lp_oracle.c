@@ -16,13 +16,23 @@
  *     domain, Sect. 2.1.2 and Sect. 3.3);
  *   - a Brownian displacement with uniform Kh (the behaviour term of Eq. (1),
  *     Sect. 2.1.2 and Sect. 4.2.7), drawn with Philox4x32-10 (Salmon et al.,
- *     "Parallel random numbers: as easy as 1, 2, 3", SC'11).
+ *     "Parallel random numbers: as easy as 1, 2, 3", SC'11);
+ *   - the alternative integrators named in Sect. 2.1.1: Euler forward and the
+ *     adaptive Runge-Kutta-Fehlberg pair RKF45 (Fehlberg, NASA TR R-315, 1969),
+ *     with the step-size control read below.
  *
  * Readings where the paper is silent (each one is listed with its reason in the
  * design notes): classical RK4 tableau; lower-cell rule at a node with the last
  * node in the last cell; space first, then time; metres per degree 1852*60;
  * cos(lat) taken at each stage point; a step is rejected whole if any stage
  * point or the end point leaves the domain; a land cell has four land corners.
+ * RKF45 (the paper names it only): the fourth-order solution advances the
+ * particle; the error is the length in metres of the fifth-minus-fourth-order
+ * difference; each particle's step is |dt| 2^e with an integer e in [emin, emax]
+ * that starts at 0; a step with error above tol is retried at half the size
+ * (unless e = emin), an accepted step with error at most tol/32 doubles the next
+ * one (up to emax); the step is cut short to land on the end of the output
+ * interval, and a cut step leaves e as it was.
  */
 #include <math.h>
 #include <stdint.h>
@@ -59,8 +69,10 @@ typedef struct {
     int policy;              /* 0: delete on error, 1: freeze on error */
     double Kh;               /* horizontal diffusivity, 0 = no Brownian term */
     uint32_t run_id, seed;   /* Philox key */
-    int scheme;              /* 0: classical RK4, 1: Euler forward (Sect. 2.1.1) */
+    int scheme;              /* 0: classical RK4, 1: Euler forward, 2: RKF45 (Sect. 2.1.1) */
     int nearest;             /* 1: nearest-neighbour instead of linear in space (Sect. 2.3) */
+    double tol;              /* RKF45: error tolerance per step in metres */
+    int emin, emax;          /* RKF45: range of the step exponent e, step = |dt| 2^e */
 } or_options;
 
 /* ---------------------------------------------------------------- cell search */
@@ -412,6 +424,169 @@ int or_advance(const or_fieldset *fs, int64_t n, double *x, double *y, double *z
     }
     if (psteps)
         *psteps += total;
+    return OR_OK;
+}
+
+/* ---------------------------------------------------------------- RKF45 */
+/* The Fehlberg 4(5) pair: stage nodes c, stage matrix a (row i uses the slopes
+ * before it), fourth-order weights b4 and fifth-order weights b5. */
+static const double RKF_C[6] = {0.0, 1.0 / 4.0, 3.0 / 8.0, 12.0 / 13.0, 1.0, 1.0 / 2.0};
+static const double RKF_A[6][5] = {
+    {0.0, 0.0, 0.0, 0.0, 0.0},
+    {1.0 / 4.0, 0.0, 0.0, 0.0, 0.0},
+    {3.0 / 32.0, 9.0 / 32.0, 0.0, 0.0, 0.0},
+    {1932.0 / 2197.0, -7200.0 / 2197.0, 7296.0 / 2197.0, 0.0, 0.0},
+    {439.0 / 216.0, -8.0, 3680.0 / 513.0, -845.0 / 4104.0, 0.0},
+    {-8.0 / 27.0, 2.0, -3544.0 / 2565.0, 1859.0 / 4104.0, -11.0 / 40.0}};
+static const double RKF_B4[6] = {25.0 / 216.0, 0.0, 1408.0 / 2565.0, 2197.0 / 4104.0,
+                                 -1.0 / 5.0, 0.0};
+static const double RKF_B5[6] = {16.0 / 135.0, 0.0, 6656.0 / 12825.0, 28561.0 / 56430.0,
+                                 -9.0 / 50.0, 2.0 / 55.0};
+
+/* One RKF45 attempt of signed size h from p at time t: the fourth-order end point
+ * p4, the fifth-order end point p5 (may be NULL) and the error estimate
+ * err = p5 - p4, written as h times the weight differences times the slopes.
+ * Returns 1 if a stage point lies outside the grid, 2 outside the snapshots. */
+int or_rkf45_attempt(const or_fieldset *fs, int nearest, double t, double h, const double p[3],
+                     double p4[3], double p5[3], double err[3])
+{
+    double k[6][3];
+    for (int i = 0; i < 6; i++) {
+        double q[3];
+        for (int d = 0; d < 3; d++) {
+            double s = 0.0;
+            for (int j = 0; j < i; j++)
+                s = s + RKF_A[i][j] * k[j][d];
+            q[d] = p[d] + h * s;
+        }
+        int rc = sample_mode(fs, q[0], q[1], q[2], t + RKF_C[i] * h, k[i], nearest);
+        if (rc)
+            return rc;
+    }
+    for (int d = 0; d < 3; d++) {
+        double s4 = 0.0, s5 = 0.0, se = 0.0;
+        for (int i = 0; i < 6; i++) {
+            s4 = s4 + RKF_B4[i] * k[i][d];
+            s5 = s5 + RKF_B5[i] * k[i][d];
+            se = se + (RKF_B5[i] - RKF_B4[i]) * k[i][d];
+        }
+        p4[d] = p[d] + h * s4;
+        if (p5)
+            p5[d] = p[d] + h * s5;
+        err[d] = h * se;
+    }
+    if (fs->nz <= 0) {
+        p4[2] = p[2];
+        if (p5)
+            p5[2] = p[2];
+        err[2] = 0.0;
+    }
+    return 0;
+}
+
+/* Length in metres of a displacement (dx, dy, dz) taken at latitude y. */
+double or_metres(const or_fieldset *fs, double y, const double e[3])
+{
+    double ex = e[0], ey = e[1], ez = e[2];
+    if (fs->spherical) {
+        ex = ex * (OR_M * cos(y * OR_D));
+        ey = ey * OR_M;
+    }
+    return sqrt((ex * ex + ey * ey) + ez * ez);
+}
+
+/* Carry one particle from t_s to t_e (either direction, sign of dt) with adaptive
+ * RKF45 steps; *pe is its step exponent.  Counts the attempts that were not
+ * retried for accuracy (*acc) and the retried ones (*rej). */
+static void rkf45_particle(const or_fieldset *fs, const or_options *opt, double t_s, double t_e,
+                           double dt, double *px, double *py, double *pz, unsigned char *st,
+                           signed char *pe, int64_t *acc, int64_t *rej)
+{
+    const int is3d = fs->nz > 0;
+    const unsigned char err_extra = opt->policy == 0 ? OR_ST_DELETED : 0;
+    const double sg = dt > 0.0 ? 1.0 : -1.0, adt = fabs(dt);
+    double p[3] = {*px, *py, is3d ? *pz : 0.0};
+    int e = *pe;
+    double t = t_s;
+    while (t != t_e) {
+        const double h = ldexp(adt, e);
+        const double rem = sg > 0.0 ? t_e - t : t - t_e;
+        const int cut = h >= rem;
+        const double hs = sg * (cut ? rem : h);
+        double p4[3], ev[3];
+        if (or_rkf45_attempt(fs, opt->nearest, t, hs, p, p4, NULL, ev)) {
+            (*acc)++;
+            *st = (unsigned char)(OR_ST_OOB | err_extra);
+            break;
+        }
+        const double err = or_metres(fs, p[1], ev);
+        if (err > opt->tol && e > opt->emin) {
+            e--;
+            (*rej)++;
+            continue;
+        }
+        (*acc)++;
+        or_cell c;
+        if (!in_domain(fs, p4[0], p4[1], p4[2], &c)) {
+            *st = (unsigned char)(OR_ST_OOB | err_extra);
+            break;
+        }
+        if (fs->land && land_cell(fs, c.i, c.j)) {
+            *st = (unsigned char)(OR_ST_LAND | err_extra);
+            break;
+        }
+        p[0] = p4[0];
+        p[1] = p4[1];
+        p[2] = p4[2];
+        t = cut ? t_e : t + hs;
+        if (!cut && err <= opt->tol * 0.03125 && e < opt->emax)
+            e++;
+    }
+    *px = p[0];
+    *py = p[1];
+    if (is3d)
+        *pz = p[2];
+    *pe = (signed char)e;
+}
+
+/* Advance n particles from t_s to t_e with RKF45 (opt->scheme is ignored).  The
+ * smallest step |dt| 2^emin must move a time of magnitude max(|t_s|, |t_e|).
+ * Returns OR_EINVAL for bad arguments and OR_ETIME if [t_s, t_e] is not covered. */
+int or_advance_rkf45(const or_fieldset *fs, int64_t n, double *x, double *y, double *z,
+                     unsigned char *status, signed char *exps, double t_s, double t_e,
+                     double dt, const or_options *opt, int64_t *accepted, int64_t *rejected,
+                     int nthreads)
+{
+    if (dt == 0.0 || n < 0 || !(opt->tol > 0.0) || opt->emin > 0 || opt->emax < 0 ||
+        opt->emin < -30 || opt->emax > 30 || (t_e - t_s) * dt < 0.0)
+        return OR_EINVAL;
+    const double tm = fabs(t_s) > fabs(t_e) ? fabs(t_s) : fabs(t_e);
+    if (tm + ldexp(fabs(dt), opt->emin) * 0.25 == tm && t_s != t_e)
+        return OR_EINVAL;
+    if (fs->nt > 1 && !(fs->period > 0.0)) {
+        const double lo = t_s < t_e ? t_s : t_e, hi = t_s < t_e ? t_e : t_s;
+        if (lo < fs->T[0] || hi > fs->T[fs->nt - 1])
+            return OR_ETIME;
+    }
+    int64_t ta = 0, tr = 0;
+#ifdef _OPENMP
+    if (nthreads <= 0)
+        nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 64) num_threads(nthreads) reduction(+ : ta, tr)
+#endif
+    for (int64_t q = 0; q < n; q++) {
+        if (status[q])
+            continue;
+        int64_t a = 0, r = 0;
+        rkf45_particle(fs, opt, t_s, t_e, dt, &x[q], &y[q], z ? &z[q] : NULL, &status[q],
+                       &exps[q], &a, &r);
+        ta += a;
+        tr += r;
+    }
+    if (accepted)
+        *accepted += ta;
+    if (rejected)
+        *rejected += tr;
     return OR_OK;
 }
 

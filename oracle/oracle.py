@@ -55,11 +55,17 @@ class _FS(C.Structure):
 class _OPT(C.Structure):
     _fields_ = [("policy", C.c_int), ("Kh", C.c_double),
                 ("run_id", C.c_uint32), ("seed", C.c_uint32),
-                ("scheme", C.c_int), ("nearest", C.c_int)]
+                ("scheme", C.c_int), ("nearest", C.c_int),
+                ("tol", C.c_double), ("emin", C.c_int), ("emax", C.c_int)]
 
 
 SCHEME_RK4 = 0
 SCHEME_EULER = 1
+SCHEME_RKF45 = 2
+# RKF45 step control defaults: tolerance per step (m) and exponent range of |dt| 2^e
+RKF_TOL = 1.0
+RKF_EMIN = -6
+RKF_EMAX = 4
 
 
 _lib = None
@@ -89,6 +95,15 @@ def lib():
                                  C.c_double, C.c_int64, C.c_int64, C.POINTER(_OPT),
                                  C.POINTER(C.c_int64), C.c_int]
         L.or_advance.restype = C.c_int
+        L.or_rkf45_attempt.argtypes = [C.POINTER(_FS), C.c_int, C.c_double, C.c_double, P, P,
+                                       P, P]
+        L.or_rkf45_attempt.restype = C.c_int
+        L.or_metres.argtypes = [C.POINTER(_FS), C.c_double, P]
+        L.or_metres.restype = C.c_double
+        L.or_advance_rkf45.argtypes = [C.POINTER(_FS), C.c_int64, P, P, P, P, P, C.c_double,
+                                       C.c_double, C.c_double, C.POINTER(_OPT),
+                                       C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.c_int]
+        L.or_advance_rkf45.restype = C.c_int
         L.or_cell_indices.argtypes = [C.POINTER(_FS), C.c_int64, P, P, P, P, P, P]
         L.or_cell_indices.restype = None
         L.or_max_threads.argtypes = []
@@ -144,6 +159,20 @@ class OracleFieldSet:
         rc = f(C.byref(self.s), x, y, z, t, out.ctypes.data)
         return rc, out
 
+    def rkf45_attempt(self, t, h, p, nearest=False):
+        """One RKF45 attempt: (rc, fourth-order end point, fifth-order end point,
+        error estimate) from position p = (x, y, z) at time t with signed step h."""
+        p = np.ascontiguousarray(p, np.float64)
+        p4, p5, err = np.zeros(3), np.zeros(3), np.zeros(3)
+        rc = lib().or_rkf45_attempt(C.byref(self.s), int(bool(nearest)), float(t), float(h),
+                                    p.ctypes.data, p4.ctypes.data, p5.ctypes.data,
+                                    err.ctypes.data)
+        return rc, p4, p5, err
+
+    def metres(self, y, e):
+        e = np.ascontiguousarray(e, np.float64)
+        return lib().or_metres(C.byref(self.s), float(y), e.ctypes.data)
+
     def time_bracket(self, t):
         s0, s1, tau = C.c_int(), C.c_int(), C.c_double()
         rc = lib().or_time_bracket(C.byref(self.s), t, C.byref(s0), C.byref(s1), C.byref(tau))
@@ -194,6 +223,8 @@ class State:
     step: int
     psteps: int = 0
     dt: Optional[float] = None  # dt of the previous advance (time origin bookkeeping)
+    exps: Optional[np.ndarray] = None  # RKF45 step exponents (int8), step = |dt| 2^e
+    rejected: int = 0                  # RKF45 attempts retried for accuracy
 
 
 def make_state(x, y, z=None, pid=None, t_org=0.0, step=0) -> State:
@@ -201,23 +232,45 @@ def make_state(x, y, z=None, pid=None, t_org=0.0, step=0) -> State:
     y = np.array(y, np.float64, copy=True)
     z = None if z is None else np.array(z, np.float64, copy=True)
     pid = np.arange(x.size, dtype=np.uint32) if pid is None else np.ascontiguousarray(pid, np.uint32)
-    return State(x, y, z, np.zeros(x.size, np.uint8), pid, float(t_org), int(step))
+    return State(x, y, z, np.zeros(x.size, np.uint8), pid, float(t_org), int(step),
+                 exps=np.zeros(x.size, np.int8))
 
 
 def advance(fs: OracleFieldSet, st: State, dt: float, nsteps: int, Kh: float = 0.0,
             run_id: int = 0, seed: int = SEED, policy: int = POLICY_DELETE,
-            nthreads: int = 0, scheme: int = SCHEME_RK4, nearest: bool = False) -> int:
+            nthreads: int = 0, scheme: int = SCHEME_RK4, nearest: bool = False,
+            tol: float = RKF_TOL, emin: int = RKF_EMIN, emax: int = RKF_EMAX) -> int:
     """Advance ``st`` in place by ``nsteps`` steps of ``dt`` (negative dt runs
     backward in time); returns the oracle's return code (0, or -4 if a needed time
-    lies outside the snapshots)."""
+    lies outside the snapshots).  With RKF45 the call is one output interval: every
+    particle goes from t_org + step dt to t_org + (step + nsteps) dt in adaptive
+    steps |dt| 2^e."""
     if fs.is3d and st.z is None:
         raise ValueError("3D field set needs depths")
     opt = _OPT(int(policy), float(Kh), int(run_id) & 0xFFFFFFFF, int(seed) & 0xFFFFFFFF,
-               int(scheme), int(bool(nearest)))
+               int(scheme), int(bool(nearest)), float(tol), int(emin), int(emax))
     # time is t_org + step * dt; a change of dt keeps the current time
     if st.dt is not None and dt != st.dt:
         st.t_org = (st.t_org + st.step * st.dt) - st.step * dt
     ps = C.c_int64(0)
+    if scheme == SCHEME_RKF45:
+        if Kh != 0.0:
+            raise ValueError("RKF45 takes no Brownian term")
+        if st.exps is None:
+            st.exps = np.zeros(st.x.size, np.int8)
+        t_s = st.t_org + st.step * dt
+        t_e = st.t_org + (st.step + int(nsteps)) * dt
+        rj = C.c_int64(0)
+        rc = lib().or_advance_rkf45(C.byref(fs.s), st.x.size, _ptr(st.x), _ptr(st.y),
+                                    _ptr(st.z if fs.is3d else None), _ptr(st.status),
+                                    _ptr(st.exps), t_s, t_e, float(dt), C.byref(opt),
+                                    C.byref(ps), C.byref(rj), int(nthreads))
+        if rc == 0:
+            st.step += int(nsteps)
+            st.psteps += ps.value
+            st.rejected += rj.value
+            st.dt = float(dt)
+        return rc
     rc = lib().or_advance(C.byref(fs.s), st.x.size, _ptr(st.x), _ptr(st.y),
                           _ptr(st.z if fs.is3d else None), _ptr(st.status), _ptr(st.pid),
                           st.t_org, float(dt), st.step, int(nsteps), C.byref(opt),
@@ -241,7 +294,8 @@ def record(fs: OracleFieldSet, st: State) -> dict:
 def run(fs: OracleFieldSet, st: State, dt: float, runtime: float, outputdt: float,
         Kh: float = 0.0, run_id: int = 0, policy: int = POLICY_DELETE,
         nthreads: int = 0, first_record: bool = True, scheme: int = SCHEME_RK4,
-        nearest: bool = False):
+        nearest: bool = False, tol: float = RKF_TOL, emin: int = RKF_EMIN,
+        emax: int = RKF_EMAX):
     """Execute for ``runtime`` with records every ``outputdt``; returns the list of
     records (the first taken at the start time when ``first_record``).  A negative
     dt runs backward in time (runtime and outputdt stay positive)."""
@@ -255,7 +309,7 @@ def run(fs: OracleFieldSet, st: State, dt: float, runtime: float, outputdt: floa
     while done < nsteps:
         k = min(per, nsteps - done)
         rc = advance(fs, st, dt, k, Kh=Kh, run_id=run_id, policy=policy, nthreads=nthreads,
-                     scheme=scheme, nearest=nearest)
+                     scheme=scheme, nearest=nearest, tol=tol, emin=emin, emax=emax)
         if rc != 0:
             raise RuntimeError(f"oracle advance failed: {rc}")
         done += k
