@@ -70,6 +70,8 @@ extern "C" {
 /* integrators (Sect. 2.1.1) */
 #define LP_KERNEL_RK4 0   /* classical fourth-order Runge-Kutta, the default */
 #define LP_KERNEL_EULER 1 /* Euler forward: one slope per step */
+#define LP_KERNEL_RKF45 2 /* adaptive Runge-Kutta-Fehlberg 4(5), per-particle step;
+                             see lp_exec_opts.rkf_tol */
 
 /* spatial interpolation (Sect. 2.3); time is always linear */
 #define LP_INTERP_LINEAR 0  /* bilinear / trilinear */
@@ -134,7 +136,7 @@ int pset_create_device(lp_fieldset *fs, int64_t n, const double *dlon, const dou
                        lp_pset **out);
 
 typedef struct {
-    int32_t kernel;       /* LP_KERNEL_RK4 or LP_KERNEL_EULER */
+    int32_t kernel;       /* LP_KERNEL_RK4, LP_KERNEL_EULER or LP_KERNEL_RKF45 */
     int32_t recovery;     /* LP_DELETE or LP_FREEZE */
     double Kh;            /* > 0: add a Brownian displacement sqrt(2 Kh dt) N(0,1)
                              per horizontal component after each step (Sect. 4.2.7) */
@@ -149,6 +151,20 @@ typedef struct {
                              0: gather the stencil at every stage (same results up
                              to rounding) */
     int32_t interp;       /* LP_INTERP_LINEAR or LP_INTERP_NEAREST */
+    /* LP_KERNEL_RKF45 (the adaptive scheme named in Sect. 2.1.1; the control
+     * rule is this library's reading): each particle steps by |dt| 2^e with its
+     * own integer exponent e in [rkf_min_exp, rkf_max_exp] (e starts at 0 and is
+     * kept from call to call).  An attempt takes the six Fehlberg slopes; the
+     * fourth-order solution advances the particle and the fifth-minus-fourth
+     * difference, as a length in metres, is its error.  An error above rkf_tol
+     * retries the step at e - 1 (unless e is already the minimum); an accepted
+     * error at most rkf_tol / 32 raises e by one for the next step (up to the
+     * maximum).  The last step of each output interval is cut short to land on
+     * the output time and leaves e unchanged.  Needs Kh = 0; the batched launch
+     * and the autotuner do not take it; stencil_cache is ignored. */
+    double rkf_tol;       /* > 0, metres per step */
+    int32_t rkf_min_exp;  /* in [-30, 0]; |dt| 2^min must still move the clock */
+    int32_t rkf_max_exp;  /* in [0, 30] */
 } lp_exec_opts;
 
 /* Advance every active particle by runtime/|dt| steps of dt, taking an output
@@ -163,9 +179,11 @@ int pset_execute(lp_pset *ps, double runtime, double dt, double outputdt,
 
 typedef struct {
     int64_t n, active, oob, land, deleted;
-    int64_t particle_steps; /* (particle, step) pairs that started active */
+    int64_t particle_steps; /* (particle, step) pairs that started active; with
+                               RKF45 the attempts that were not retried */
     double time;            /* current time */
-    int64_t step;           /* steps taken since t0 */
+    int64_t step;           /* steps of dt taken since t0 */
+    int64_t rejected_steps; /* RKF45 attempts retried at half the step */
 } lp_counts;
 
 /* Run many independent particle sets (each with its own field set: grid size,
@@ -199,6 +217,8 @@ int pset_status(lp_pset *ps, lp_counts *c, uint8_t *status);
  * pointer may be NULL.  Synchronises. */
 int pset_get(lp_pset *ps, double *lon, double *lat, double *depth, int32_t *ci, int32_t *cj,
              int32_t *ck);
+/* The n RKF45 step exponents e (step |dt| 2^e) in id order.  Synchronises. */
+int pset_get_step_exponents(lp_pset *ps, int8_t *e);
 /* Output records: *nrec records of *nper = ceil(n / output_stride) particles
  * (ids 0, k, 2k, ...), record-major.  Call with NULL arrays to get the sizes.
  * Synchronises. */

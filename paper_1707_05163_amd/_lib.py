@@ -19,6 +19,7 @@ LP_DELETE, LP_FREEZE = 0, 1
 LP_ST_OOB, LP_ST_LAND, LP_ST_DELETED = 1, 2, 4
 LP_KERNEL_RK4 = 0
 LP_KERNEL_EULER = 1
+LP_KERNEL_RKF45 = 2
 LP_INTERP_LINEAR, LP_INTERP_NEAREST = 0, 1
 
 # every function declared in include/lp.h
@@ -27,6 +28,7 @@ EXPORTS = (
     "fieldset_push_snapshot_device", "fieldset_get_snapshot", "fieldset_resident",
     "fieldset_destroy", "lp_philox_normals",
     "pset_create", "pset_create_device", "pset_execute", "pset_status", "pset_get",
+    "pset_get_step_exponents",
     "pset_records", "pset_timing", "pset_destroy", "lp_last_error", "lp_version",
     "pset_execute_batch", "pset_autotune_batch",
     "surrogate_param_count", "surrogate_create", "surrogate_get_params", "surrogate_set_params",
@@ -46,13 +48,14 @@ class lp_exec_opts(C.Structure):
     _fields_ = [("kernel", C.c_int32), ("recovery", C.c_int32), ("Kh", C.c_double),
                 ("run_id", C.c_uint32), ("seed", C.c_uint32), ("output_stride", C.c_int32),
                 ("sort_every", C.c_int32), ("profile", C.c_int32),
-                ("stencil_cache", C.c_int32), ("interp", C.c_int32)]
+                ("stencil_cache", C.c_int32), ("interp", C.c_int32),
+                ("rkf_tol", C.c_double), ("rkf_min_exp", C.c_int32), ("rkf_max_exp", C.c_int32)]
 
 
 class lp_counts(C.Structure):
     _fields_ = [("n", C.c_int64), ("active", C.c_int64), ("oob", C.c_int64),
                 ("land", C.c_int64), ("deleted", C.c_int64), ("particle_steps", C.c_int64),
-                ("time", C.c_double), ("step", C.c_int64)]
+                ("time", C.c_double), ("step", C.c_int64), ("rejected_steps", C.c_int64)]
 
 
 class lp_tune(C.Structure):
@@ -102,6 +105,7 @@ def _declare(L):
         "pset_execute": ([P, C.c_double, C.c_double, C.c_double, C.POINTER(lp_exec_opts), P], I),
         "pset_status": ([P, C.POINTER(lp_counts), P], I),
         "pset_get": ([P, P, P, P, P, P, P], I),
+        "pset_get_step_exponents": ([P, P], I),
         "pset_records": ([P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), P, P, P, P, P, P, P], I),
         "pset_timing": ([P, C.POINTER(C.c_double), C.POINTER(C.c_int64)], I),
         "pset_execute_batch": ([C.POINTER(C.c_void_p), C.c_int32, C.c_double, C.c_double,

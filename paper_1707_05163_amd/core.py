@@ -16,7 +16,9 @@ SEED = 0x17070516
 _DTYPES = {"f64": L.LP_F64, "f32": L.LP_F32, "bf16": L.LP_BF16, "f16s": L.LP_F16_SCALED}
 _MESH = {"flat": L.LP_MESH_FLAT, "spherical": L.LP_MESH_SPHERICAL}
 _RECOVERY = {"delete": L.LP_DELETE, "freeze": L.LP_FREEZE}
-_KERNEL = {"rk4": L.LP_KERNEL_RK4, "euler": L.LP_KERNEL_EULER}
+_KERNEL = {"rk4": L.LP_KERNEL_RK4, "euler": L.LP_KERNEL_EULER, "rkf45": L.LP_KERNEL_RKF45}
+# RKF45 step control: tolerance per step (m), exponent range of the step |dt| 2^e
+RKF_TOL, RKF_MIN_EXP, RKF_MAX_EXP = 1.0, -6, 4
 _INTERP = {"linear": L.LP_INTERP_LINEAR, "nearest": L.LP_INTERP_NEAREST}
 
 
@@ -165,19 +167,24 @@ class ParticleSet:
     @staticmethod
     def opts(recovery: str = "delete", Kh: float = 0.0, run_id: int = 0, seed: int = SEED,
              output_stride: int = 0, sort_every: int = 1, profile: bool = False,
-             stencil_cache: bool = True, kernel: str = "rk4", interp: str = "linear"):
+             stencil_cache: bool = True, kernel: str = "rk4", interp: str = "linear",
+             tol: float = RKF_TOL, min_exp: int = RKF_MIN_EXP, max_exp: int = RKF_MAX_EXP):
         return L.lp_exec_opts(_KERNEL[kernel], _RECOVERY[recovery], float(Kh), int(run_id),
                               int(seed) & 0xFFFFFFFF, int(output_stride), int(sort_every),
-                              int(bool(profile)), int(bool(stencil_cache)), _INTERP[interp])
+                              int(bool(profile)), int(bool(stencil_cache)), _INTERP[interp],
+                              float(tol), int(min_exp), int(max_exp))
 
     def execute(self, runtime: float, dt: float, outputdt: float = 0.0,
                 recovery: str = "delete", Kh: float = 0.0, run_id: int = 0, seed: int = SEED,
                 output_stride: int = 0, sort_every: int = 1, profile: bool = False,
                 stencil_cache: bool = True, kernel: str = "rk4", interp: str = "linear",
+                tol: float = RKF_TOL, min_exp: int = RKF_MIN_EXP, max_exp: int = RKF_MAX_EXP,
                 stream=None):
-        """The update loop: runtime/|dt| steps of dt (negative dt runs backward)."""
+        """The update loop: runtime/|dt| steps of dt (negative dt runs backward).  With
+        kernel="rkf45" each particle steps adaptively by |dt| 2^e, e in
+        [min_exp, max_exp], to within `tol` metres per step."""
         o = self.opts(recovery, Kh, run_id, seed, output_stride, sort_every, profile,
-                      stencil_cache, kernel, interp)
+                      stencil_cache, kernel, interp, tol, min_exp, max_exp)
         L.check(L.lib.pset_execute(self._h, float(runtime), float(dt), float(outputdt),
                                    C.byref(o), _stream(stream)))
 
@@ -187,6 +194,12 @@ class ParticleSet:
         L.check(L.lib.pset_status(self._h, C.byref(c), st.ctypes.data))
         counts = {k: getattr(c, k) for k, _ in L.lp_counts._fields_}
         return counts, st
+
+    def step_exponents(self):
+        """RKF45 step exponents e (step |dt| 2^e), id order."""
+        e = np.empty(self.n, np.int8)
+        L.check(L.lib.pset_get_step_exponents(self._h, e.ctypes.data))
+        return e
 
     def get(self):
         n = self.n

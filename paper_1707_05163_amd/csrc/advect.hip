@@ -337,6 +337,204 @@ __global__ __launch_bounds__(kBlock) void k_advect(AdvectParams P)
         atomicAdd(P.psteps, (unsigned long long)steps);
 }
 
+// ---------------------------------------------------------------- adaptive RKF45
+// The Runge-Kutta-Fehlberg option of Sect. 2.1.1 with a per-particle step |dt| 2^e.
+// Each lane runs its own sequence of attempts from t_start to t_end, so its stage
+// times are its own: the bracketing snapshots of each stage time are found per
+// lane in the resident-snapshot table, with the same arithmetic as the host's
+// stage-time table (periodic fields first map t into [T0, T0 + period)).
+__device__ inline TimeEntry bracket_lane(const AdvectParams &P, double t)
+{
+    const ResTime *r = P.res;
+    const int m = P.nres;
+    TimeEntry e;
+    if (P.f.steady) {
+        e.tau = 0.0;
+        e.sa = e.sb = r[0].slot;
+        return e;
+    }
+    if (P.period > 0.0) {
+        const double T0 = r[0].t;
+        double q = fmod(t - T0, P.period);
+        if (q < 0.0)
+            q += P.period;
+        const double tp = T0 + q;
+        int lo = 0, hi = m - 1;  // largest k with r[k].t <= tp (r[0].t <= tp)
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (r[mid].t <= tp)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const double tn = lo + 1 < m ? r[lo + 1].t : T0 + P.period;
+        e.sa = r[lo].slot;
+        e.sb = lo + 1 < m ? r[lo + 1].slot : r[0].slot;
+        e.tau = (tp - r[lo].t) / (tn - r[lo].t);
+        return e;
+    }
+    int lo = 0, hi = m - 2;  // largest k <= m-2 with r[k].t <= t (the host checked
+    while (lo < hi) {        // that [t_start, t_end] lies inside the table)
+        const int mid = (lo + hi + 1) >> 1;
+        if (r[mid].t <= t)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    e.sa = r[lo].slot;
+    e.sb = r[lo + 1].slot;
+    e.tau = (t - r[lo].t) / (r[lo + 1].t - r[lo].t);
+    return e;
+}
+
+// Fehlberg 4(5) pair: nodes, stage matrix, fourth-order weights, and the
+// differences fifth- minus fourth-order weights (the error estimate).
+struct Fehlberg {
+    static constexpr double c[6] = {0.0, 1.0 / 4.0, 3.0 / 8.0, 12.0 / 13.0, 1.0, 1.0 / 2.0};
+    static constexpr double a[6][5] = {
+        {0.0, 0.0, 0.0, 0.0, 0.0},
+        {1.0 / 4.0, 0.0, 0.0, 0.0, 0.0},
+        {3.0 / 32.0, 9.0 / 32.0, 0.0, 0.0, 0.0},
+        {1932.0 / 2197.0, -7200.0 / 2197.0, 7296.0 / 2197.0, 0.0, 0.0},
+        {439.0 / 216.0, -8.0, 3680.0 / 513.0, -845.0 / 4104.0, 0.0},
+        {-8.0 / 27.0, 2.0, -3544.0 / 2565.0, 1859.0 / 4104.0, -11.0 / 40.0}};
+    static constexpr double b4[6] = {25.0 / 216.0, 0.0, 1408.0 / 2565.0, 2197.0 / 4104.0,
+                                     -1.0 / 5.0, 0.0};
+    static constexpr double b5[6] = {16.0 / 135.0, 0.0, 6656.0 / 12825.0, 28561.0 / 56430.0,
+                                     -9.0 / 50.0, 2.0 / 55.0};
+};
+
+// One attempt of signed size h from p at time t: fourth-order end point p4 and
+// error estimate ev (fifth minus fourth order); false if a stage leaves the grid.
+template <int ST, bool IS3D, bool STEADY>
+__device__ inline bool rkf45_attempt(const AdvectParams &P, double t, double h,
+                                     const double p[3], double p4[3], double ev[3])
+{
+    double k[6][3];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        double q[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            double s = 0.0;
+#pragma unroll
+            for (int j = 0; j < i; ++j)
+                s = s + Fehlberg::a[i][j] * k[j][d];
+            q[d] = p[d] + h * s;
+        }
+        const TimeEntry te = bracket_lane(P, t + Fehlberg::c[i] * h);
+        if (!sample<ST, IS3D, STEADY>(P, te, q[0], q[1], q[2], k[i]))
+            return false;
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        double s4 = 0.0, se = 0.0;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            s4 = s4 + Fehlberg::b4[i] * k[i][d];
+            se = se + (Fehlberg::b5[i] - Fehlberg::b4[i]) * k[i][d];
+        }
+        p4[d] = p[d] + h * s4;
+        ev[d] = h * se;
+    }
+    if constexpr (!IS3D) {
+        p4[2] = p[2];
+        ev[2] = 0.0;
+    }
+    return true;
+}
+
+template <int ST, bool IS3D, bool STEADY>
+__global__ __launch_bounds__(kBlock) void k_rkf45(AdvectParams P)
+{
+    const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const uint32_t k = blk * kBlock + threadIdx.x;
+    const uint32_t nact = *P.n_active;
+    long long acc = 0, rej = 0;
+    if (k < nact) {
+        const uint32_t id = P.order[k];
+        uint8_t st = P.status[id];
+        if (st == 0) {
+            const uint8_t extra = P.policy == 0 ? ST_DELETED : 0;
+            double p[3] = {P.x[id], P.y[id], IS3D ? P.z[id] : 0.0};
+            int e = P.hexp[id];
+            const double sg = P.dt > 0.0 ? 1.0 : -1.0, adt = fabs(P.dt);
+            const double te = P.t_end;
+            double t = P.t_start;
+            // every attempt either lowers e (at most e - emin times in a row) or moves
+            // t by at least the floor step, so max_iter is never reached
+            for (int it = 0; t != te; ++it) {
+                if (it >= P.max_iter) {
+                    st = (uint8_t)(ST_OOB | extra);
+                    break;
+                }
+                const double h = ldexp(adt, e);
+                const double rem = sg > 0.0 ? te - t : t - te;
+                const bool cut = h >= rem;
+                const double hs = sg * (cut ? rem : h);
+                double p4[3], ev[3];
+                if (!rkf45_attempt<ST, IS3D, STEADY>(P, t, hs, p, p4, ev)) {
+                    ++acc;
+                    st = (uint8_t)(ST_OOB | extra);
+                    break;
+                }
+                double ex = ev[0], ey = ev[1];
+                if (P.g.spherical) {
+                    ex = ex * (kMetresPerDegree * cos(p[1] * kDegToRad));
+                    ey = ey * kMetresPerDegree;
+                }
+                const double err = sqrt((ex * ex + ey * ey) + ev[2] * ev[2]);
+                if (err > P.tol && e > P.emin) {
+                    --e;
+                    ++rej;
+                    continue;
+                }
+                ++acc;
+                int ci, cj, ck;
+                double f;
+                if (!locate(P.g.ax, p4[0], ci, f) || !locate(P.g.ay, p4[1], cj, f)) {
+                    st = (uint8_t)(ST_OOB | extra);
+                    break;
+                }
+                if constexpr (IS3D) {
+                    if (!locate(P.g.az, p4[2], ck, f)) {
+                        st = (uint8_t)(ST_OOB | extra);
+                        break;
+                    }
+                }
+                if (P.g.landcell &&
+                    P.g.landcell[(size_t)cj * (size_t)(P.g.ax.n - 1) + (size_t)ci]) {
+                    st = (uint8_t)(ST_LAND | extra);
+                    break;
+                }
+                p[0] = p4[0];
+                p[1] = p4[1];
+                p[2] = p4[2];
+                t = cut ? te : t + hs;
+                if (!cut && err <= P.tol * 0.03125 && e < P.emax)
+                    ++e;
+            }
+            P.x[id] = p[0];
+            P.y[id] = p[1];
+            if constexpr (IS3D)
+                P.z[id] = p[2];
+            P.hexp[id] = (int8_t)e;
+            if (st)
+                P.status[id] = st;
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        acc += __shfl_xor(acc, off, 64);
+        rej += __shfl_xor(rej, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (acc)
+            atomicAdd(P.psteps, (unsigned long long)acc);
+        if (rej)
+            atomicAdd(P.prej, (unsigned long long)rej);
+    }
+}
+
 // ---------------------------------------------------------------- 2D with a stencil cache
 // Each lane keeps the stencil of the cell it is in, as the coefficients of the
 // bilinear polynomial f = c0 + c1 xi + c2 eta + c3 xi eta of U and V for the
@@ -1064,6 +1262,43 @@ hipError_t launch_advect(int store, bool is3d, const AdvectParams &p, uint32_t n
                             : launch3<kBF16, false>(p, steady, n_launch, s);
     case kF16S: return is3d ? launch3<kF16S, true>(p, steady, n_launch, s)
                             : launch3<kF16S, false>(p, steady, n_launch, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+namespace {
+
+template <int ST, bool IS3D>
+hipError_t rkf3(const AdvectParams &p, bool steady, uint32_t n_launch, hipStream_t s)
+{
+    const uint32_t blocks = (n_launch + kBlock - 1) / kBlock;
+    if (blocks == 0)
+        return hipSuccess;
+    if (steady)
+        hipLaunchKernelGGL((k_rkf45<ST, IS3D, true>), dim3(blocks), dim3(kBlock), 0, s, p);
+    else
+        hipLaunchKernelGGL((k_rkf45<ST, IS3D, false>), dim3(blocks), dim3(kBlock), 0, s, p);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_rkf45(int store, bool is3d, const AdvectParams &p, uint32_t n_launch,
+                        hipStream_t s)
+{
+    const bool steady = p.f.steady != 0;
+    if (!p.res || p.nres < 1 || (!steady && p.period <= 0.0 && p.nres < 2) || !p.hexp ||
+        !p.prej)
+        return hipErrorInvalidValue;
+    switch (store) {
+    case kF64: return is3d ? rkf3<kF64, true>(p, steady, n_launch, s)
+                           : rkf3<kF64, false>(p, steady, n_launch, s);
+    case kF32: return is3d ? rkf3<kF32, true>(p, steady, n_launch, s)
+                           : rkf3<kF32, false>(p, steady, n_launch, s);
+    case kBF16: return is3d ? rkf3<kBF16, true>(p, steady, n_launch, s)
+                            : rkf3<kBF16, false>(p, steady, n_launch, s);
+    case kF16S: return is3d ? rkf3<kF16S, true>(p, steady, n_launch, s)
+                            : rkf3<kF16S, false>(p, steady, n_launch, s);
     }
     return hipErrorInvalidValue;
 }

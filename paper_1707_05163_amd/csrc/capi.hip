@@ -514,6 +514,8 @@ extern "C" void pset_destroy(lp_pset *ps)
     dfree(ps->dhist);
     dfree(ps->dblk);
     dfree(ps->dpsteps);
+    dfree(ps->dexp);
+    dfree(ps->dres);
     dfree(ps->rx);
     dfree(ps->ry);
     dfree(ps->rz);
@@ -564,7 +566,8 @@ static int pset_create_common(lp_fieldset *fs, int64_t n, const double *lon, con
     if ((rc = dalloc(&ps->dx, N)) || (rc = dalloc(&ps->dy, N)) ||
         (fs->is3d && (rc = dalloc(&ps->dz, N))) || (rc = dalloc(&ps->dst, N)) ||
         (rc = dalloc(&ps->dorder[0], N)) || (rc = dalloc(&ps->dorder[1], N)) ||
-        (rc = dalloc(&ps->dcount, 2)) || (rc = dalloc(&ps->dpsteps, 1)))
+        (rc = dalloc(&ps->dcount, 2)) || (rc = dalloc(&ps->dpsteps, 2)) ||
+        (rc = dalloc(&ps->dexp, N)))
         return bail(rc);
     ps->nbins = lp::sort_bins(fs->g);
     if ((rc = dalloc(&ps->dkeys, N)) || (rc = dalloc(&ps->dhist, ps->nbins)) ||
@@ -583,7 +586,8 @@ static int pset_create_common(lp_fieldset *fs, int64_t n, const double *lon, con
         (fs->is3d && cp(ps->dz, depth) != hipSuccess))
         return bail(fail(LP_EDEVICE, "particle upload failed"));
     if (hipMemsetAsync(ps->dst, 0, N, stream) != hipSuccess ||
-        hipMemsetAsync(ps->dpsteps, 0, sizeof(unsigned long long), stream) != hipSuccess ||
+        hipMemsetAsync(ps->dpsteps, 0, 2 * sizeof(unsigned long long), stream) != hipSuccess ||
+        hipMemsetAsync(ps->dexp, 0, N, stream) != hipSuccess ||
         lp::launch_iota(ps->dorder[0], N, stream) != hipSuccess ||
         lp::launch_fill_u32(ps->dcount, (uint32_t)n, 1, stream) != hipSuccess)
         return bail(fail(LP_EDEVICE, "particle set initialisation failed"));
@@ -702,8 +706,16 @@ int exec_prepare(lp_pset *ps, double runtime, double dt, double outputdt, const 
     if (!ps || !o)
         return fail(LP_EINVAL, "null argument");
     lp_fieldset *fs = ps->fs;
-    if (o->kernel != LP_KERNEL_RK4 && o->kernel != LP_KERNEL_EULER)
+    if (o->kernel != LP_KERNEL_RK4 && o->kernel != LP_KERNEL_EULER &&
+        o->kernel != LP_KERNEL_RKF45)
         return fail(LP_EINVAL, "unknown kernel %d", o->kernel);
+    const bool rkf = o->kernel == LP_KERNEL_RKF45;
+    if (rkf && (!(o->rkf_tol > 0.0) || !std::isfinite(o->rkf_tol) || o->rkf_min_exp > 0 ||
+                o->rkf_min_exp < -30 || o->rkf_max_exp < 0 || o->rkf_max_exp > 30))
+        return fail(LP_EINVAL, "RKF45 needs rkf_tol > 0, rkf_min_exp in [-30, 0] and "
+                               "rkf_max_exp in [0, 30]");
+    if (rkf && o->Kh != 0.0)
+        return fail(LP_EINVAL, "RKF45 takes no Brownian term (Kh must be 0)");
     if (o->interp != LP_INTERP_LINEAR && o->interp != LP_INTERP_NEAREST)
         return fail(LP_EINVAL, "unknown interpolation %d", o->interp);
     if (o->recovery != LP_DELETE && o->recovery != LP_FREEZE)
@@ -746,13 +758,47 @@ int exec_prepare(lp_pset *ps, double runtime, double dt, double outputdt, const 
     for (int64_t a = 0; a < nsteps; a += per)
         plan.segs.emplace_back(ps->step + a, std::min(per, nsteps - a));
     size_t ntab = 0;
-    for (auto &sg : plan.segs)
-        ntab += 2 * (size_t)sg.second + 1;
+    if (!rkf)
+        for (auto &sg : plan.segs)
+            ntab += 2 * (size_t)sg.second + 1;
+    const auto res = resident(fs);
+    plan.used.assign(fs->capacity, 0);
+    if (rkf) {
+        // every particle runs its own stage times inside [t_a, t_b]: check the ends
+        // against the resident snapshots, keep them all, and make sure the floor
+        // step moves the clock anywhere in that range
+        const double ta = t0 + (double)ps->step * dt, tb = t0 + (double)(ps->step + nsteps) * dt;
+        TimeEntry e;
+        int rc;
+        if ((rc = bracket(fs, res, ta, e)) || (rc = bracket(fs, res, tb, e)))
+            return rc;
+        const double tm = std::max(std::fabs(ta), std::fabs(tb));
+        if (tm + std::ldexp(adt, o->rkf_min_exp) * 0.25 == tm)
+            return fail(LP_EINVAL, "the RKF45 floor step |dt| 2^%d is too small for times "
+                                   "near %g", o->rkf_min_exp, tm);
+        if (res.size() > ps->res_cap) {
+            dfree(ps->dres);
+            ps->res_cap = 0;
+            if ((rc = dalloc(&ps->dres, res.size())))
+                return rc;
+            ps->res_cap = res.size();
+        }
+        std::vector<lp::ResTime> rt(res.size());
+        for (size_t q = 0; q < res.size(); ++q) {
+            rt[q].t = res[q].t;
+            rt[q].slot = res[q].slot;
+            rt[q].pad = 0;
+            plan.used[res[q].slot] = 1;
+        }
+        // the table is tiny; a synchronous upload keeps it valid for every launch
+        HIPCHECK(hipMemcpy(ps->dres, rt.data(), rt.size() * sizeof(lp::ResTime),
+                           hipMemcpyHostToDevice));
+    }
     if (ps->tab_pending) {
         HIPCHECK(hipEventSynchronize(ps->tab_ev));
         ps->tab_pending = false;
     }
-    if (ntab > ps->tab_cap) {
+    if (ntab > 0 && ntab > ps->tab_cap) {
         dfree(ps->dtab);
         if (ps->htab)
             (void)hipHostFree(ps->htab);
@@ -766,9 +812,7 @@ int exec_prepare(lp_pset *ps, double runtime, double dt, double outputdt, const 
             return fail(LP_ENOMEM, "pinned allocation of the time table failed");
         ps->tab_cap = ntab;
     }
-    const auto res = resident(fs);
-    plan.used.assign(fs->capacity, 0);
-    {
+    if (!rkf) {
         size_t q = 0;
         for (auto &sg : plan.segs) {
             for (int64_t h = 0; h <= 2 * sg.second; ++h) {
@@ -783,10 +827,12 @@ int exec_prepare(lp_pset *ps, double runtime, double dt, double outputdt, const 
         }
     }
     ps->t0 = t0;
-    HIPCHECK(hipMemcpyAsync(ps->dtab, ps->htab, ntab * sizeof(TimeEntry), hipMemcpyHostToDevice,
-                            stream));
-    HIPCHECK(hipEventRecord(ps->tab_ev, stream));
-    ps->tab_pending = true;
+    if (ntab > 0) {
+        HIPCHECK(hipMemcpyAsync(ps->dtab, ps->htab, ntab * sizeof(TimeEntry),
+                                hipMemcpyHostToDevice, stream));
+        HIPCHECK(hipEventRecord(ps->tab_ev, stream));
+        ps->tab_pending = true;
+    }
     for (int s = 0; s < fs->capacity; ++s)
         if (plan.used[s])
             HIPCHECK(hipStreamWaitEvent(stream, fs->ready[s], 0));
@@ -812,7 +858,7 @@ int exec_prepare(lp_pset *ps, double runtime, double dt, double outputdt, const 
     P.dt = dt;
     P.policy = o->recovery == LP_DELETE ? 0 : 1;
     P.cache = o->stencil_cache ? 1 : 0;
-    P.scheme = o->kernel == LP_KERNEL_EULER ? 1 : 0;
+    P.scheme = o->kernel == LP_KERNEL_EULER ? 1 : (rkf ? 2 : 0);
     P.nearest = o->interp == LP_INTERP_NEAREST ? 1 : 0;
     P.Kh = o->Kh;
     P.run_id = o->run_id;
@@ -822,6 +868,22 @@ int exec_prepare(lp_pset *ps, double runtime, double dt, double outputdt, const 
     P.z = ps->dz;
     P.status = ps->dst;
     P.psteps = ps->dpsteps;
+    P.prej = ps->dpsteps + 1;
+    P.hexp = ps->dexp;
+    if (rkf) {
+        P.res = ps->dres;
+        P.nres = (int32_t)res.size();
+        P.period = fs->period;
+        P.tol = o->rkf_tol;
+        P.emin = o->rkf_min_exp;
+        P.emax = o->rkf_max_exp;
+        // attempts per particle and segment: at most one non-cut accepted step per
+        // floor step of the segment, one cut step, one retry per accepted step plus
+        // the initial descent to the floor
+        const double floor_steps = std::ceil((double)per / std::ldexp(1.0, o->rkf_min_exp));
+        const double bound = 2.0 * (floor_steps + 2.0) + (o->rkf_max_exp - o->rkf_min_exp) + 8.0;
+        P.max_iter = bound > 2.0e9 ? 2000000000 : (int32_t)bound;
+    }
     return LP_OK;
 }
 
@@ -844,6 +906,8 @@ int exec_segment_pre(lp_pset *ps, const lp_exec_opts *o, ExecPlan &plan, size_t 
     plan.P.nsteps = (int32_t)sg.second;
     plan.P.order = ps->dorder[ps->cur];
     plan.P.n_active = ps->dcount + ps->cur;
+    plan.P.t_start = ps->t0 + (double)sg.first * ps->dt;
+    plan.P.t_end = ps->t0 + (double)(sg.first + sg.second) * ps->dt;
     return LP_OK;
 }
 
@@ -898,7 +962,11 @@ extern "C" int pset_execute(lp_pset *ps, double runtime, double dt, double outpu
             HIPCHECK(hipEventCreate(&e1));
             HIPCHECK(hipEventRecord(e0, stream));
         }
-        HIPCHECK(lp::launch_advect(ps->fs->dtype, ps->fs->is3d, plan.P, ps->n_launch, stream));
+        if (plan.P.scheme == 2)
+            HIPCHECK(lp::launch_rkf45(ps->fs->dtype, ps->fs->is3d, plan.P, ps->n_launch, stream));
+        else
+            HIPCHECK(lp::launch_advect(ps->fs->dtype, ps->fs->is3d, plan.P, ps->n_launch,
+                                       stream));
         if (o->profile) {
             HIPCHECK(hipEventRecord(e1, stream));
             ps->prof.emplace_back(e0, e1);
@@ -978,6 +1046,8 @@ int execute_batch(lp_pset **ps, int32_t nruns, double runtime, double dt, double
                                    "and all steady or all time-varying (run %d differs)", r);
         if (opts[r].stencil_cache != opts[0].stencil_cache)
             return fail(LP_EINVAL, "batched runs share the stencil_cache setting");
+        if (opts[r].kernel == LP_KERNEL_RKF45)
+            return fail(LP_EINVAL, "the batched launch takes RK4 or Euler, not RKF45 (run %d)", r);
         for (int q = 0; q < r; ++q)
             if (ps[q] == ps[r])
                 return fail(LP_EINVAL, "particle set %d appears twice", r);
@@ -1271,8 +1341,8 @@ extern "C" int pset_status(lp_pset *ps, lp_counts *c, uint8_t *status)
     HIPCHECK(hipStreamSynchronize(ps->last_stream));
     std::vector<uint8_t> st((size_t)ps->n);
     HIPCHECK(hipMemcpy(st.data(), ps->dst, st.size(), hipMemcpyDeviceToHost));
-    unsigned long long steps = 0;
-    HIPCHECK(hipMemcpy(&steps, ps->dpsteps, sizeof steps, hipMemcpyDeviceToHost));
+    unsigned long long steps[2] = {0, 0};
+    HIPCHECK(hipMemcpy(steps, ps->dpsteps, sizeof steps, hipMemcpyDeviceToHost));
     lp_counts r{};
     r.n = ps->n;
     for (uint8_t s : st) {
@@ -1281,12 +1351,22 @@ extern "C" int pset_status(lp_pset *ps, lp_counts *c, uint8_t *status)
         if (s & LP_ST_LAND) r.land++;
         if (s & LP_ST_DELETED) r.deleted++;
     }
-    r.particle_steps = (int64_t)steps;
+    r.particle_steps = (int64_t)steps[0];
+    r.rejected_steps = (int64_t)steps[1];
     r.step = ps->step;
     r.time = ps->t0 + (double)ps->step * (ps->dt != 0.0 ? ps->dt : 0.0);
     *c = r;
     if (status)
         std::memcpy(status, st.data(), st.size());
+    return LP_OK;
+}
+
+extern "C" int pset_get_step_exponents(lp_pset *ps, int8_t *e)
+{
+    if (!ps || !e)
+        return fail(LP_EINVAL, "null argument");
+    HIPCHECK(hipStreamSynchronize(ps->last_stream));
+    HIPCHECK(hipMemcpy(e, ps->dexp, (size_t)ps->n, hipMemcpyDeviceToHost));
     return LP_OK;
 }
 
@@ -1391,7 +1471,8 @@ int lp_pset_reset_device(lp_pset *ps, int64_t n, const double *x, const double *
     HIPCHECK(hipMemsetAsync(ps->dst, 0, (size_t)ps->n, stream));
     if (n < ps->n)  // the unused tail is never advanced
         HIPCHECK(hipMemsetAsync(ps->dst + n, LP_ST_DELETED, (size_t)(ps->n - n), stream));
-    HIPCHECK(hipMemsetAsync(ps->dpsteps, 0, sizeof(unsigned long long), stream));
+    HIPCHECK(hipMemsetAsync(ps->dpsteps, 0, 2 * sizeof(unsigned long long), stream));
+    HIPCHECK(hipMemsetAsync(ps->dexp, 0, (size_t)ps->n, stream));
     HIPCHECK(lp::launch_iota(ps->dorder[0], (size_t)n, stream));
     HIPCHECK(lp::launch_fill_u32(ps->dcount, (uint32_t)n, 1, stream));
     ps->cur = 0;

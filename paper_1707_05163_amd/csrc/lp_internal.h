@@ -41,6 +41,12 @@ struct TimeEntry {
     int32_t sa, sb;          // slot indices
 };
 
+// One resident snapshot: its time and slot, in increasing time order.
+struct ResTime {
+    double t;
+    int32_t slot, pad;
+};
+
 struct FieldDev {
     const void *slots;       // capacity slots, each slot_bytes long
     size_t slot_bytes;
@@ -67,6 +73,16 @@ struct AdvectParams {
     const uint32_t *order;   // active ids, processing order
     const uint32_t *n_active;// device count of `order`
     unsigned long long *psteps;
+    // adaptive RKF45 (scheme 2): each lane brackets its own stage times
+    const ResTime *res;      // resident snapshots by time
+    int32_t nres;
+    int32_t emin, emax;      // step exponent range, step = |dt| 2^e
+    int32_t max_iter;        // attempts per particle and launch (a bound never reached)
+    double period;           // > 0: periodic snapshots
+    double t_start, t_end;   // the launch carries every particle from t_start to t_end
+    double tol;              // error tolerance per step, metres
+    int8_t *hexp;            // per-particle step exponents, id order
+    unsigned long long *prej;// attempts retried at half the step
 };
 
 struct RecordParams {
@@ -100,6 +116,8 @@ struct GemmArgs {
 // launchers (return hipError_t of the launch)
 hipError_t launch_advect(int store, bool is3d, const AdvectParams &p, uint32_t n_launch,
                          hipStream_t s);
+hipError_t launch_rkf45(int store, bool is3d, const AdvectParams &p, uint32_t n_launch,
+                        hipStream_t s);
 hipError_t launch_record(const RecordParams &p, hipStream_t s);
 hipError_t launch_advect_batch(int store, bool steady, bool spherical, const AdvectParams *runs,
                                const uint32_t *cstart, int nruns, uint32_t total,

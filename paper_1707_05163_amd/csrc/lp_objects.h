@@ -55,7 +55,10 @@ struct lp_pset {
     bool count_pending = false;
     uint32_t *dkeys = nullptr, *dhist = nullptr, *dblk = nullptr;
     uint32_t nbins = 0;
-    unsigned long long *dpsteps = nullptr;
+    unsigned long long *dpsteps = nullptr;  // [0] particle-steps, [1] RKF45 retries
+    int8_t *dexp = nullptr;                  // RKF45 step exponents
+    lp::ResTime *dres = nullptr;             // resident-snapshot table of RKF45 launches
+    size_t res_cap = 0;
     double t0 = 0.0, dt = 0.0;
     int64_t step = 0;
     // output records (record-major)
