@@ -38,6 +38,13 @@ STATE_BYTES_2D = 8 + 8 + 8 + 8 + 4 + 1 + 1  # lon, lat read + write, order id, s
 FLOPS_2D_STEP = 230
 FLOPS_3D_STEP = 567
 FLOPS_BROWNIAN = 9  # sqrt(2 Kh dt), two kicks, -2 ln u1 scaling, 2 pi u2 (transcendentals excluded)
+# One RKF45 attempt in 2D: six stages of 51 flops (as in RK4), 80 for the stage
+# positions (15 tableau terms x 2 flops x 2 coordinates + 5 x 4 for p + h s), 62
+# for the fourth-order and error combinations, the end point, the error length and
+# the six stage times; stencil bytes: six stages x 64 B.
+FLOPS_RKF45_ATTEMPT_2D = 448
+STENCIL_BYTES_RKF45_2D_F32 = 6 * 64
+STATE_BYTES_RKF45_2D = STATE_BYTES_2D + 2  # plus the step exponent read and written
 
 # HBM traffic of the dominant kernel, from two rocprofv3 --pmc passes (FETCH_SIZE,
 # then WRITE_SIZE, KiB per dispatch) over each mode's default workload.  FETCH_SIZE
@@ -70,7 +77,14 @@ def parse():
     p.add_argument("--train-iters", type=int, default=12_000)
     p.add_argument("--residual-m", default="50",
                    help="comma-separated residual thresholds in metres (cfg4)")
-    p.add_argument("--stencil-cache", type=int, default=1)
+    p.add_argument("--stencil-cache", type=int, default=None,
+                   help="1: register stencil cache kernels (default for RK4); 0: gather at "
+                        "every stage (default for RKF45, whose long steps leave the cell often)")
+    p.add_argument("--kernel", default="rk4", choices=["rk4", "rkf45"],
+                   help="cfg1: the integrator (rkf45: adaptive steps |dt| 2^e)")
+    p.add_argument("--rkf-tol", type=float, default=1e-3, help="RKF45 tolerance, m per step")
+    p.add_argument("--rkf-min-exp", type=int, default=-6)
+    p.add_argument("--rkf-max-exp", type=int, default=5)
     p.add_argument("--calibrate-copy", type=float, default=0.0,
                    help="first copy this many GB device-to-device (a plain copy kernel of "
                         "known size, to scale hardware byte counters)")
@@ -415,8 +429,44 @@ def main_cfg4(a):
     print(json.dumps(out), flush=True)
 
 
+def report_rkf45(a, w, el, psteps, retried, kms, launches, psets):
+    """Bench line of the adaptive RKF45 run on the cfg1 workload: accepted steps per
+    second, with the simulated particle-days per second beside it (the RK4 line's
+    1M particles x 30 days of the same workload)."""
+    avg_launch_s = kms / 1e3 / launches
+    attempts = psteps + retried
+    per_launch = attempts / launches
+    bytes_per_attempt = STENCIL_BYTES_RKF45_2D_F32 + STATE_BYTES_RKF45_2D * w.n / per_launch
+    roof, other = roofline(per_launch, avg_launch_s, bytes_per_attempt, FLOPS_RKF45_ATTEMPT_2D)
+    ex = np.concatenate([p.step_exponents() for p in psets])
+    days = w.nsteps * w.dt / 86400.0
+    out = {
+        "metric": "RKF45 accepted particle-steps/s", "value": psteps / el,
+        "unit": "particle-steps/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": el / a.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": w.name, "grid": f"{w.grid.nx}x{w.grid.ny}",
+                   "snapshots": w.fields.nt, "particles": w.n, "days": days,
+                   "base_dt_s": w.dt, "tol_m": a.rkf_tol, "exp_range": [a.rkf_min_exp,
+                                                                          a.rkf_max_exp],
+                   "stencil_cache": a.stencil_cache},
+        "roofline": roof, "roofline_other": other,
+        "kernel": {"name": "k_rkf45_2d" if a.stencil_cache else "k_rkf45",
+                   "launches": launches, "avg_launch_ms": round(avg_launch_s * 1e3, 4),
+                   "attempts_per_launch": per_launch,
+                   "kernel_share_of_step": round(kms / 1e3 / el, 4)},
+        "retried_fraction": retried / max(attempts, 1),
+        "particle_days_per_s": w.n * days * a.steps / el,
+        "final_step_exponents": {int(k): int(v) for k, v in
+                                 zip(*np.unique(ex, return_counts=True))},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
+    if a.stencil_cache is None:
+        a.stencil_cache = 0 if a.kernel == "rkf45" else 1
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": a.gpus}))
@@ -457,7 +507,8 @@ def main():
     def step(ps, profile):
         ps.execute(runtime, w.dt, w.outputdt, output_stride=a.output_stride,
                    sort_every=a.sort_every, profile=profile,
-                   stencil_cache=bool(a.stencil_cache), stream=stream)
+                   stencil_cache=bool(a.stencil_cache), kernel=a.kernel, tol=a.rkf_tol,
+                   min_exp=a.rkf_min_exp, max_exp=a.rkf_max_exp, stream=stream)
 
     for i in range(a.warmup):
         step(psets[i], False)
@@ -469,15 +520,19 @@ def main():
     el = time.perf_counter() - t0
 
     psteps = 0
+    retried = 0
     kms = 0.0
     launches = 0
     for ps in psets[a.warmup:]:
         c, _ = ps.status()
         psteps += c["particle_steps"]
+        retried += c["rejected_steps"]
         ms, k = ps.timing()
         kms += ms
         launches += k
     rate = psteps / el
+    if a.kernel == "rkf45":
+        return report_rkf45(a, w, el, psteps, retried, kms, launches, psets[a.warmup:])
     avg_launch_s = kms / 1e3 / launches
     steps_per_launch = psteps / launches
     S = w.outputdt / w.dt

@@ -161,7 +161,8 @@ typedef struct {
      * error at most rkf_tol / 32 raises e by one for the next step (up to the
      * maximum).  The last step of each output interval is cut short to land on
      * the output time and leaves e unchanged.  Needs Kh = 0; the batched launch
-     * and the autotuner do not take it; stencil_cache is ignored. */
+     * and the autotuner do not take it.  In 2D, stencil_cache = 1 runs the six
+     * stages on the register stencil cache (same results up to rounding). */
     double rkf_tol;       /* > 0, metres per step */
     int32_t rkf_min_exp;  /* in [-30, 0]; |dt| 2^min must still move the clock */
     int32_t rkf_max_exp;  /* in [0, 30] */

@@ -343,7 +343,40 @@ __global__ __launch_bounds__(kBlock) void k_advect(AdvectParams P)
 // times are its own: the bracketing snapshots of each stage time are found per
 // lane in the resident-snapshot table, with the same arithmetic as the host's
 // stage-time table (periodic fields first map t into [T0, T0 + period)).
-__device__ inline TimeEntry bracket_lane(const AdvectParams &P, double t)
+// fmod(a, P) for P > 0 (and |a / P| < 2^51), bit for bit: the remainder a - n P
+// with n = trunc(a / P) is exactly representable, so once the estimate of n from
+// a / P is corrected by at most one, the fused multiply-add returns it unrounded.
+__device__ inline double exact_fmod(double a, double P, double invP)
+{
+    double n = trunc(a * invP);
+    double r = fma(-n, P, a);
+    if (a >= 0.0) {
+        if (r < 0.0) {
+            n -= 1.0;
+            r = fma(-n, P, a);
+        } else if (r >= P) {
+            n += 1.0;
+            r = fma(-n, P, a);
+        }
+    } else {
+        if (r > 0.0) {
+            n += 1.0;
+            r = fma(-n, P, a);
+        } else if (r <= -P) {
+            n -= 1.0;
+            r = fma(-n, P, a);
+        }
+    }
+    return r;
+}
+
+// A lane's current bracket: the resident-table index lo and the times around it.
+struct LaneTime {
+    double t_lo, t_hi;
+    int32_t lo, sa, sb;
+};
+
+__device__ inline TimeEntry bracket_lane(const AdvectParams &P, double t, LaneTime &b)
 {
     const ResTime *r = P.res;
     const int m = P.nres;
@@ -353,13 +386,20 @@ __device__ inline TimeEntry bracket_lane(const AdvectParams &P, double t)
         e.sa = e.sb = r[0].slot;
         return e;
     }
-    if (P.period > 0.0) {
-        const double T0 = r[0].t;
-        double q = fmod(t - T0, P.period);
+    const bool periodic = P.period > 0.0;
+    double tp = t;
+    double T0 = 0.0;
+    if (periodic) {
+        T0 = r[0].t;
+        double q = exact_fmod(t - T0, P.period, P.inv_period);
         if (q < 0.0)
             q += P.period;
-        const double tp = T0 + q;
-        int lo = 0, hi = m - 1;  // largest k with r[k].t <= tp (r[0].t <= tp)
+        tp = T0 + q;
+    }
+    // fast path: still inside the lane's bracket (strictly below its upper end, so
+    // the index is the largest one at or below tp, as in the host's search)
+    if (!(b.lo >= 0 && tp >= b.t_lo && tp < b.t_hi)) {
+        int lo = 0, hi = periodic ? m - 1 : m - 2;  // the host checked [t_start, t_end]
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
             if (r[mid].t <= tp)
@@ -367,23 +407,20 @@ __device__ inline TimeEntry bracket_lane(const AdvectParams &P, double t)
             else
                 hi = mid - 1;
         }
-        const double tn = lo + 1 < m ? r[lo + 1].t : T0 + P.period;
-        e.sa = r[lo].slot;
-        e.sb = lo + 1 < m ? r[lo + 1].slot : r[0].slot;
-        e.tau = (tp - r[lo].t) / (tn - r[lo].t);
-        return e;
+        b.lo = lo;
+        b.t_lo = r[lo].t;
+        b.sa = r[lo].slot;
+        if (lo + 1 < m) {
+            b.t_hi = r[lo + 1].t;
+            b.sb = r[lo + 1].slot;
+        } else {  // periodic wrap: the first snapshot again, one period later
+            b.t_hi = T0 + P.period;
+            b.sb = r[0].slot;
+        }
     }
-    int lo = 0, hi = m - 2;  // largest k <= m-2 with r[k].t <= t (the host checked
-    while (lo < hi) {        // that [t_start, t_end] lies inside the table)
-        const int mid = (lo + hi + 1) >> 1;
-        if (r[mid].t <= t)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    e.sa = r[lo].slot;
-    e.sb = r[lo + 1].slot;
-    e.tau = (t - r[lo].t) / (r[lo + 1].t - r[lo].t);
+    e.sa = b.sa;
+    e.sb = b.sb;
+    e.tau = (tp - b.t_lo) / (b.t_hi - b.t_lo);
     return e;
 }
 
@@ -408,7 +445,8 @@ struct Fehlberg {
 // error estimate ev (fifth minus fourth order); false if a stage leaves the grid.
 template <int ST, bool IS3D, bool STEADY>
 __device__ inline bool rkf45_attempt(const AdvectParams &P, double t, double h,
-                                     const double p[3], double p4[3], double ev[3])
+                                     const double p[3], double p4[3], double ev[3],
+                                     LaneTime &lt)
 {
     double k[6][3];
 #pragma unroll
@@ -422,7 +460,7 @@ __device__ inline bool rkf45_attempt(const AdvectParams &P, double t, double h,
                 s = s + Fehlberg::a[i][j] * k[j][d];
             q[d] = p[d] + h * s;
         }
-        const TimeEntry te = bracket_lane(P, t + Fehlberg::c[i] * h);
+        const TimeEntry te = bracket_lane(P, t + Fehlberg::c[i] * h, lt);
         if (!sample<ST, IS3D, STEADY>(P, te, q[0], q[1], q[2], k[i]))
             return false;
     }
@@ -444,96 +482,118 @@ __device__ inline bool rkf45_attempt(const AdvectParams &P, double t, double h,
     return true;
 }
 
-template <int ST, bool IS3D, bool STEADY>
-__global__ __launch_bounds__(kBlock) void k_rkf45(AdvectParams P)
+// The step control shared by both RKF45 lanes: an attempt whose error length is
+// above tol is retried at e - 1 (unless e is at its floor); an accepted one that
+// passes the end-point checks moves the lane's time on and, if it was a full step
+// with error at most tol / 32, raises e for the next one.
+struct RkfState {
+    double t;
+    int32_t e, it;
+    uint32_t id;
+    uint8_t st;
+};
+
+__device__ inline bool rkf_accept(const AdvectParams &P, RkfState &s, double err,
+                                  long long &acc, long long &rej)
 {
-    const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
-    const uint32_t k = blk * kBlock + threadIdx.x;
-    const uint32_t nact = *P.n_active;
-    long long acc = 0, rej = 0;
-    if (k < nact) {
-        const uint32_t id = P.order[k];
-        uint8_t st = P.status[id];
-        if (st == 0) {
-            const uint8_t extra = P.policy == 0 ? ST_DELETED : 0;
-            double p[3] = {P.x[id], P.y[id], IS3D ? P.z[id] : 0.0};
-            int e = P.hexp[id];
-            const double sg = P.dt > 0.0 ? 1.0 : -1.0, adt = fabs(P.dt);
-            const double te = P.t_end;
-            double t = P.t_start;
-            // every attempt either lowers e (at most e - emin times in a row) or moves
-            // t by at least the floor step, so max_iter is never reached
-            for (int it = 0; t != te; ++it) {
-                if (it >= P.max_iter) {
-                    st = (uint8_t)(ST_OOB | extra);
-                    break;
-                }
-                const double h = ldexp(adt, e);
-                const double rem = sg > 0.0 ? te - t : t - te;
-                const bool cut = h >= rem;
-                const double hs = sg * (cut ? rem : h);
-                double p4[3], ev[3];
-                if (!rkf45_attempt<ST, IS3D, STEADY>(P, t, hs, p, p4, ev)) {
-                    ++acc;
-                    st = (uint8_t)(ST_OOB | extra);
-                    break;
-                }
-                double ex = ev[0], ey = ev[1];
-                if (P.g.spherical) {
-                    ex = ex * (kMetresPerDegree * cos(p[1] * kDegToRad));
-                    ey = ey * kMetresPerDegree;
-                }
-                const double err = sqrt((ex * ex + ey * ey) + ev[2] * ev[2]);
-                if (err > P.tol && e > P.emin) {
-                    --e;
-                    ++rej;
-                    continue;
-                }
-                ++acc;
-                int ci, cj, ck;
-                double f;
-                if (!locate(P.g.ax, p4[0], ci, f) || !locate(P.g.ay, p4[1], cj, f)) {
-                    st = (uint8_t)(ST_OOB | extra);
-                    break;
-                }
-                if constexpr (IS3D) {
-                    if (!locate(P.g.az, p4[2], ck, f)) {
-                        st = (uint8_t)(ST_OOB | extra);
-                        break;
-                    }
-                }
-                if (P.g.landcell &&
-                    P.g.landcell[(size_t)cj * (size_t)(P.g.ax.n - 1) + (size_t)ci]) {
-                    st = (uint8_t)(ST_LAND | extra);
-                    break;
-                }
-                p[0] = p4[0];
-                p[1] = p4[1];
-                p[2] = p4[2];
-                t = cut ? te : t + hs;
-                if (!cut && err <= P.tol * 0.03125 && e < P.emax)
-                    ++e;
-            }
-            P.x[id] = p[0];
-            P.y[id] = p[1];
-            if constexpr (IS3D)
-                P.z[id] = p[2];
-            P.hexp[id] = (int8_t)e;
-            if (st)
-                P.status[id] = st;
-        }
+    if (err > P.tol && s.e > P.emin) {
+        --s.e;
+        ++rej;
+        return false;
     }
-    for (int off = 32; off > 0; off >>= 1) {
-        acc += __shfl_xor(acc, off, 64);
-        rej += __shfl_xor(rej, off, 64);
-    }
-    if ((threadIdx.x & 63) == 0) {
-        if (acc)
-            atomicAdd(P.psteps, (unsigned long long)acc);
-        if (rej)
-            atomicAdd(P.prej, (unsigned long long)rej);
-    }
+    ++acc;
+    return true;
 }
+
+__device__ inline void rkf_commit(const AdvectParams &P, RkfState &s, double err, bool cut,
+                                  double hs)
+{
+    s.t = cut ? P.t_end : s.t + hs;
+    if (!cut && err <= P.tol * 0.03125 && s.e < P.emax)
+        ++s.e;
+}
+
+// One particle's state for the gather form (2D or 3D): every stage gathers its
+// stencil from the snapshots.
+template <int ST, bool IS3D, bool STEADY>
+struct GatherLane {
+    RkfState s;
+    double p[3];
+    LaneTime lt;
+
+    __device__ void begin(const AdvectParams &P, uint32_t id)
+    {
+        s.id = id;
+        s.st = 0;
+        s.t = P.t_start;
+        s.e = P.hexp[id];
+        s.it = 0;
+        p[0] = P.x[id];
+        p[1] = P.y[id];
+        p[2] = IS3D ? P.z[id] : 0.0;
+        lt.lo = -1;
+    }
+
+    // one attempt; true when the particle is done for this launch
+    __device__ bool attempt(const AdvectParams &P, long long &acc, long long &rej)
+    {
+        const uint8_t extra = P.policy == 0 ? ST_DELETED : 0;
+        if (s.t == P.t_end)
+            return true;
+        if (s.it++ >= P.max_iter) {  // never reached: see max_iter
+            s.st = (uint8_t)(ST_OOB | extra);
+            return true;
+        }
+        const double sg = P.dt > 0.0 ? 1.0 : -1.0;
+        const double h = ldexp(fabs(P.dt), s.e);
+        const double rem = sg > 0.0 ? P.t_end - s.t : s.t - P.t_end;
+        const bool cut = h >= rem;
+        const double hs = sg * (cut ? rem : h);
+        double p4[3], ev[3];
+        if (!rkf45_attempt<ST, IS3D, STEADY>(P, s.t, hs, p, p4, ev, lt)) {
+            ++acc;
+            s.st = (uint8_t)(ST_OOB | extra);
+            return true;
+        }
+        double ex = ev[0], ey = ev[1];
+        if (P.g.spherical) {
+            ex = ex * (kMetresPerDegree * cos(p[1] * kDegToRad));
+            ey = ey * kMetresPerDegree;
+        }
+        const double err = sqrt((ex * ex + ey * ey) + ev[2] * ev[2]);
+        if (!rkf_accept(P, s, err, acc, rej))
+            return false;
+        int ci, cj, ck;
+        double f;
+        bool out = !locate(P.g.ax, p4[0], ci, f) || !locate(P.g.ay, p4[1], cj, f);
+        if constexpr (IS3D)
+            out = out || !locate(P.g.az, p4[2], ck, f);
+        if (out) {
+            s.st = (uint8_t)(ST_OOB | extra);
+            return true;
+        }
+        if (P.g.landcell && P.g.landcell[(size_t)cj * (size_t)(P.g.ax.n - 1) + (size_t)ci]) {
+            s.st = (uint8_t)(ST_LAND | extra);
+            return true;
+        }
+        p[0] = p4[0];
+        p[1] = p4[1];
+        p[2] = p4[2];
+        rkf_commit(P, s, err, cut, hs);
+        return s.t == P.t_end;
+    }
+
+    __device__ void finish(const AdvectParams &P)
+    {
+        P.x[s.id] = p[0];
+        P.y[s.id] = p[1];
+        if constexpr (IS3D)
+            P.z[s.id] = p[2];
+        P.hexp[s.id] = (int8_t)s.e;
+        if (s.st)
+            P.status[s.id] = s.st;
+    }
+};
 
 // ---------------------------------------------------------------- 2D with a stencil cache
 // Each lane keeps the stencil of the cell it is in, as the coefficients of the
@@ -806,6 +866,215 @@ __global__ __launch_bounds__(kBlock) void k_advect2d(AdvectParams P)
 // ranges, one per XCD, each with its own atomic counter.  A block takes items from
 // the range of the XCD it runs on and, when that is exhausted, from the others;
 // every block leaves once all 8 ranges are exhausted, so the grid always drains.
+// ---------------------------------------------------------------- 2D RKF45 with the cache
+// The adaptive scheme on the register stencil cache: each of the six Fehlberg
+// stages is a stage2() evaluation (the cached bilinear polynomials, reloaded when
+// the stage point leaves the cell or the lane's time bracket moves on).  The stage
+// loop is not unrolled; the tableau rows come from constant memory and the earlier
+// slopes sit in five named registers, so nothing is indexed dynamically.
+__constant__ double kRkfC[6] = {0.0, 1.0 / 4.0, 3.0 / 8.0, 12.0 / 13.0, 1.0, 1.0 / 2.0};
+__constant__ double kRkfA[6][5] = {
+    {0.0, 0.0, 0.0, 0.0, 0.0},
+    {1.0 / 4.0, 0.0, 0.0, 0.0, 0.0},
+    {3.0 / 32.0, 9.0 / 32.0, 0.0, 0.0, 0.0},
+    {1932.0 / 2197.0, -7200.0 / 2197.0, 7296.0 / 2197.0, 0.0, 0.0},
+    {439.0 / 216.0, -8.0, 3680.0 / 513.0, -845.0 / 4104.0, 0.0},
+    {-8.0 / 27.0, 2.0, -3544.0 / 2565.0, 1859.0 / 4104.0, -11.0 / 40.0}};
+__constant__ double kRkfB4[6] = {25.0 / 216.0, 0.0, 1408.0 / 2565.0, 2197.0 / 4104.0,
+                                 -1.0 / 5.0, 0.0};
+__constant__ double kRkfE[6] = {16.0 / 135.0 - 25.0 / 216.0, 0.0,
+                                6656.0 / 12825.0 - 1408.0 / 2565.0,
+                                28561.0 / 56430.0 - 2197.0 / 4104.0, -9.0 / 50.0 + 1.0 / 5.0,
+                                2.0 / 55.0};
+
+template <int ST, bool STEADY, bool SPH>
+struct CachedLane2 {
+    using R = typename Real<ST>::T;
+    RkfState s;
+    double x, y;
+    Cell2<R> c;
+    int32_t csa, csb;
+    LaneTime lt;
+
+    __device__ void begin(const AdvectParams &P, uint32_t id)
+    {
+        s.id = id;
+        s.st = 0;
+        s.t = P.t_start;
+        s.e = P.hexp[id];
+        s.it = 0;
+        x = P.x[id];
+        y = P.y[id];
+        c.valid = false;
+        csa = csb = -1;
+        lt.lo = -1;
+    }
+
+    __device__ bool attempt(const AdvectParams &P, long long &acc, long long &rej)
+    {
+        const uint8_t extra = P.policy == 0 ? ST_DELETED : 0;
+        if (s.t == P.t_end)
+            return true;
+        if (s.it++ >= P.max_iter) {  // never reached: see max_iter
+            s.st = (uint8_t)(ST_OOB | extra);
+            return true;
+        }
+        const double sg = P.dt > 0.0 ? 1.0 : -1.0;
+        const double h = ldexp(fabs(P.dt), s.e);
+        const double rem = sg > 0.0 ? P.t_end - s.t : s.t - P.t_end;
+        const bool cut = h >= rem;
+        const double hs = sg * (cut ? rem : h);
+        double k0x = 0.0, k0y = 0.0, k1x = 0.0, k1y = 0.0, k2x = 0.0, k2y = 0.0;
+        double k3x = 0.0, k3y = 0.0, k4x = 0.0, k4y = 0.0;
+        double s4x = 0.0, s4y = 0.0, sex = 0.0, sey = 0.0;
+#pragma nounroll
+        for (int q = 0; q < 6; ++q) {
+            const double *a = kRkfA[q];
+            const double ax = (((a[0] * k0x + a[1] * k1x) + a[2] * k2x) + a[3] * k3x) + a[4] * k4x;
+            const double ay = (((a[0] * k0y + a[1] * k1y) + a[2] * k2y) + a[3] * k3y) + a[4] * k4y;
+            const TimeEntry ent = bracket_lane(P, s.t + kRkfC[q] * hs, lt);
+            if (ent.sa != csa || ent.sb != csb) {
+                c.valid = false;
+                csa = ent.sa;
+                csb = ent.sb;
+            }
+            double kx, ky;
+            if (!stage2<ST, STEADY, SPH>(P, c, ent, x + hs * ax, y + hs * ay, kx, ky)) {
+                ++acc;
+                s.st = (uint8_t)(ST_OOB | extra);
+                return true;
+            }
+            s4x = s4x + kRkfB4[q] * kx;
+            s4y = s4y + kRkfB4[q] * ky;
+            sex = sex + kRkfE[q] * kx;
+            sey = sey + kRkfE[q] * ky;
+            switch (q) {
+            case 0: k0x = kx; k0y = ky; break;
+            case 1: k1x = kx; k1y = ky; break;
+            case 2: k2x = kx; k2y = ky; break;
+            case 3: k3x = kx; k3y = ky; break;
+            case 4: k4x = kx; k4y = ky; break;
+            default: break;
+            }
+        }
+        double ex = hs * sex, ey = hs * sey;
+        if constexpr (SPH) {
+            ex = ex * (kMetresPerDegree * cos(y * kDegToRad));
+            ey = ey * kMetresPerDegree;
+        }
+        const double err = sqrt(ex * ex + ey * ey);
+        if (!rkf_accept(P, s, err, acc, rej))
+            return false;
+        const double xs = x + hs * s4x, ys = y + hs * s4y;
+        bool land;
+        if (in_cell(c, P, xs, ys)) {
+            land = c.land;
+        } else {
+            int ci, cj;
+            double f;
+            if (!locate(P.g.ax, xs, ci, f) || !locate(P.g.ay, ys, cj, f)) {
+                s.st = (uint8_t)(ST_OOB | extra);
+                return true;
+            }
+            land = P.g.landcell && P.g.landcell[(size_t)cj * (size_t)(P.g.ax.n - 1) + (size_t)ci];
+        }
+        if (land) {
+            s.st = (uint8_t)(ST_LAND | extra);
+            return true;
+        }
+        x = xs;
+        y = ys;
+        rkf_commit(P, s, err, cut, hs);
+        return s.t == P.t_end;
+    }
+
+    __device__ void finish(const AdvectParams &P)
+    {
+        P.x[s.id] = x;
+        P.y[s.id] = y;
+        P.hexp[s.id] = (int8_t)s.e;
+        if (s.st)
+            P.status[s.id] = s.st;
+    }
+};
+
+// Persistent RKF45 launch with lane refill.  Particles need different numbers of
+// attempts, so a wave that kept its 64 particles to the end would run as long as
+// its slowest one.  Here a lane that is done takes the next particle instead: once
+// a quarter of the wave is idle (or all of it), one lane reserves that many entries
+// of the processing order with an atomic add on its XCD's queue (the order is cut
+// into eight contiguous ranges, one per XCD, so neighbouring particles stay on one
+// L2) and the idle lanes take them by rank.  A drained queue sends the wave on to
+// the next XCD's range; the wave ends when every queue is drained and every lane is
+// idle.  Each particle's arithmetic is the same as in a one-particle-per-lane launch.
+template <class Lane>
+__device__ inline void rkf45_refill(const AdvectParams &P)
+{
+    uint32_t *queues = P.queues;
+    const uint32_t nact = *P.n_active;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t home = blockIdx.x & 7u;
+    uint32_t qtry = 0;
+    bool busy = false;
+    long long acc = 0, rej = 0;
+    Lane L;
+    for (;;) {
+        const uint64_t idle = __ballot(!busy);
+        const uint32_t nidle = (uint32_t)__popcll(idle);
+        if (qtry < 8 && (nidle >= 16 || nidle == 64)) {
+            const uint32_t x = (home + qtry) & 7u;
+            const uint32_t lo = (uint32_t)(((uint64_t)nact * x) >> 3);
+            const uint32_t hi = (uint32_t)(((uint64_t)nact * (x + 1)) >> 3);
+            uint32_t t = 0;
+            if (lane == 0)
+                t = lo < hi ? atomicAdd(&queues[x], nidle) : 0u;
+            t = __shfl(t, 0, 64);
+            const uint32_t start = lo + t;
+            const uint32_t avail = (lo < hi && start < hi) ? min(nidle, hi - start) : 0u;
+            if (avail < nidle)
+                ++qtry;
+            if (!busy) {
+                const uint32_t rank = (uint32_t)__popcll(idle & ((1ull << lane) - 1ull));
+                if (rank < avail) {
+                    L.begin(P, P.order[start + rank]);
+                    busy = true;
+                }
+            }
+        }
+        if (__ballot(busy) == 0) {
+            if (qtry >= 8)
+                break;
+            continue;
+        }
+        if (busy && L.attempt(P, acc, rej)) {
+            L.finish(P);
+            busy = false;
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        acc += __shfl_xor(acc, off, 64);
+        rej += __shfl_xor(rej, off, 64);
+    }
+    if (lane == 0) {
+        if (acc)
+            atomicAdd(P.psteps, (unsigned long long)acc);
+        if (rej)
+            atomicAdd(P.prej, (unsigned long long)rej);
+    }
+}
+
+template <int ST, bool IS3D, bool STEADY>
+__global__ __launch_bounds__(kBlock) void k_rkf45(AdvectParams P)
+{
+    rkf45_refill<GatherLane<ST, IS3D, STEADY>>(P);
+}
+
+template <int ST, bool STEADY, bool SPH>
+__global__ __launch_bounds__(kBlock) void k_rkf45_2d(AdvectParams P)
+{
+    rkf45_refill<CachedLane2<ST, STEADY, SPH>>(P);
+}
+
 template <int ST, bool STEADY, bool SPH>
 __global__ __launch_bounds__(512) void k_advect2d_batch(const AdvectParams *runs,
                                                         const uint32_t *cstart, int nruns,
@@ -1268,17 +1537,43 @@ hipError_t launch_advect(int store, bool is3d, const AdvectParams &p, uint32_t n
 
 namespace {
 
+// Persistent grid: as many blocks as fit on the device at once (no more than the
+// particles need); the eight queues are cleared on the stream first.
+template <class K>
+hipError_t launch_persistent(K kern, const AdvectParams &p, uint32_t n_launch, hipStream_t s)
+{
+    int per_cu = 0, cus = 0, dev = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlock, 0);
+    if (e != hipSuccess)
+        return e;
+    if ((e = hipGetDevice(&dev)) != hipSuccess ||
+        (e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+        return e;
+    uint32_t grid = (uint32_t)(per_cu > 0 ? per_cu : 1) * (uint32_t)(cus > 0 ? cus : 1);
+    const uint32_t need = (n_launch + kBlock - 1) / kBlock;
+    grid = grid < need ? grid : need;
+    if ((e = launch_fill_u32(p.queues, 0u, 8, s)) != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, p);
+    return hipGetLastError();
+}
+
 template <int ST, bool IS3D>
 hipError_t rkf3(const AdvectParams &p, bool steady, uint32_t n_launch, hipStream_t s)
 {
-    const uint32_t blocks = (n_launch + kBlock - 1) / kBlock;
-    if (blocks == 0)
+    if (n_launch == 0)
         return hipSuccess;
-    if (steady)
-        hipLaunchKernelGGL((k_rkf45<ST, IS3D, true>), dim3(blocks), dim3(kBlock), 0, s, p);
-    else
-        hipLaunchKernelGGL((k_rkf45<ST, IS3D, false>), dim3(blocks), dim3(kBlock), 0, s, p);
-    return hipGetLastError();
+    if constexpr (!IS3D) {
+        if (p.cache) {
+            if (p.g.spherical)
+                return steady ? launch_persistent(k_rkf45_2d<ST, true, true>, p, n_launch, s)
+                              : launch_persistent(k_rkf45_2d<ST, false, true>, p, n_launch, s);
+            return steady ? launch_persistent(k_rkf45_2d<ST, true, false>, p, n_launch, s)
+                          : launch_persistent(k_rkf45_2d<ST, false, false>, p, n_launch, s);
+        }
+    }
+    return steady ? launch_persistent(k_rkf45<ST, IS3D, true>, p, n_launch, s)
+                  : launch_persistent(k_rkf45<ST, IS3D, false>, p, n_launch, s);
 }
 
 }  // namespace
@@ -1288,7 +1583,7 @@ hipError_t launch_rkf45(int store, bool is3d, const AdvectParams &p, uint32_t n_
 {
     const bool steady = p.f.steady != 0;
     if (!p.res || p.nres < 1 || (!steady && p.period <= 0.0 && p.nres < 2) || !p.hexp ||
-        !p.prej)
+        !p.prej || !p.queues)
         return hipErrorInvalidValue;
     switch (store) {
     case kF64: return is3d ? rkf3<kF64, true>(p, steady, n_launch, s)

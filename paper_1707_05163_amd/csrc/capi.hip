@@ -515,6 +515,7 @@ extern "C" void pset_destroy(lp_pset *ps)
     dfree(ps->dblk);
     dfree(ps->dpsteps);
     dfree(ps->dexp);
+    dfree(ps->dqueues);
     dfree(ps->dres);
     dfree(ps->rx);
     dfree(ps->ry);
@@ -567,7 +568,7 @@ static int pset_create_common(lp_fieldset *fs, int64_t n, const double *lon, con
         (fs->is3d && (rc = dalloc(&ps->dz, N))) || (rc = dalloc(&ps->dst, N)) ||
         (rc = dalloc(&ps->dorder[0], N)) || (rc = dalloc(&ps->dorder[1], N)) ||
         (rc = dalloc(&ps->dcount, 2)) || (rc = dalloc(&ps->dpsteps, 2)) ||
-        (rc = dalloc(&ps->dexp, N)))
+        (rc = dalloc(&ps->dexp, N)) || (rc = dalloc(&ps->dqueues, 8)))
         return bail(rc);
     ps->nbins = lp::sort_bins(fs->g);
     if ((rc = dalloc(&ps->dkeys, N)) || (rc = dalloc(&ps->dhist, ps->nbins)) ||
@@ -870,10 +871,12 @@ int exec_prepare(lp_pset *ps, double runtime, double dt, double outputdt, const 
     P.psteps = ps->dpsteps;
     P.prej = ps->dpsteps + 1;
     P.hexp = ps->dexp;
+    P.queues = ps->dqueues;
     if (rkf) {
         P.res = ps->dres;
         P.nres = (int32_t)res.size();
         P.period = fs->period;
+        P.inv_period = fs->period > 0.0 ? 1.0 / fs->period : 0.0;
         P.tol = o->rkf_tol;
         P.emin = o->rkf_min_exp;
         P.emax = o->rkf_max_exp;

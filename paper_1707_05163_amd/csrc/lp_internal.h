@@ -79,9 +79,11 @@ struct AdvectParams {
     int32_t emin, emax;      // step exponent range, step = |dt| 2^e
     int32_t max_iter;        // attempts per particle and launch (a bound never reached)
     double period;           // > 0: periodic snapshots
+    double inv_period;       // 1 / period (a quotient estimate only)
     double t_start, t_end;   // the launch carries every particle from t_start to t_end
     double tol;              // error tolerance per step, metres
     int8_t *hexp;            // per-particle step exponents, id order
+    uint32_t *queues;        // 8 work-queue counters of the persistent launch
     unsigned long long *prej;// attempts retried at half the step
 };
 

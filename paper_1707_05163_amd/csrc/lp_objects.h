@@ -57,6 +57,7 @@ struct lp_pset {
     uint32_t nbins = 0;
     unsigned long long *dpsteps = nullptr;  // [0] particle-steps, [1] RKF45 retries
     int8_t *dexp = nullptr;                  // RKF45 step exponents
+    uint32_t *dqueues = nullptr;             // RKF45 work queues (8)
     lp::ResTime *dres = nullptr;             // resident-snapshot table of RKF45 launches
     size_t res_cap = 0;
     double t0 = 0.0, dt = 0.0;

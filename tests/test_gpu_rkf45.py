@@ -22,12 +22,13 @@ def _check_exps(ps, st, exempt_ok=0):
     assert bad.size <= exempt_ok, bad[:10]
 
 
-def _run(w, dt, runtime, outputdt, tol, emin, emax, t0=0.0, dtype="f32", fs=None, ofs=None):
+def _run(w, dt, runtime, outputdt, tol, emin, emax, t0=0.0, dtype="f32", fs=None, ofs=None,
+         cache=True):
     from paper_1707_05163_amd import FieldSet, ParticleSet
     fs = fs or FieldSet.from_workload(w, dtype=dtype)
     ps = ParticleSet(fs, w.lon0, w.lat0, w.depth0, t0=t0)
     ps.execute(runtime, dt, outputdt, output_stride=1, kernel="rkf45", tol=tol, min_exp=emin,
-               max_exp=emax)
+               max_exp=emax, stencil_cache=cache)
     ofs = ofs or O.OracleFieldSet.from_workload(w)
     st = O.make_state(w.lon0, w.lat0, w.depth0, t_org=t0)
     orecs = O.run(ofs, st, dt, runtime, outputdt, scheme=O.SCHEME_RKF45, tol=tol, emin=emin,
@@ -50,25 +51,28 @@ def _compare(ps, recs, orecs, ofs, st, w, extent, label):
     return c
 
 
+@pytest.mark.parametrize("cache", [True, False])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_rkf45_cfg0_rotation(dtype):
+def test_rkf45_cfg0_rotation(dtype, cache):
     w = SC.cfg0_solid_body(n_particles=3000, nsteps=1440)
     if dtype == "f32":  # both sides read the same float32 values
         w.fields.U = w.fields.U.astype(np.float32)
         w.fields.V = w.fields.V.astype(np.float32)
-    log(f"rkf45 cfg0 {dtype}")
+    log(f"rkf45 cfg0 {dtype} cache={cache}")
     ps, recs, orecs, ofs, st = _run(w, w.dt, w.nsteps * w.dt, 14400.0, 1e-6, -4, 6,
-                                    dtype=dtype)
+                                    dtype=dtype, cache=cache)
     _compare(ps, recs, orecs, ofs, st, w, 1e5, "cfg0")
 
 
-@pytest.mark.parametrize("tol,emin,emax", [(1e-8, -5, 3), (1e-3, -6, 5)])
-def test_rkf45_cfg1_small(tol, emin, emax):
+@pytest.mark.parametrize("tol,emin,emax,cache", [(1e-8, -5, 3, True), (1e-8, -5, 3, False),
+                                                (1e-3, -6, 5, True)])
+def test_rkf45_cfg1_small(tol, emin, emax, cache):
     """Periodic snapshots, spherical mesh, land: retries, growth and the floor all
     occur at the tighter tolerance."""
     w = SC.cfg1_global_eddies(nx=144, ny=72, nt=30, n_particles=5000, nsteps=288)
-    log(f"rkf45 cfg1 small tol {tol}")
-    ps, recs, orecs, ofs, st = _run(w, 7200.0, 4 * 86400.0, 86400.0, tol, emin, emax)
+    log(f"rkf45 cfg1 small tol {tol} cache={cache}")
+    ps, recs, orecs, ofs, st = _run(w, 7200.0, 4 * 86400.0, 86400.0, tol, emin, emax,
+                                    cache=cache)
     c = _compare(ps, recs, orecs, ofs, st, w, 360.0, "cfg1")
     if tol < 1e-6:
         assert c["rejected_steps"] > 0
