@@ -190,8 +190,9 @@ typedef struct {
 /* Run many independent particle sets (each with its own field set: grid size,
  * snapshots and particle count may all differ) through one persistent launch per
  * output segment.  Same result per set as calling pset_execute on each with its
- * own opts[r] (which must agree on stencil_cache); the field sets must all be 2D
- * with one storage type, one mesh kind, and all steady or all time-varying.  The
+ * own opts[r] (which must agree on stencil_cache, use RK4 or Euler and linear
+ * interpolation); the field sets must all be 2D with one storage type, one mesh
+ * kind, and all steady or all time-varying.  The
  * active particles of all sets are cut into chunks of `block` (64, 128, 256 or
  * 512; 0 = 256) particles, handed out through per-XCD atomic work queues. */
 int pset_execute_batch(lp_pset **ps, int32_t nruns, double runtime, double dt, double outputdt,

@@ -605,7 +605,9 @@ struct GatherLane {
 // f_a) is the same linear time interpolation (Sect. 2.4); only rounding differs.
 template <class R>
 struct Cell2 {
-    double x0, ux, y0, uy;  // lower faces; exclusive upper faces (+inf for the last cell)
+    double x0, ux, y0, uy;  // lower faces; exclusive upper faces (for the last cell the
+                            // next double above the last node, so the domain's closed
+                            // upper end needs no separate test)
     double rx, ry;          // inverse cell widths
     double cl, sl;          // cos and sin of the lower latitude face
     R a[2][4];              // earlier snapshot: U, V coefficients
@@ -640,10 +642,10 @@ __device__ inline bool reload2(const AdvectParams &P, Cell2<typename Real<ST>::T
         return false;
     const AxisDev &ax = P.g.ax, &ay = P.g.ay;
     c.x0 = ax.c[i];
-    c.ux = (i == ax.n - 2) ? __builtin_inf() : ax.c[i + 1];
+    c.ux = (i == ax.n - 2) ? nextafter(ax.hi, __builtin_inf()) : ax.c[i + 1];
     c.rx = ax.rw[i];
     c.y0 = ay.c[j];
-    c.uy = (j == ay.n - 2) ? __builtin_inf() : ay.c[j + 1];
+    c.uy = (j == ay.n - 2) ? nextafter(ay.hi, __builtin_inf()) : ay.c[j + 1];
     c.ry = ay.rw[j];
     if (P.g.coslat) {
         c.cl = P.g.coslat[j];
@@ -689,8 +691,7 @@ __device__ inline bool reload2(const AdvectParams &P, Cell2<typename Real<ST>::T
 template <class R>
 __device__ inline bool in_cell(const Cell2<R> &c, const AdvectParams &P, double x, double y)
 {
-    return c.valid && x >= c.x0 && x < c.ux && x <= P.g.ax.hi && y >= c.y0 && y < c.uy &&
-           y <= P.g.ay.hi;
+    return c.valid && x >= c.x0 && x < c.ux && y >= c.y0 && y < c.uy;
 }
 
 // 1 / d to within an ulp or two: hardware reciprocal refined by two Newton steps
@@ -703,19 +704,34 @@ __device__ inline double recip(double d)
 }
 
 // cos of a latitude inside the cached cell: cos(l0 + dl) = cos l0 cos dl - sin l0 sin dl
-// with dl = lat - l0 (at most 5 degrees) and cos dl, sin dl by their Taylor series to
-// order dl^8 / dl^9 (truncation below 1e-17).
+// with dl = lat - l0 and cos dl, sin dl by their Taylor series, cut after 2, 3 or 4
+// terms so that the truncation stays below a quarter ulp for the grid's tallest cell
+// (0.3, 1.5 or 5 degrees).
+__device__ inline double cos_series(double cl, double sl, double y0, double y, int terms)
+{
+    const double dl = (y - y0) * kDegToRad, d2 = dl * dl;
+    double cd, sd;
+    if (terms <= 2) {
+        cd = fma(d2, fma(d2, 1.0 / 24.0, -0.5), 1.0);
+        sd = dl * fma(d2, fma(d2, 1.0 / 120.0, -1.0 / 6.0), 1.0);
+    } else if (terms == 3) {
+        cd = fma(d2, fma(d2, fma(d2, -1.0 / 720.0, 1.0 / 24.0), -0.5), 1.0);
+        sd = dl * fma(d2, fma(d2, fma(d2, -1.0 / 5040.0, 1.0 / 120.0), -1.0 / 6.0), 1.0);
+    } else {
+        cd = fma(d2, fma(d2, fma(d2, fma(d2, 1.0 / 40320.0, -1.0 / 720.0), 1.0 / 24.0), -0.5),
+                 1.0);
+        sd = dl * fma(d2, fma(d2, fma(d2, fma(d2, 1.0 / 362880.0, -1.0 / 5040.0), 1.0 / 120.0),
+                              -1.0 / 6.0), 1.0);
+    }
+    return cl * cd - sl * sd;
+}
+
 template <class R>
 __device__ inline double cos_lat(const Cell2<R> &c, const AdvectParams &P, double y)
 {
     if (!P.g.coslat)
         return cos(y * kDegToRad);
-    const double dl = (y - c.y0) * kDegToRad, d2 = dl * dl;
-    const double cd = fma(d2, fma(d2, fma(d2, fma(d2, 1.0 / 40320.0, -1.0 / 720.0), 1.0 / 24.0),
-                                  -0.5), 1.0);
-    const double sd = dl * fma(d2, fma(d2, fma(d2, fma(d2, 1.0 / 362880.0, -1.0 / 5040.0),
-                                                1.0 / 120.0), -1.0 / 6.0), 1.0);
-    return c.cl * cd - c.sl * sd;
+    return cos_series(c.cl, c.sl, c.y0, y, P.g.cos_terms);
 }
 
 template <int ST, bool STEADY, bool SPH>
@@ -727,11 +743,7 @@ __device__ inline bool stage2(const AdvectParams &P, Cell2<typename Real<ST>::T>
         if (!reload2<ST, STEADY>(P, c, e.sa, e.sb, x, y))
             return false;
     }
-    R xi = (R)((x - c.x0) * c.rx), eta = (R)((y - c.y0) * c.ry);
-    if (P.nearest) {
-        xi = xi < (R)0.5 ? (R)0 : (R)1;
-        eta = eta < (R)0.5 ? (R)0 : (R)1;
-    }
+    const R xi = (R)((x - c.x0) * c.rx), eta = (R)((y - c.y0) * c.ry);
     R u = poly<R>(c.a[0], xi, eta), v = poly<R>(c.a[1], xi, eta);
     if constexpr (!STEADY) {
         const R tau = (R)e.tau;
@@ -774,22 +786,21 @@ __device__ inline long long advect_lane_2d(const AdvectParams &P, uint32_t k, ui
                 const int nst = P.scheme ? 1 : 4;
 #pragma nounroll
                 for (int q = 0; q < nst; ++q) {
+                    // wave-uniform stage constants: time entry, offset along the
+                    // previous slope, and the slope's weight in the sum (stage 4's
+                    // slope is added after the loop)
                     const TimeEntry e = q == 0 ? e0 : (q == 3 ? e2 : e1);
                     const double h = q == 0 ? 0.0 : (q == 3 ? dt : hd);
-                    if (e.sa != csa || e.sb != csb) {
+                    const double wq = q == 0 ? 1.0 : (q == 3 ? 0.0 : 2.0);
+                    if (e.sa != csa || e.sb != csb || !P.cache) {
                         c.valid = false;
                         csa = e.sa;
                         csb = e.sb;
                     }
                     if (!stage2<ST, STEADY, SPH>(P, c, e, x + kx * h, y + ky * h, kx, ky))
                         goto fail;
-                    if (q == 1 || q == 2) {
-                        sx += 2.0 * kx;
-                        sy += 2.0 * ky;
-                    } else if (q == 0) {
-                        sx = kx;
-                        sy = ky;
-                    }
+                    sx = fma(wq, kx, sx);
+                    sy = fma(wq, ky, sy);
                 }
                 {
                     double xs, ys;
@@ -1173,13 +1184,13 @@ __device__ inline bool reload3(const AdvectParams &P, Cell3<typename Real<ST>::T
         return false;
     const AxisDev &ax = P.g.ax, &ay = P.g.ay, &az = P.g.az;
     c.x0 = ax.c[i];
-    c.ux = (i == ax.n - 2) ? __builtin_inf() : ax.c[i + 1];
+    c.ux = (i == ax.n - 2) ? nextafter(ax.hi, __builtin_inf()) : ax.c[i + 1];
     c.rx = ax.rw[i];
     c.y0 = ay.c[j];
-    c.uy = (j == ay.n - 2) ? __builtin_inf() : ay.c[j + 1];
+    c.uy = (j == ay.n - 2) ? nextafter(ay.hi, __builtin_inf()) : ay.c[j + 1];
     c.ry = ay.rw[j];
     c.z0 = az.c[k];
-    c.uz = (k == az.n - 2) ? __builtin_inf() : az.c[k + 1];
+    c.uz = (k == az.n - 2) ? nextafter(az.hi, __builtin_inf()) : az.c[k + 1];
     c.rz = az.rw[k];
     if (P.g.coslat) {
         c.cl = P.g.coslat[j];
@@ -1237,8 +1248,7 @@ template <class R>
 __device__ inline bool in_cell3(const Cell3<R> &c, const AdvectParams &P, double x, double y,
                                 double z)
 {
-    return c.valid && x >= c.x0 && x < c.ux && x <= P.g.ax.hi && y >= c.y0 && y < c.uy &&
-           y <= P.g.ay.hi && z >= c.z0 && z < c.uz && z <= P.g.az.hi;
+    return c.valid && x >= c.x0 && x < c.ux && y >= c.y0 && y < c.uy && z >= c.z0 && z < c.uz;
 }
 
 template <int ST, bool STEADY, bool SPH>
@@ -1250,13 +1260,8 @@ __device__ inline bool stage3(const AdvectParams &P, Cell3<typename Real<ST>::T>
         if (!reload3<ST, STEADY>(P, c, e.sa, e.sb, x, y, z))
             return false;
     }
-    R xi = (R)((x - c.x0) * c.rx), eta = (R)((y - c.y0) * c.ry);
-    R zeta = (R)((z - c.z0) * c.rz);
-    if (P.nearest) {
-        xi = xi < (R)0.5 ? (R)0 : (R)1;
-        eta = eta < (R)0.5 ? (R)0 : (R)1;
-        zeta = zeta < (R)0.5 ? (R)0 : (R)1;
-    }
+    const R xi = (R)((x - c.x0) * c.rx), eta = (R)((y - c.y0) * c.ry);
+    const R zeta = (R)((z - c.z0) * c.rz);
     R v[3];
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
@@ -1265,18 +1270,8 @@ __device__ inline bool stage3(const AdvectParams &P, Cell3<typename Real<ST>::T>
             v[q] = fma((R)e.tau, poly3<R>(c.d[q], xi, eta, zeta), v[q]);
     }
     if constexpr (SPH) {
-        double cosl;
-        if (P.g.coslat) {
-            const double dl = (y - c.y0) * kDegToRad, d2 = dl * dl;
-            const double cd = fma(d2, fma(d2, fma(d2, fma(d2, 1.0 / 40320.0, -1.0 / 720.0),
-                                                  1.0 / 24.0), -0.5), 1.0);
-            const double sd = dl * fma(d2, fma(d2, fma(d2, fma(d2, 1.0 / 362880.0,
-                                                                -1.0 / 5040.0), 1.0 / 120.0),
-                                                -1.0 / 6.0), 1.0);
-            cosl = c.cl * cd - c.sl * sd;
-        } else {
-            cosl = cos(y * kDegToRad);
-        }
+        const double cosl = P.g.coslat ? cos_series(c.cl, c.sl, c.y0, y, P.g.cos_terms)
+                                       : cos(y * kDegToRad);
         k[0] = (double)v[0] * recip(kMetresPerDegree * cosl);
         k[1] = (double)v[1] * (1.0 / kMetresPerDegree);
     } else {
@@ -1322,9 +1317,10 @@ __global__ __launch_bounds__(kBlock) void k_advect3d(AdvectParams P)
                     if (!stage3<ST, STEADY, SPH>(P, c, e, x + k[0] * h, y + k[1] * h,
                                                  z + k[2] * h, k))
                         goto fail;
+                    const double wq = q == 0 ? 1.0 : (q == 3 ? 0.0 : 2.0);
 #pragma unroll
                     for (int v = 0; v < 3; ++v)
-                        sm[v] = q == 0 ? k[v] : (q == 3 ? sm[v] : fma(2.0, k[v], sm[v]));
+                        sm[v] = fma(wq, k[v], sm[v]);
                 }
                 {
                     double xs, ys, zs;
@@ -1478,7 +1474,7 @@ hipError_t launch3(const AdvectParams &p, bool steady, uint32_t n_launch, hipStr
     const uint32_t blocks = (n_launch + kBlock - 1) / kBlock;
     if (blocks == 0)
         return hipSuccess;
-    if (!p.cache) {
+    if (!p.cache || p.nearest) {  // the cached kernels interpolate linearly only
         if (steady)
             hipLaunchKernelGGL((k_advect<ST, IS3D, true>), dim3(blocks), dim3(kBlock), 0, s, p);
         else
@@ -1564,7 +1560,7 @@ hipError_t rkf3(const AdvectParams &p, bool steady, uint32_t n_launch, hipStream
     if (n_launch == 0)
         return hipSuccess;
     if constexpr (!IS3D) {
-        if (p.cache) {
+        if (p.cache && !p.nearest) {
             if (p.g.spherical)
                 return steady ? launch_persistent(k_rkf45_2d<ST, true, true>, p, n_launch, s)
                               : launch_persistent(k_rkf45_2d<ST, false, true>, p, n_launch, s);

@@ -210,6 +210,8 @@ extern "C" int fieldset_create(const lp_grid_desc *g, lp_fieldset **out)
                 return bail(fail(LP_EDEVICE, "latitude table kernel failed"));
             fs->g.coslat = fs->dcoslat;
             fs->g.sinlat = fs->dsinlat;
+            // truncation of the series below a quarter ulp for the tallest cell
+            fs->g.cos_terms = tallest <= 0.3 ? 2 : (tallest <= 1.5 ? 3 : 4);
         }
     }
     if (g->land) {
@@ -1051,6 +1053,8 @@ int execute_batch(lp_pset **ps, int32_t nruns, double runtime, double dt, double
             return fail(LP_EINVAL, "batched runs share the stencil_cache setting");
         if (opts[r].kernel == LP_KERNEL_RKF45)
             return fail(LP_EINVAL, "the batched launch takes RK4 or Euler, not RKF45 (run %d)", r);
+        if (opts[r].interp != LP_INTERP_LINEAR)
+            return fail(LP_EINVAL, "the batched launch interpolates linearly only (run %d)", r);
         for (int q = 0; q < r; ++q)
             if (ps[q] == ps[r])
                 return fail(LP_EINVAL, "particle set %d appears twice", r);

@@ -33,6 +33,8 @@ struct GridDev {
     const double *coslat;    // cos and sin of each latitude node (spherical meshes whose
     const double *sinlat;    // cells are at most 5 degrees tall), else null
     int32_t spherical;
+    int32_t cos_terms;       // terms of the cos / sin series across one cell (2, 3 or 4,
+                             // from the tallest cell: 0.3, 1.5 or 5 degrees)
 };
 
 // Bracketing snapshots and weight of one stage time.
