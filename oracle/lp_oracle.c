@@ -19,7 +19,10 @@
  *     "Parallel random numbers: as easy as 1, 2, 3", SC'11);
  *   - the alternative integrators named in Sect. 2.1.1: Euler forward and the
  *     adaptive Runge-Kutta-Fehlberg pair RKF45 (Fehlberg, NASA TR R-315, 1969),
- *     with the step-size control read below.
+ *     with the step-size control read below;
+ *   - the custom kernels of the worked example (Sect. 4.3): sinking, age with
+ *     deletion at a maximum age, and sampling of a tracer (temperature), run
+ *     before the advection of each step.
  *
  * Readings where the paper is silent (each one is listed with its reason in the
  * design notes): classical RK4 tableau; lower-cell rule at a node with the last
@@ -33,6 +36,12 @@
  * (unless e = emin), an accepted step with error at most tol/32 doubles the next
  * one (up to emax); the step is cut short to land on the end of the output
  * interval, and a cut step leaves e as it was.
+ * Worked-example kernels (their code is not in the text): each step first sinks
+ * a particle deeper than its dwelling depth by w_s dt, not past that depth (a
+ * time-backward run raises it back to where it lived); then a particle at or
+ * above the dwelling depth ages by |dt| and is deleted once its age reaches
+ * maxage; then the tracer is sampled at the step's start; then RK4 advects it,
+ * horizontally only while it is at its dwelling depth.
  */
 #include <math.h>
 #include <stdint.h>
@@ -44,6 +53,7 @@
 #define OR_ST_OOB 1u
 #define OR_ST_LAND 2u
 #define OR_ST_DELETED 4u
+#define OR_ST_AGED 8u
 
 #define OR_OK 0
 #define OR_EINVAL (-1)
@@ -63,6 +73,8 @@ typedef struct {
     int stored_f32;          /* 1: U, V, W hold float; 0: double */
     const void *U, *V, *W;   /* [nt][max(nz,1)][ny][nx], i fastest */
     const unsigned char *land; /* [ny][nx] node mask (1 = land) or NULL */
+    const void *tracer;      /* scalar tracer, laid out like U, or NULL */
+    int tracer_f32;          /* 1: the tracer holds float */
 } or_fieldset;
 
 typedef struct {
@@ -73,6 +85,10 @@ typedef struct {
     int nearest;             /* 1: nearest-neighbour instead of linear in space (Sect. 2.3) */
     double tol;              /* RKF45: error tolerance per step in metres */
     int emin, emax;          /* RKF45: range of the step exponent e, step = |dt| 2^e */
+    double sink_speed;       /* m/s, > 0: the sinking kernel (3D) */
+    double dwell_depth;      /* m: depth the particle lives at */
+    double maxage;           /* s, > 0: the age kernel deletes at this age */
+    int sample;              /* 1: sample the tracer into the particle's temp */
 } or_options;
 
 /* ---------------------------------------------------------------- cell search */
@@ -99,7 +115,8 @@ int or_locate(double x, const double *X, int n, int *idx, double *frac)
 
 static double rd(const or_fieldset *fs, const void *F, size_t off)
 {
-    if (fs->stored_f32)
+    const int f32 = F == fs->tracer ? fs->tracer_f32 : fs->stored_f32;
+    if (f32)
         return (double)((const float *)F)[off];
     return ((const double *)F)[off];
 }
@@ -238,6 +255,30 @@ int or_sample_nearest(const or_fieldset *fs, double x, double y, double z, doubl
     return sample_mode(fs, x, y, z, t, out, 1);
 }
 
+/* Tracer value at (x, y, z, t), linear in space and time like the velocity.
+ * Returns 1 outside the grid, 2 outside the snapshots, 3 without a tracer. */
+int or_sample_tracer(const or_fieldset *fs, double x, double y, double z, double t,
+                     double *val)
+{
+    if (!fs->tracer)
+        return 3;
+    or_cell c = {0, 0, 0, 0.0, 0.0, 0.0};
+    if (or_locate(x, fs->X, fs->nx, &c.i, &c.xi) || or_locate(y, fs->Y, fs->ny, &c.j, &c.eta))
+        return 1;
+    if (fs->nz > 0 && or_locate(z, fs->Z, fs->nz, &c.k, &c.zeta))
+        return 1;
+    int s0, s1;
+    double tau;
+    if (or_time_bracket(fs, t, &s0, &s1, &tau) != OR_OK)
+        return 2;
+    if (fs->nt == 1)
+        *val = spatial(fs, fs->tracer, 0, &c);
+    else
+        *val = (1.0 - tau) * spatial(fs, fs->tracer, s0, &c) +
+               tau * spatial(fs, fs->tracer, s1, &c);
+    return 0;
+}
+
 /* ---------------------------------------------------------------- Philox4x32-10 */
 /* Counter-based generator of Salmon et al. (SC'11): ten rounds of the four-word
  * Philox round, each multiplying words 0 and 2 by the two round multipliers and
@@ -315,7 +356,7 @@ static int land_cell(const or_fieldset *fs, int i, int j)
 /* Advance one particle by step n (time t_org + n dt to t_org + (n+1) dt). */
 static void rk4_step(const or_fieldset *fs, const or_options *opt, double t_org, double dt,
                      int64_t n, uint32_t pid, double *px, double *py, double *pz,
-                     unsigned char *st)
+                     unsigned char *st, int horizontal)
 {
     const int is3d = fs->nz > 0;
     const unsigned char err_extra = opt->policy == 0 ? OR_ST_DELETED : 0;
@@ -348,6 +389,8 @@ static void rk4_step(const or_fieldset *fs, const or_options *opt, double t_org,
         ys = y + ((((k1[1] + 2.0 * k2[1]) + 2.0 * k3[1]) + k4[1]) * dt) / 6.0;
         zs = z + ((((k1[2] + 2.0 * k2[2]) + 2.0 * k3[2]) + k4[2]) * dt) / 6.0;
     }
+    if (horizontal)
+        zs = z;
 
     if (opt->Kh > 0.0) {
         double nn[2];
@@ -379,6 +422,38 @@ out_of_bounds:
     *st = (unsigned char)(OR_ST_OOB | err_extra);
 }
 
+/* One step of the worked example's kernel chain for one particle: sinking, age,
+ * tracer sample (all at the step's start), then the advection. */
+static void behave_step(const or_fieldset *fs, const or_options *opt, double t_org, double dt,
+                        int64_t n, uint32_t pid, double *px, double *py, double *pz,
+                        unsigned char *st, double *temp, double *age)
+{
+    const unsigned char err_extra = opt->policy == 0 ? OR_ST_DELETED : 0;
+    const int is3d = fs->nz > 0;
+    const int sinking = is3d && opt->sink_speed > 0.0;
+    if (sinking && *pz > opt->dwell_depth) {
+        double zn = *pz + opt->sink_speed * dt;
+        *pz = zn > opt->dwell_depth ? zn : opt->dwell_depth;
+    }
+    const int dwelling = !sinking || *pz <= opt->dwell_depth;
+    if (opt->maxage > 0.0 && dwelling) {
+        *age = *age + fabs(dt);
+        if (*age >= opt->maxage) {
+            *st = (unsigned char)(OR_ST_AGED | OR_ST_DELETED);
+            return;
+        }
+    }
+    if (opt->sample) {
+        double v;
+        if (or_sample_tracer(fs, *px, *py, is3d ? *pz : 0.0, t_org + (double)n * dt, &v)) {
+            *st = (unsigned char)(OR_ST_OOB | err_extra);
+            return;
+        }
+        *temp = v;
+    }
+    rk4_step(fs, opt, t_org, dt, n, pid, px, py, pz, st, sinking && dwelling);
+}
+
 /* Check that every stage time of steps step0 .. step0+nsteps-1 has snapshots. */
 static int check_time(const or_fieldset *fs, double t_org, double dt, int64_t step0, int64_t nsteps)
 {
@@ -399,8 +474,11 @@ static int check_time(const or_fieldset *fs, double t_org, double dt, int64_t st
 int or_advance(const or_fieldset *fs, int64_t n, double *x, double *y, double *z,
                unsigned char *status, const uint32_t *pid, double t_org, double dt,
                int64_t step0, int64_t nsteps, const or_options *opt, int64_t *psteps,
-               int nthreads)
+               int nthreads, double *temp, double *age)
 {
+    const int behave = opt->sample || opt->maxage > 0.0 || (fs->nz > 0 && opt->sink_speed > 0.0);
+    if (behave && (!temp || !age || (opt->sample && !fs->tracer)))
+        return OR_EINVAL;
     if (dt == 0.0 || nsteps < 0 || n < 0)
         return OR_EINVAL;
     if (check_time(fs, t_org, dt, step0, nsteps) != OR_OK)
@@ -417,8 +495,12 @@ int or_advance(const or_fieldset *fs, int64_t n, double *x, double *y, double *z
             if (status[p])
                 break;
             active++;
-            rk4_step(fs, opt, t_org, dt, step0 + q, pid[p], &x[p], &y[p],
-                     z ? &z[p] : NULL, &status[p]);
+            if (behave)
+                behave_step(fs, opt, t_org, dt, step0 + q, pid[p], &x[p], &y[p],
+                            z ? &z[p] : NULL, &status[p], &temp[p], &age[p]);
+            else
+                rk4_step(fs, opt, t_org, dt, step0 + q, pid[p], &x[p], &y[p],
+                         z ? &z[p] : NULL, &status[p], 0);
         }
         total += active;
     }

@@ -27,6 +27,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 ST_OOB = 1
 ST_LAND = 2
 ST_DELETED = 4
+ST_AGED = 8
 POLICY_DELETE = 0
 POLICY_FREEZE = 1
 # Philox key word used with the run id: (run_id, SEED)
@@ -49,14 +50,16 @@ class _FS(C.Structure):
                 ("spherical", C.c_int), ("nt", C.c_int), ("T", C.c_void_p),
                 ("period", C.c_double), ("stored_f32", C.c_int),
                 ("U", C.c_void_p), ("V", C.c_void_p), ("W", C.c_void_p),
-                ("land", C.c_void_p)]
+                ("land", C.c_void_p), ("tracer", C.c_void_p), ("tracer_f32", C.c_int)]
 
 
 class _OPT(C.Structure):
     _fields_ = [("policy", C.c_int), ("Kh", C.c_double),
                 ("run_id", C.c_uint32), ("seed", C.c_uint32),
                 ("scheme", C.c_int), ("nearest", C.c_int),
-                ("tol", C.c_double), ("emin", C.c_int), ("emax", C.c_int)]
+                ("tol", C.c_double), ("emin", C.c_int), ("emax", C.c_int),
+                ("sink_speed", C.c_double), ("dwell_depth", C.c_double),
+                ("maxage", C.c_double), ("sample", C.c_int)]
 
 
 SCHEME_RK4 = 0
@@ -84,6 +87,9 @@ def lib():
         L.or_sample.restype = C.c_int
         L.or_sample_nearest.argtypes = L.or_sample.argtypes
         L.or_sample_nearest.restype = C.c_int
+        L.or_sample_tracer.argtypes = [C.POINTER(_FS), C.c_double, C.c_double, C.c_double,
+                                       C.c_double, C.POINTER(C.c_double)]
+        L.or_sample_tracer.restype = C.c_int
         L.or_time_bracket.argtypes = [C.POINTER(_FS), C.c_double, C.POINTER(C.c_int),
                                       C.POINTER(C.c_int), C.POINTER(C.c_double)]
         L.or_time_bracket.restype = C.c_int
@@ -93,7 +99,7 @@ def lib():
         L.or_normals.restype = None
         L.or_advance.argtypes = [C.POINTER(_FS), C.c_int64, P, P, P, P, P, C.c_double,
                                  C.c_double, C.c_int64, C.c_int64, C.POINTER(_OPT),
-                                 C.POINTER(C.c_int64), C.c_int]
+                                 C.POINTER(C.c_int64), C.c_int, P, P]
         L.or_advance.restype = C.c_int
         L.or_rkf45_attempt.argtypes = [C.POINTER(_FS), C.c_int, C.c_double, C.c_double, P, P,
                                        P, P]
@@ -123,7 +129,7 @@ class OracleFieldSet:
     or float64 (read as FP64)."""
 
     def __init__(self, lon, lat, depth, times, U, V, W=None, spherical=False,
-                 period=0.0, land=None):
+                 period=0.0, land=None, tracer=None):
         self.lon = np.ascontiguousarray(lon, np.float64)
         self.lat = np.ascontiguousarray(lat, np.float64)
         self.depth = None if depth is None else np.ascontiguousarray(depth, np.float64)
@@ -134,13 +140,16 @@ class OracleFieldSet:
         self.V = np.ascontiguousarray(V, dt_)
         self.W = None if W is None else np.ascontiguousarray(W, dt_)
         self.land = None if land is None else np.ascontiguousarray(land, np.uint8)
+        self.tracer = None if tracer is None else np.ascontiguousarray(
+            tracer, np.float32 if np.asarray(tracer).dtype == np.float32 else np.float64)
         nz = 0 if self.depth is None else self.depth.size
         if self.depth is not None and self.W is None:
             raise ValueError("3D field set needs W")
         self.s = _FS(self.lon.size, self.lat.size, nz, _ptr(self.lon), _ptr(self.lat),
                      _ptr(self.depth), int(bool(spherical)), self.times.size, _ptr(self.times),
                      float(period), int(f32), _ptr(self.U), _ptr(self.V), _ptr(self.W),
-                     _ptr(self.land))
+                     _ptr(self.land), _ptr(self.tracer),
+                     int(self.tracer is not None and self.tracer.dtype == np.float32))
 
     @property
     def is3d(self):
@@ -150,7 +159,8 @@ class OracleFieldSet:
     def from_workload(cls, w):
         U, V, W = w.fields.materialise()
         return cls(w.grid.lon, w.grid.lat, w.grid.depth, w.fields.times, U, V, W,
-                   spherical=w.grid.spherical, period=w.fields.period, land=w.grid.land)
+                   spherical=w.grid.spherical, period=w.fields.period, land=w.grid.land,
+                   tracer=w.fields.materialise_tracer())
 
     # -- single-point primitives used by the pins
     def sample(self, x, y, z, t, nearest=False):
@@ -172,6 +182,11 @@ class OracleFieldSet:
     def metres(self, y, e):
         e = np.ascontiguousarray(e, np.float64)
         return lib().or_metres(C.byref(self.s), float(y), e.ctypes.data)
+
+    def sample_tracer(self, x, y, z, t):
+        v = C.c_double()
+        rc = lib().or_sample_tracer(C.byref(self.s), x, y, z, t, C.byref(v))
+        return rc, v.value
 
     def time_bracket(self, t):
         s0, s1, tau = C.c_int(), C.c_int(), C.c_double()
@@ -225,6 +240,8 @@ class State:
     dt: Optional[float] = None  # dt of the previous advance (time origin bookkeeping)
     exps: Optional[np.ndarray] = None  # RKF45 step exponents (int8), step = |dt| 2^e
     rejected: int = 0                  # RKF45 attempts retried for accuracy
+    temp: Optional[np.ndarray] = None  # sampled tracer (NaN before the first sample)
+    age: Optional[np.ndarray] = None   # seconds lived at the dwelling depth
 
 
 def make_state(x, y, z=None, pid=None, t_org=0.0, step=0) -> State:
@@ -233,13 +250,16 @@ def make_state(x, y, z=None, pid=None, t_org=0.0, step=0) -> State:
     z = None if z is None else np.array(z, np.float64, copy=True)
     pid = np.arange(x.size, dtype=np.uint32) if pid is None else np.ascontiguousarray(pid, np.uint32)
     return State(x, y, z, np.zeros(x.size, np.uint8), pid, float(t_org), int(step),
-                 exps=np.zeros(x.size, np.int8))
+                 exps=np.zeros(x.size, np.int8), temp=np.full(x.size, np.nan),
+                 age=np.zeros(x.size))
 
 
 def advance(fs: OracleFieldSet, st: State, dt: float, nsteps: int, Kh: float = 0.0,
             run_id: int = 0, seed: int = SEED, policy: int = POLICY_DELETE,
             nthreads: int = 0, scheme: int = SCHEME_RK4, nearest: bool = False,
-            tol: float = RKF_TOL, emin: int = RKF_EMIN, emax: int = RKF_EMAX) -> int:
+            tol: float = RKF_TOL, emin: int = RKF_EMIN, emax: int = RKF_EMAX,
+            sink_speed: float = 0.0, dwell_depth: float = 0.0, maxage: float = 0.0,
+            sample: bool = False) -> int:
     """Advance ``st`` in place by ``nsteps`` steps of ``dt`` (negative dt runs
     backward in time); returns the oracle's return code (0, or -4 if a needed time
     lies outside the snapshots).  With RKF45 the call is one output interval: every
@@ -248,7 +268,8 @@ def advance(fs: OracleFieldSet, st: State, dt: float, nsteps: int, Kh: float = 0
     if fs.is3d and st.z is None:
         raise ValueError("3D field set needs depths")
     opt = _OPT(int(policy), float(Kh), int(run_id) & 0xFFFFFFFF, int(seed) & 0xFFFFFFFF,
-               int(scheme), int(bool(nearest)), float(tol), int(emin), int(emax))
+               int(scheme), int(bool(nearest)), float(tol), int(emin), int(emax),
+               float(sink_speed), float(dwell_depth), float(maxage), int(bool(sample)))
     # time is t_org + step * dt; a change of dt keeps the current time
     if st.dt is not None and dt != st.dt:
         st.t_org = (st.t_org + st.step * st.dt) - st.step * dt
@@ -274,7 +295,7 @@ def advance(fs: OracleFieldSet, st: State, dt: float, nsteps: int, Kh: float = 0
     rc = lib().or_advance(C.byref(fs.s), st.x.size, _ptr(st.x), _ptr(st.y),
                           _ptr(st.z if fs.is3d else None), _ptr(st.status), _ptr(st.pid),
                           st.t_org, float(dt), st.step, int(nsteps), C.byref(opt),
-                          C.byref(ps), int(nthreads))
+                          C.byref(ps), int(nthreads), _ptr(st.temp), _ptr(st.age))
     if rc == 0:
         st.step += int(nsteps)
         st.psteps += ps.value
@@ -284,7 +305,8 @@ def advance(fs: OracleFieldSet, st: State, dt: float, nsteps: int, Kh: float = 0
 
 def record(fs: OracleFieldSet, st: State) -> dict:
     ci, cj, ck = fs.cell_indices(st.x, st.y, st.z if fs.is3d else None)
-    r = dict(lon=st.x.copy(), lat=st.y.copy(), status=st.status.copy(), ci=ci, cj=cj)
+    r = dict(lon=st.x.copy(), lat=st.y.copy(), status=st.status.copy(), ci=ci, cj=cj,
+             temp=st.temp.copy(), age=st.age.copy())
     if fs.is3d:
         r["depth"] = st.z.copy()
         r["ck"] = ck
@@ -295,7 +317,8 @@ def run(fs: OracleFieldSet, st: State, dt: float, runtime: float, outputdt: floa
         Kh: float = 0.0, run_id: int = 0, policy: int = POLICY_DELETE,
         nthreads: int = 0, first_record: bool = True, scheme: int = SCHEME_RK4,
         nearest: bool = False, tol: float = RKF_TOL, emin: int = RKF_EMIN,
-        emax: int = RKF_EMAX):
+        emax: int = RKF_EMAX, sink_speed: float = 0.0, dwell_depth: float = 0.0,
+        maxage: float = 0.0, sample: bool = False):
     """Execute for ``runtime`` with records every ``outputdt``; returns the list of
     records (the first taken at the start time when ``first_record``).  A negative
     dt runs backward in time (runtime and outputdt stay positive)."""
@@ -309,7 +332,9 @@ def run(fs: OracleFieldSet, st: State, dt: float, runtime: float, outputdt: floa
     while done < nsteps:
         k = min(per, nsteps - done)
         rc = advance(fs, st, dt, k, Kh=Kh, run_id=run_id, policy=policy, nthreads=nthreads,
-                     scheme=scheme, nearest=nearest, tol=tol, emin=emin, emax=emax)
+                     scheme=scheme, nearest=nearest, tol=tol, emin=emin, emax=emax,
+                     sink_speed=sink_speed, dwell_depth=dwell_depth, maxage=maxage,
+                     sample=sample)
         if rc != 0:
             raise RuntimeError(f"oracle advance failed: {rc}")
         done += k

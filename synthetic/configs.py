@@ -77,10 +77,28 @@ class Fields:
     V: Optional[np.ndarray] = None
     W: Optional[np.ndarray] = None
     maker: Optional[Callable[[int], tuple]] = None
+    # optional scalar tracer (e.g. temperature) on the same grid and snapshots:
+    # arrays with the leading time axis, or ``tracer_maker(s) -> T_s``
+    tracer: Optional[np.ndarray] = None
+    tracer_maker: Optional[Callable[[int], np.ndarray]] = None
 
     @property
     def nt(self) -> int:
         return int(self.times.size)
+
+    @property
+    def has_tracer(self) -> bool:
+        return self.tracer is not None or self.tracer_maker is not None
+
+    def tracer_snapshot(self, s: int):
+        if self.tracer_maker is not None:
+            return self.tracer_maker(s)
+        return None if self.tracer is None else self.tracer[s]
+
+    def materialise_tracer(self):
+        if self.tracer is not None or self.tracer_maker is None:
+            return self.tracer
+        return np.stack([self.tracer_maker(s) for s in range(self.nt)])
 
     def snapshot(self, s: int):
         if self.maker is not None:
@@ -343,3 +361,70 @@ def cfg3_ensemble(n_runs: int = 64, side_min: int = 64, side_max: int = 1024,
                             x0, y0, None, dt=dt, nsteps=nsteps, outputdt=nsteps * dt,
                             Kh=Kh, run_id=r))
     return out
+
+
+def foram_footprint(nx: int = 350, ny: int = 300, nz: int = 54, nt: int = 21,
+                    n_particles: int = 100_000, dt: float = -300.0,
+                    days: int = 42) -> Workload:
+    """Stand-in for the worked example of Sect. 4 (virtual foraminifera ending on
+    the sea floor off Cape Town, tracked backward in time through a regional
+    1/10 degree, 54-level OGCM with 3-day snapshots).  The OFES data is not here:
+    the domain 5-40 E, 50-20 S at 0.1 degree, 54 stretched levels (5-5500 m),
+    3-day snapshots and a temperature tracer are synthesised.  Velocities as in
+    cfg2 (eddies decaying with depth, rotating over 30 days, small W); the
+    temperature falls with depth and towards the south, plus eddy anomalies:
+    T = 26 - 0.4 (-20 - lat) - 14 (1 - exp(-z / 600)) + 1.5 exp(-z / 300) A(x, y, t)
+    (deg C).  All particles start at the core site, 17.3 E 34.7 S, at 2,440 m,
+    jittered by up to 0.05 degree; the run goes backward from the last snapshot
+    (dt < 0) for ``days`` days with daily output."""
+    rs = _streams(5)
+    lon = np.linspace(5.0, 40.0, nx)
+    lat = np.linspace(-50.0, -20.0, ny)
+    z = depth_levels(nz, 5.0, 5500.0)
+    cell_m = ((lon[-1] - lon[0]) / (nx - 1)) * METRES_PER_DEGREE
+    ua, va, ub, vb = _eddy_pair(rs, ny, nx, lat, cell_m)
+    sa = 0.8 / np.sqrt(ua * ua + va * va).max()
+    sb = 0.8 / np.sqrt(ub * ub + vb * vb).max()
+    ua *= sa
+    va *= sa
+    ub *= sb
+    vb *= sb
+    C = random_streamfunction(rs[2], ny, nx, _kappa0_cells(cell_m))
+    A = random_streamfunction(rs[3], ny, nx, _kappa0_cells(cell_m))
+    omega = 2.0 * np.pi / (30.0 * DAY)
+    times = 3.0 * DAY * np.arange(nt, dtype=np.float64)
+    decay = np.exp(-z / 1500.0)
+    wprof = 5e-5 * np.sin(np.pi * (z - z[0]) / (z[-1] - z[0]))
+    base_t = 26.0 - 0.4 * (-20.0 - lat)[:, None] + np.zeros((ny, nx))
+
+    def maker(s: int):
+        t = times[s]
+        U = np.empty((nz, ny, nx), np.float32)
+        V = np.empty_like(U)
+        W = np.empty_like(U)
+        for k in range(nz):
+            c = decay[k] * np.cos(omega * t + z[k] / 800.0)
+            sn = decay[k] * np.sin(omega * t + z[k] / 800.0)
+            U[k] = c * ua + sn * ub
+            V[k] = c * va + sn * vb
+            W[k] = (wprof[k] * np.cos(omega * t)) * C
+        return U, V, W
+
+    def tracer(s: int):
+        t = times[s]
+        T = np.empty((nz, ny, nx), np.float32)
+        for k in range(nz):
+            T[k] = (base_t - 14.0 * (1.0 - np.exp(-z[k] / 600.0))
+                    + 1.5 * np.exp(-z[k] / 300.0) * np.cos(omega * t) * A)
+        return T
+
+    g = rs[4]
+    x0 = 17.3 + g.uniform(-0.05, 0.05, n_particles)
+    y0 = -34.7 + g.uniform(-0.05, 0.05, n_particles)
+    d0 = np.full(n_particles, 2440.0)
+    grid = Grid(lon=lon, lat=lat, depth=z, spherical=True)
+    nsteps = int(round(days * DAY / abs(dt)))
+    meta = dict(sink_speed=200.0 / DAY, dwell_depth=50.0, maxage=30.0 * DAY)
+    return Workload(f"foram_{nx}x{ny}x{nz}_{n_particles}", grid,
+                    Fields(times=times, period=0.0, maker=maker, tracer_maker=tracer),
+                    x0, y0, d0, dt, nsteps, DAY, t0=float(times[-1]), meta=meta)
