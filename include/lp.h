@@ -66,6 +66,7 @@ extern "C" {
 #define LP_ST_OOB 1u     /* a stage point or the end point left the grid */
 #define LP_ST_LAND 2u    /* the end point fell in a cell with four land corners */
 #define LP_ST_DELETED 4u /* removed by the DELETE policy */
+#define LP_ST_AGED 8u    /* reached maxage (with LP_ST_DELETED); see lp_exec_opts */
 
 /* integrators (Sect. 2.1.1) */
 #define LP_KERNEL_RK4 0   /* classical fourth-order Runge-Kutta, the default */
@@ -113,6 +114,14 @@ int fieldset_push_snapshot_f64(lp_fieldset *fs, double t, const double *U, const
 /* Same with float arrays already in device memory (no host copy). */
 int fieldset_push_snapshot_device(lp_fieldset *fs, double t, const float *dU, const float *dV,
                                   const float *dW, void *stream);
+/* A scalar tracer (the temperature of the worked example, Sect. 4.3) for the
+ * resident snapshot at time t: a host float array laid out like U ([max(nz,1)][ny]
+ * [nx]), interpolated like the velocity.  The tracer belongs to that snapshot: when
+ * a later push takes its slot, the slot has no tracer until this is called again.
+ * LP_ESTATE if no resident snapshot has time t.  Synchronises the upload. */
+int fieldset_push_tracer(lp_fieldset *fs, double t, const float *T, void *stream);
+/* Same with a device array (copied in order on `stream`). */
+int fieldset_push_tracer_device(lp_fieldset *fs, double t, const float *dT, void *stream);
 /* Values held for the resident snapshot at time t, as float [max(nz,1)][ny][nx]
  * arrays (bfloat16 and scaled float16 values are returned exactly, as floats);
  * W may be NULL in 2D.  LP_ETIME if no resident snapshot has time t.  Syncs. */
@@ -166,6 +175,21 @@ typedef struct {
     double rkf_tol;       /* > 0, metres per step */
     int32_t rkf_min_exp;  /* in [-30, 0]; |dt| 2^min must still move the clock */
     int32_t rkf_max_exp;  /* in [0, 30] */
+    /* The worked example's custom kernels (Sect. 4.3), run in this order before
+     * the advection of each step (the paper prints their code only as figures;
+     * this is the library's reading).  Sinking (3D, sink_speed > 0): a particle
+     * deeper than dwell_depth moves by sink_speed * dt, not past dwell_depth (so a
+     * time-backward run raises it back to where it lived).  Age (maxage > 0): a
+     * particle at or above dwell_depth (any particle when sinking is off) ages by
+     * |dt|; on the step its age reaches maxage it gets LP_ST_AGED | LP_ST_DELETED
+     * and does not move.  Sample (sample_tracer = 1): the particle's temp becomes
+     * the tracer at its position and the step's start time.  While a sinking
+     * particle is at its dwelling depth the advection is horizontal only.  Any of
+     * these needs LP_KERNEL_RK4 or LP_KERNEL_EULER; they run on the gather kernels. */
+    double sink_speed;    /* m/s, >= 0 (0 = off) */
+    double dwell_depth;   /* m */
+    double maxage;        /* s, >= 0 (0 = off) */
+    int32_t sample_tracer;/* 1: sample the field set's tracer every step */
 } lp_exec_opts;
 
 /* Advance every active particle by runtime/|dt| steps of dt, taking an output
@@ -219,6 +243,13 @@ int pset_status(lp_pset *ps, lp_counts *c, uint8_t *status);
  * pointer may be NULL.  Synchronises. */
 int pset_get(lp_pset *ps, double *lon, double *lat, double *depth, int32_t *ci, int32_t *cj,
              int32_t *ck);
+/* The particles' sampled tracer (NaN before the first sample) and age in seconds,
+ * id order; either pointer may be NULL.  Synchronises. */
+int pset_get_behaviour(lp_pset *ps, double *temp, double *age);
+/* The tracer and age of every output record (record-major, like pset_records);
+ * records taken before the first execute with a worked-example kernel hold NaN
+ * and 0.  LP_ESTATE if no such execute has run.  Synchronises. */
+int pset_records_behaviour(lp_pset *ps, double *temp, double *age);
 /* The n RKF45 step exponents e (step |dt| 2^e) in id order.  Synchronises. */
 int pset_get_step_exponents(lp_pset *ps, int8_t *e);
 /* Output records: *nrec records of *nper = ceil(n / output_stride) particles

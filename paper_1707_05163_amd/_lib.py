@@ -28,7 +28,8 @@ EXPORTS = (
     "fieldset_push_snapshot_device", "fieldset_get_snapshot", "fieldset_resident",
     "fieldset_destroy", "lp_philox_normals",
     "pset_create", "pset_create_device", "pset_execute", "pset_status", "pset_get",
-    "pset_get_step_exponents",
+    "pset_get_step_exponents", "pset_get_behaviour", "pset_records_behaviour",
+    "fieldset_push_tracer", "fieldset_push_tracer_device",
     "pset_records", "pset_timing", "pset_destroy", "lp_last_error", "lp_version",
     "pset_execute_batch", "pset_autotune_batch",
     "surrogate_param_count", "surrogate_create", "surrogate_get_params", "surrogate_set_params",
@@ -49,7 +50,9 @@ class lp_exec_opts(C.Structure):
                 ("run_id", C.c_uint32), ("seed", C.c_uint32), ("output_stride", C.c_int32),
                 ("sort_every", C.c_int32), ("profile", C.c_int32),
                 ("stencil_cache", C.c_int32), ("interp", C.c_int32),
-                ("rkf_tol", C.c_double), ("rkf_min_exp", C.c_int32), ("rkf_max_exp", C.c_int32)]
+                ("rkf_tol", C.c_double), ("rkf_min_exp", C.c_int32), ("rkf_max_exp", C.c_int32),
+                ("sink_speed", C.c_double), ("dwell_depth", C.c_double), ("maxage", C.c_double),
+                ("sample_tracer", C.c_int32)]
 
 
 class lp_counts(C.Structure):
@@ -106,6 +109,10 @@ def _declare(L):
         "pset_status": ([P, C.POINTER(lp_counts), P], I),
         "pset_get": ([P, P, P, P, P, P, P], I),
         "pset_get_step_exponents": ([P, P], I),
+        "pset_get_behaviour": ([P, P, P], I),
+        "pset_records_behaviour": ([P, P, P], I),
+        "fieldset_push_tracer": ([P, C.c_double, P, P], I),
+        "fieldset_push_tracer_device": ([P, C.c_double, P, P], I),
         "pset_records": ([P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), P, P, P, P, P, P, P], I),
         "pset_timing": ([P, C.POINTER(C.c_double), C.POINTER(C.c_int64)], I),
         "pset_execute_batch": ([C.POINTER(C.c_void_p), C.c_int32, C.c_double, C.c_double,

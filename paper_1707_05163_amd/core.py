@@ -83,6 +83,8 @@ class FieldSet:
         if push:
             for s in range(min(cap, w.fields.nt)):
                 fs.push_snapshot(w.fields.times[s], *w.fields.snapshot(s))
+                if w.fields.has_tracer:
+                    fs.push_tracer(w.fields.times[s], w.fields.tracer_snapshot(s))
         return fs
 
     @property
@@ -105,6 +107,15 @@ class FieldSet:
                                              _stream(stream)))
 
     advancetime = push_snapshot
+
+    def push_tracer(self, t: float, T, stream=None):
+        """The scalar tracer (e.g. temperature) of the resident snapshot at time t."""
+        if _is_torch(T):
+            L.check(L.lib.fieldset_push_tracer_device(self._h, float(t), _ptr(T),
+                                                      _stream(stream)))
+            return
+        L.check(L.lib.fieldset_push_tracer(self._h, float(t), _ptr(_host(T, np.float32)),
+                                           _stream(stream)))
 
     def get_snapshot(self, t: float):
         """Values held on the device for the snapshot at time t (exact, as float32)."""
@@ -168,23 +179,28 @@ class ParticleSet:
     def opts(recovery: str = "delete", Kh: float = 0.0, run_id: int = 0, seed: int = SEED,
              output_stride: int = 0, sort_every: int = 1, profile: bool = False,
              stencil_cache: bool = True, kernel: str = "rk4", interp: str = "linear",
-             tol: float = RKF_TOL, min_exp: int = RKF_MIN_EXP, max_exp: int = RKF_MAX_EXP):
+             tol: float = RKF_TOL, min_exp: int = RKF_MIN_EXP, max_exp: int = RKF_MAX_EXP,
+             sink_speed: float = 0.0, dwell_depth: float = 0.0, maxage: float = 0.0,
+             sample: bool = False):
         return L.lp_exec_opts(_KERNEL[kernel], _RECOVERY[recovery], float(Kh), int(run_id),
                               int(seed) & 0xFFFFFFFF, int(output_stride), int(sort_every),
                               int(bool(profile)), int(bool(stencil_cache)), _INTERP[interp],
-                              float(tol), int(min_exp), int(max_exp))
+                              float(tol), int(min_exp), int(max_exp), float(sink_speed),
+                              float(dwell_depth), float(maxage), int(bool(sample)))
 
     def execute(self, runtime: float, dt: float, outputdt: float = 0.0,
                 recovery: str = "delete", Kh: float = 0.0, run_id: int = 0, seed: int = SEED,
                 output_stride: int = 0, sort_every: int = 1, profile: bool = False,
                 stencil_cache: bool = True, kernel: str = "rk4", interp: str = "linear",
                 tol: float = RKF_TOL, min_exp: int = RKF_MIN_EXP, max_exp: int = RKF_MAX_EXP,
-                stream=None):
+                sink_speed: float = 0.0, dwell_depth: float = 0.0, maxage: float = 0.0,
+                sample: bool = False, stream=None):
         """The update loop: runtime/|dt| steps of dt (negative dt runs backward).  With
         kernel="rkf45" each particle steps adaptively by |dt| 2^e, e in
         [min_exp, max_exp], to within `tol` metres per step."""
         o = self.opts(recovery, Kh, run_id, seed, output_stride, sort_every, profile,
-                      stencil_cache, kernel, interp, tol, min_exp, max_exp)
+                      stencil_cache, kernel, interp, tol, min_exp, max_exp, sink_speed,
+                      dwell_depth, maxage, sample)
         L.check(L.lib.pset_execute(self._h, float(runtime), float(dt), float(outputdt),
                                    C.byref(o), _stream(stream)))
 
@@ -194,6 +210,12 @@ class ParticleSet:
         L.check(L.lib.pset_status(self._h, C.byref(c), st.ctypes.data))
         counts = {k: getattr(c, k) for k, _ in L.lp_counts._fields_}
         return counts, st
+
+    def behaviour(self):
+        """Sampled tracer (NaN before the first sample) and age in seconds, id order."""
+        temp, age = np.empty(self.n), np.empty(self.n)
+        L.check(L.lib.pset_get_behaviour(self._h, temp.ctypes.data, age.ctypes.data))
+        return temp, age
 
     def step_exponents(self):
         """RKF45 step exponents e (step |dt| 2^e), id order."""
@@ -227,6 +249,10 @@ class ParticleSet:
                                    _ptr(out["lat"]), _ptr(out.get("depth")),
                                    _ptr(out["status"]), _ptr(out["ci"]), _ptr(out["cj"]),
                                    _ptr(out.get("ck"))))
+        temp, age = np.empty(shape), np.empty(shape)
+        if L.lib.pset_records_behaviour(self._h, _ptr(temp), _ptr(age)) == 0:
+            out["temp"] = temp
+            out["age"] = age
         return out
 
     def execute_surrogate(self, model: "Surrogate", runtime: float, dt: float = 300.0,

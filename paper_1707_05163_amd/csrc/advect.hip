@@ -20,7 +20,7 @@ namespace lp {
 
 namespace {
 
-constexpr uint8_t ST_OOB = 1, ST_LAND = 2, ST_DELETED = 4;
+constexpr uint8_t ST_OOB = 1, ST_LAND = 2, ST_DELETED = 4, ST_AGED = 8;
 
 // Blocks are dispatched round-robin over the 8 XCDs (block b -> XCD b % 8).  Map
 // the hardware block id so that each XCD works on one contiguous range of the
@@ -243,7 +243,7 @@ __device__ inline double unit53(uint32_t a, uint32_t b)
 
 template <int ST, bool IS3D, bool STEADY>
 __device__ inline uint8_t rk4_step(const AdvectParams &P, int s, uint32_t id, double &x,
-                                   double &y, double &z)
+                                   double &y, double &z, bool horizontal = false)
 {
     const TimeEntry e0 = P.tab[2 * s], e1 = P.tab[2 * s + 1], e2 = P.tab[2 * s + 2];
     const double dt = P.dt, hd = 0.5 * dt;
@@ -270,6 +270,10 @@ __device__ inline uint8_t rk4_step(const AdvectParams &P, int s, uint32_t id, do
         ys = y + ((((k1[1] + 2.0 * k2[1]) + 2.0 * k3[1]) + k4[1]) * dt) / 6.0;
         if constexpr (IS3D)
             zs = z + ((((k1[2] + 2.0 * k2[2]) + 2.0 * k3[2]) + k4[2]) * dt) / 6.0;
+    }
+    if constexpr (IS3D) {
+        if (horizontal)  // a dwelling particle keeps its depth
+            zs = z;
     }
     if (P.Kh > 0.0) {
         uint32_t c[4] = {id, (uint32_t)(P.step0 + s), 0u, 0u};
@@ -303,6 +307,71 @@ __device__ inline uint8_t rk4_step(const AdvectParams &P, int s, uint32_t id, do
     return 0;
 }
 
+// Tracer at (x, y, z) for the time entry te: trilinear (bilinear in 2D) on the
+// float tracer slots in FP64, then linear in time; false outside the grid.
+template <bool IS3D, bool STEADY>
+__device__ inline bool sample_tracer(const AdvectParams &P, const TimeEntry &te, double x,
+                                     double y, double z, double &val)
+{
+    Cell c;
+    if (!locate(P.g.ax, x, c.i, c.xi) || !locate(P.g.ay, y, c.j, c.eta))
+        return false;
+    c.k = 0;
+    c.zeta = 0.0;
+    if constexpr (IS3D) {
+        if (!locate(P.g.az, z, c.k, c.zeta))
+            return false;
+    }
+    const size_t nx = (size_t)P.g.ax.n, plane = nx * (size_t)P.g.ay.n;
+    auto level = [&](int slot, int k) {
+        const float *F = P.f.tracer + ((size_t)slot * P.f.nzl + (size_t)k) * plane;
+        const size_t n00 = (size_t)c.j * nx + (size_t)c.i;
+        const double w00 = (1.0 - c.xi) * (1.0 - c.eta), w10 = c.xi * (1.0 - c.eta);
+        const double w11 = c.xi * c.eta, w01 = (1.0 - c.xi) * c.eta;
+        return ((w00 * (double)F[n00] + w10 * (double)F[n00 + 1]) +
+                w11 * (double)F[n00 + nx + 1]) + w01 * (double)F[n00 + nx];
+    };
+    auto spatial_t = [&](int slot) {
+        if constexpr (!IS3D)
+            return level(slot, 0);
+        return (1.0 - c.zeta) * level(slot, c.k) + c.zeta * level(slot, c.k + 1);
+    };
+    if constexpr (STEADY)
+        val = spatial_t(te.sa);
+    else
+        val = (1.0 - te.tau) * spatial_t(te.sa) + te.tau * spatial_t(te.sb);
+    return true;
+}
+
+// The worked example's kernels ahead of the advection of step s (sinking, age,
+// tracer sample); returns a status to stop with, or 0.  The sinking update is
+// rounded as written (no contraction) so that reaching the dwelling depth is the
+// same decision as in a plain FP64 evaluation.
+template <bool IS3D, bool STEADY>
+__device__ inline uint8_t behave_pre(const AdvectParams &P, int s, double x, double y,
+                                     double &z, double &temp, double &age, bool &horizontal)
+{
+    const bool sinking = IS3D && P.sink_speed > 0.0;
+    if (sinking && z > P.dwell_depth) {
+        const double zn = __dadd_rn(z, __dmul_rn(P.sink_speed, P.dt));
+        z = zn > P.dwell_depth ? zn : P.dwell_depth;
+    }
+    const bool dwelling = !sinking || z <= P.dwell_depth;
+    if (P.maxage > 0.0 && dwelling) {
+        age = age + fabs(P.dt);
+        if (age >= P.maxage)
+            return (uint8_t)(ST_AGED | ST_DELETED);
+    }
+    if (P.sample) {
+        double v;
+        if (!sample_tracer<IS3D, STEADY>(P, P.tab[2 * s], x, y, z, v))
+            return (uint8_t)(ST_OOB | (P.policy == 0 ? ST_DELETED : 0));
+        temp = v;
+    }
+    horizontal = sinking && dwelling;
+    return 0;
+}
+
 template <int ST, bool IS3D, bool STEADY>
 __global__ __launch_bounds__(kBlock) void k_advect(AdvectParams P)
 {
@@ -315,9 +384,23 @@ __global__ __launch_bounds__(kBlock) void k_advect(AdvectParams P)
         uint8_t st = P.status[id];
         if (st == 0) {
             double x = P.x[id], y = P.y[id], z = IS3D ? P.z[id] : 0.0;
+            double temp = 0.0, age = 0.0;
+            if (P.behave) {
+                temp = P.temp[id];
+                age = P.age[id];
+            }
             for (int s = 0; s < P.nsteps; ++s) {
                 ++steps;
-                const uint8_t e = rk4_step<ST, IS3D, STEADY>(P, s, id, x, y, z);
+                bool horizontal = false;
+                if (P.behave) {
+                    const uint8_t b = behave_pre<IS3D, STEADY>(P, s, x, y, z, temp, age,
+                                                               horizontal);
+                    if (b) {
+                        st = b;
+                        break;
+                    }
+                }
+                const uint8_t e = rk4_step<ST, IS3D, STEADY>(P, s, id, x, y, z, horizontal);
                 if (e) {
                     st = (uint8_t)(e | (P.policy == 0 ? ST_DELETED : 0));
                     break;
@@ -327,6 +410,10 @@ __global__ __launch_bounds__(kBlock) void k_advect(AdvectParams P)
             P.y[id] = y;
             if constexpr (IS3D)
                 P.z[id] = z;
+            if (P.behave) {
+                P.temp[id] = temp;
+                P.age[id] = age;
+            }
             if (st)
                 P.status[id] = st;
         }
@@ -1465,6 +1552,8 @@ __global__ void k_record(RecordParams R)
         if (R.ci) R.ci[r] = i;
         if (R.cj) R.cj[r] = j;
         if (R.ck) R.ck[r] = k;
+        if (R.rtemp) R.rtemp[r] = R.temp[id];
+        if (R.rage) R.rage[r] = R.age[id];
     }
 }
 
@@ -1474,7 +1563,8 @@ hipError_t launch3(const AdvectParams &p, bool steady, uint32_t n_launch, hipStr
     const uint32_t blocks = (n_launch + kBlock - 1) / kBlock;
     if (blocks == 0)
         return hipSuccess;
-    if (!p.cache || p.nearest) {  // the cached kernels interpolate linearly only
+    // the cached kernels interpolate linearly and run no worked-example kernels
+    if (!p.cache || p.nearest || p.behave) {
         if (steady)
             hipLaunchKernelGGL((k_advect<ST, IS3D, true>), dim3(blocks), dim3(kBlock), 0, s, p);
         else

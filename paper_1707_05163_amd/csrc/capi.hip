@@ -253,6 +253,7 @@ extern "C" int fieldset_create(const lp_grid_desc *g, lp_fieldset **out)
     }
     fs->slot_t.assign(fs->capacity, 0.0);
     fs->slot_seq.assign(fs->capacity, -1);
+    fs->tracer_seq.assign(fs->capacity, -1);
     *out = fs;
     return LP_OK;
 }
@@ -272,6 +273,7 @@ extern "C" void fieldset_destroy(lp_fieldset *fs)
     dfree(fs->dsinlat);
     dfree(fs->dslots);
     dfree(fs->dscales);
+    dfree(fs->dtracer);
     dfree(fs->dtmp);
     dfree(fs->dstage);
     dfree(fs->dstage64);
@@ -370,6 +372,50 @@ extern "C" int fieldset_push_snapshot_device(lp_fieldset *fs, double t, const fl
                                              const float *dV, const float *dW, void *stream)
 {
     return push_common(fs, t, dU, dV, dW, true, false, stream);
+}
+
+static int push_tracer(lp_fieldset *fs, double t, const float *T, bool device_src, void *stream)
+{
+    if (!fs || !T)
+        return fail(LP_EINVAL, "null argument");
+    int slot = -1;
+    for (int s = 0; s < fs->capacity; ++s)
+        if (fs->slot_seq[s] >= 0 && fs->slot_t[s] == t)
+            slot = s;
+    if (slot < 0)
+        return fail(LP_ESTATE, "no resident snapshot has time %.17g", t);
+    const size_t nvals = fs->plane() * fs->nzl;
+    int rc;
+    if (!fs->dtracer && (rc = dalloc(&fs->dtracer, nvals * (size_t)fs->capacity)))
+        return rc;
+    if (stream) {
+        hipEvent_t ev;
+        HIPCHECK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        HIPCHECK(hipEventRecord(ev, (hipStream_t)stream));
+        HIPCHECK(hipStreamWaitEvent(fs->up, ev, 0));
+        HIPCHECK(hipEventDestroy(ev));
+    }
+    HIPCHECK(hipStreamWaitEvent(fs->up, fs->release[slot], 0));
+    HIPCHECK(hipMemcpyAsync(fs->dtracer + (size_t)slot * nvals, T, nvals * sizeof(float),
+                            device_src ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                            fs->up));
+    // kernels that read this slot wait for `ready`, which now covers the tracer too
+    HIPCHECK(hipEventRecord(fs->ready[slot], fs->up));
+    if (!device_src)
+        HIPCHECK(hipStreamSynchronize(fs->up));
+    fs->tracer_seq[slot] = fs->slot_seq[slot];
+    return LP_OK;
+}
+
+extern "C" int fieldset_push_tracer(lp_fieldset *fs, double t, const float *T, void *stream)
+{
+    return push_tracer(fs, t, T, false, stream);
+}
+
+extern "C" int fieldset_push_tracer_device(lp_fieldset *fs, double t, const float *dT,
+                                          void *stream)
+{
+    return push_tracer(fs, t, dT, true, stream);
 }
 
 namespace {
@@ -517,6 +563,10 @@ extern "C" void pset_destroy(lp_pset *ps)
     dfree(ps->dblk);
     dfree(ps->dpsteps);
     dfree(ps->dexp);
+    dfree(ps->dtemp);
+    dfree(ps->dage);
+    dfree(ps->rtemp);
+    dfree(ps->rage);
     dfree(ps->dqueues);
     dfree(ps->dres);
     dfree(ps->rx);
@@ -570,7 +620,8 @@ static int pset_create_common(lp_fieldset *fs, int64_t n, const double *lon, con
         (fs->is3d && (rc = dalloc(&ps->dz, N))) || (rc = dalloc(&ps->dst, N)) ||
         (rc = dalloc(&ps->dorder[0], N)) || (rc = dalloc(&ps->dorder[1], N)) ||
         (rc = dalloc(&ps->dcount, 2)) || (rc = dalloc(&ps->dpsteps, 2)) ||
-        (rc = dalloc(&ps->dexp, N)) || (rc = dalloc(&ps->dqueues, 8)))
+        (rc = dalloc(&ps->dexp, N)) || (rc = dalloc(&ps->dqueues, 8)) ||
+        (rc = dalloc(&ps->dtemp, N)) || (rc = dalloc(&ps->dage, N)))
         return bail(rc);
     ps->nbins = lp::sort_bins(fs->g);
     if ((rc = dalloc(&ps->dkeys, N)) || (rc = dalloc(&ps->dhist, ps->nbins)) ||
@@ -591,6 +642,8 @@ static int pset_create_common(lp_fieldset *fs, int64_t n, const double *lon, con
     if (hipMemsetAsync(ps->dst, 0, N, stream) != hipSuccess ||
         hipMemsetAsync(ps->dpsteps, 0, 2 * sizeof(unsigned long long), stream) != hipSuccess ||
         hipMemsetAsync(ps->dexp, 0, N, stream) != hipSuccess ||
+        hipMemsetAsync(ps->dtemp, 0xFF, N * sizeof(double), stream) != hipSuccess ||  // NaN
+        hipMemsetAsync(ps->dage, 0, N * sizeof(double), stream) != hipSuccess ||
         lp::launch_iota(ps->dorder[0], N, stream) != hipSuccess ||
         lp::launch_fill_u32(ps->dcount, (uint32_t)n, 1, stream) != hipSuccess)
         return bail(fail(LP_EDEVICE, "particle set initialisation failed"));
@@ -620,7 +673,7 @@ namespace {
 
 int grow_records(lp_pset *ps, int64_t need)
 {
-    if (need <= ps->rec_cap)
+    if (need <= ps->rec_cap && (!ps->behave_records || ps->rtemp))
         return LP_OK;
     int64_t cap = std::max<int64_t>(need, std::max<int64_t>(4, ps->rec_cap * 2));
     const size_t old = (size_t)(ps->nrec * ps->nper), tot = (size_t)(cap * ps->nper);
@@ -651,6 +704,24 @@ int grow_records(lp_pset *ps, int64_t need)
     dfree(ps->rci);
     dfree(ps->rcj);
     dfree(ps->rck);
+    if (ps->behave_records) {
+        double *rt = nullptr, *ra = nullptr;
+        if ((rc = dalloc(&rt, tot)) || (rc = dalloc(&ra, tot))) {
+            dfree(rt);
+            return rc;
+        }
+        if (old && ps->rtemp) {
+            HIPCHECK(hipMemcpy(rt, ps->rtemp, old * 8, hipMemcpyDeviceToDevice));
+            HIPCHECK(hipMemcpy(ra, ps->rage, old * 8, hipMemcpyDeviceToDevice));
+        } else if (old) {  // records taken before any worked-example kernel ran
+            HIPCHECK(hipMemset(rt, 0xFF, old * 8));
+            HIPCHECK(hipMemset(ra, 0, old * 8));
+        }
+        dfree(ps->rtemp);
+        dfree(ps->rage);
+        ps->rtemp = rt;
+        ps->rage = ra;
+    }
     ps->rx = rx;
     ps->ry = ry;
     ps->rz = rz;
@@ -681,6 +752,12 @@ int take_record(lp_pset *ps, hipStream_t s)
     R.ci = ps->rci + off;
     R.cj = ps->rcj + off;
     R.ck = ps->fs->is3d ? ps->rck + off : nullptr;
+    if (ps->rtemp) {
+        R.temp = ps->dtemp;
+        R.age = ps->dage;
+        R.rtemp = ps->rtemp + off;
+        R.rage = ps->rage + off;
+    }
     HIPCHECK(lp::launch_record(R, s));
     ps->nrec++;
     return LP_OK;
@@ -719,6 +796,14 @@ int exec_prepare(lp_pset *ps, double runtime, double dt, double outputdt, const 
                                "rkf_max_exp in [0, 30]");
     if (rkf && o->Kh != 0.0)
         return fail(LP_EINVAL, "RKF45 takes no Brownian term (Kh must be 0)");
+    if (!(o->sink_speed >= 0.0) || !std::isfinite(o->sink_speed) || !(o->maxage >= 0.0) ||
+        !std::isfinite(o->maxage) || !std::isfinite(o->dwell_depth))
+        return fail(LP_EINVAL, "sink_speed and maxage must be finite and >= 0");
+    if (o->sink_speed > 0.0 && !fs->is3d)
+        return fail(LP_EINVAL, "sinking needs a 3D field set");
+    const bool behave = o->sample_tracer || o->maxage > 0.0 || o->sink_speed > 0.0;
+    if (behave && rkf)
+        return fail(LP_EINVAL, "the worked-example kernels run with RK4 or Euler, not RKF45");
     if (o->interp != LP_INTERP_LINEAR && o->interp != LP_INTERP_NEAREST)
         return fail(LP_EINVAL, "unknown interpolation %d", o->interp);
     if (o->recovery != LP_DELETE && o->recovery != LP_FREEZE)
@@ -843,7 +928,15 @@ int exec_prepare(lp_pset *ps, double runtime, double dt, double outputdt, const 
         ps->n_launch = std::min<uint32_t>(ps->n_launch, *ps->hcount);
         ps->count_pending = false;
     }
+    if (behave && o->sample_tracer) {
+        for (int s = 0; s < fs->capacity; ++s)
+            if (plan.used[s] && fs->tracer_seq[s] != fs->slot_seq[s])
+                return fail(LP_ESTATE, "the snapshot at time %.17g has no tracer",
+                            fs->slot_t[s]);
+    }
     ps->dt = dt;
+    if (behave)
+        ps->behave_records = true;
     if (plan.records) {
         int rc = grow_records(ps, ps->nrec + (int64_t)plan.segs.size() + 1);
         if (rc)
@@ -874,6 +967,14 @@ int exec_prepare(lp_pset *ps, double runtime, double dt, double outputdt, const 
     P.prej = ps->dpsteps + 1;
     P.hexp = ps->dexp;
     P.queues = ps->dqueues;
+    P.f.tracer = fs->dtracer;
+    P.behave = behave ? 1 : 0;
+    P.sample = o->sample_tracer ? 1 : 0;
+    P.sink_speed = o->sink_speed;
+    P.dwell_depth = o->dwell_depth;
+    P.maxage = o->maxage;
+    P.temp = ps->dtemp;
+    P.age = ps->dage;
     if (rkf) {
         P.res = ps->dres;
         P.nres = (int32_t)res.size();
@@ -1055,6 +1156,9 @@ int execute_batch(lp_pset **ps, int32_t nruns, double runtime, double dt, double
             return fail(LP_EINVAL, "the batched launch takes RK4 or Euler, not RKF45 (run %d)", r);
         if (opts[r].interp != LP_INTERP_LINEAR)
             return fail(LP_EINVAL, "the batched launch interpolates linearly only (run %d)", r);
+        if (opts[r].sample_tracer || opts[r].maxage > 0.0 || opts[r].sink_speed > 0.0)
+            return fail(LP_EINVAL, "the batched launch runs no worked-example kernels (run %d)",
+                        r);
         for (int q = 0; q < r; ++q)
             if (ps[q] == ps[r])
                 return fail(LP_EINVAL, "particle set %d appears twice", r);
@@ -1368,6 +1472,32 @@ extern "C" int pset_status(lp_pset *ps, lp_counts *c, uint8_t *status)
     return LP_OK;
 }
 
+extern "C" int pset_get_behaviour(lp_pset *ps, double *temp, double *age)
+{
+    if (!ps)
+        return fail(LP_EINVAL, "null argument");
+    HIPCHECK(hipStreamSynchronize(ps->last_stream));
+    const size_t N = (size_t)ps->n;
+    if (temp) HIPCHECK(hipMemcpy(temp, ps->dtemp, N * 8, hipMemcpyDeviceToHost));
+    if (age) HIPCHECK(hipMemcpy(age, ps->dage, N * 8, hipMemcpyDeviceToHost));
+    return LP_OK;
+}
+
+extern "C" int pset_records_behaviour(lp_pset *ps, double *temp, double *age)
+{
+    if (!ps)
+        return fail(LP_EINVAL, "null argument");
+    if (!ps->behave_records)
+        return fail(LP_ESTATE, "no execute with a worked-example kernel has run");
+    HIPCHECK(hipStreamSynchronize(ps->last_stream));
+    const size_t T = (size_t)(ps->nrec * ps->nper);
+    if (T == 0 || !ps->rtemp)
+        return LP_OK;
+    if (temp) HIPCHECK(hipMemcpy(temp, ps->rtemp, T * 8, hipMemcpyDeviceToHost));
+    if (age) HIPCHECK(hipMemcpy(age, ps->rage, T * 8, hipMemcpyDeviceToHost));
+    return LP_OK;
+}
+
 extern "C" int pset_get_step_exponents(lp_pset *ps, int8_t *e)
 {
     if (!ps || !e)
@@ -1480,6 +1610,8 @@ int lp_pset_reset_device(lp_pset *ps, int64_t n, const double *x, const double *
         HIPCHECK(hipMemsetAsync(ps->dst + n, LP_ST_DELETED, (size_t)(ps->n - n), stream));
     HIPCHECK(hipMemsetAsync(ps->dpsteps, 0, 2 * sizeof(unsigned long long), stream));
     HIPCHECK(hipMemsetAsync(ps->dexp, 0, (size_t)ps->n, stream));
+    HIPCHECK(hipMemsetAsync(ps->dtemp, 0xFF, (size_t)ps->n * sizeof(double), stream));
+    HIPCHECK(hipMemsetAsync(ps->dage, 0, (size_t)ps->n * sizeof(double), stream));
     HIPCHECK(lp::launch_iota(ps->dorder[0], (size_t)n, stream));
     HIPCHECK(lp::launch_fill_u32(ps->dcount, (uint32_t)n, 1, stream));
     ps->cur = 0;

@@ -55,6 +55,7 @@ struct FieldDev {
     const float *scales;     // LP_F16_SCALED: [slot][level][var] power-of-two scales
     int32_t nzl;             // levels per slot (1 in 2D)
     int32_t steady;          // single snapshot: no time interpolation
+    const float *tracer;     // scalar tracer, [slot][level][ny][nx] floats, or null
 };
 
 struct AdvectParams {
@@ -87,6 +88,13 @@ struct AdvectParams {
     int8_t *hexp;            // per-particle step exponents, id order
     uint32_t *queues;        // 8 work-queue counters of the persistent launch
     unsigned long long *prej;// attempts retried at half the step
+    // the worked example's kernels ahead of each step's advection (gather kernels)
+    int32_t behave;          // 1: any of them is on
+    int32_t sample;          // sample the tracer into temp
+    double sink_speed;       // m/s, 0 = off
+    double dwell_depth;      // m
+    double maxage;           // s, 0 = off
+    double *temp, *age;      // per particle, id order
 };
 
 struct RecordParams {
@@ -97,6 +105,8 @@ struct RecordParams {
     double *rx, *ry, *rz;
     uint8_t *rst;
     int32_t *ci, *cj, *ck;
+    const double *temp, *age;   // worked-example variables (or null)
+    double *rtemp, *rage;
 };
 
 // GEMM of the surrogate network: C[M x N] = sum_k A(i, k) B(k, j) on bf16 operands

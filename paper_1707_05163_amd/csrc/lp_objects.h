@@ -28,6 +28,8 @@ struct lp_fieldset {
     char *dslots = nullptr;
     size_t slot_bytes = 0;
     float *dscales = nullptr;
+    float *dtracer = nullptr;       // tracer slots (allocated at the first tracer push)
+    std::vector<int64_t> tracer_seq;// push index whose tracer each slot holds, -1 = none
     float *dtmp = nullptr;
     float *dstage = nullptr;
     double *dstage64 = nullptr;
@@ -57,6 +59,9 @@ struct lp_pset {
     uint32_t nbins = 0;
     unsigned long long *dpsteps = nullptr;  // [0] particle-steps, [1] RKF45 retries
     int8_t *dexp = nullptr;                  // RKF45 step exponents
+    double *dtemp = nullptr, *dage = nullptr;// worked-example tracer sample and age
+    bool behave_records = false;             // records carry temp and age
+    double *rtemp = nullptr, *rage = nullptr;
     uint32_t *dqueues = nullptr;             // RKF45 work queues (8)
     lp::ResTime *dres = nullptr;             // resident-snapshot table of RKF45 launches
     size_t res_cap = 0;
