@@ -64,6 +64,7 @@ class FieldSet:
         self.nx, self.ny = lo.size, la.size
         self.nz = 0 if de is None else de.size
         self.dtype = dtype
+        self.mesh = mesh
         g = L.lp_grid_desc(self.nx, self.ny, self.nz, lo.ctypes.data, la.ctypes.data,
                            None if de is None else de.ctypes.data, _MESH[mesh], _DTYPES[dtype],
                            int(capacity), float(time_period),
@@ -174,6 +175,9 @@ class ParticleSet:
                                       float(t0), int(step0), C.byref(h)))
         self._h = h
         self.is3d = fieldset.nz > 0
+        self._time = float(t0)       # the set's time, tracked for record times
+        self._rec_times = []         # time of each output record
+        self._stride = 0
 
     @staticmethod
     def opts(recovery: str = "delete", Kh: float = 0.0, run_id: int = 0, seed: int = SEED,
@@ -203,6 +207,26 @@ class ParticleSet:
                       dwell_depth, maxage, sample)
         L.check(L.lib.pset_execute(self._h, float(runtime), float(dt), float(outputdt),
                                    C.byref(o), _stream(stream)))
+        if runtime > 0:
+            if output_stride > 0:
+                from .particlefile import record_times
+                self._stride = int(output_stride)
+                self._rec_times.extend(record_times(self._time, float(runtime),
+                                                    float(outputdt), float(dt),
+                                                    first=not self._rec_times))
+            self._time += float(runtime) if dt > 0 else -float(runtime)
+
+    def write_trajectories(self, path: str, **kw) -> int:
+        """Write the output records as a CF-1.6 indexed-ragged trajectory file
+        (particlefile.write_indexed); returns the number of observations."""
+        from .particlefile import write_indexed
+        recs = self.records()
+        if recs["lon"].shape[0] != len(self._rec_times):
+            raise RuntimeError("records were taken outside ParticleSet.execute; "
+                               "use particlefile.write_indexed with their times")
+        ids = np.arange(0, self.n, max(self._stride, 1))
+        return write_indexed(path, recs, self._rec_times, ids,
+                             spherical=self.fieldset.mesh == "spherical", **kw)
 
     def status(self):
         c = L.lp_counts()

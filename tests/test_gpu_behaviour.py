@@ -111,3 +111,24 @@ def test_behaviour_argument_errors():
     ps.execute(3600.0, 300.0, maxage=1800.0)
     c, st = ps.status()
     assert ((st & O.ST_AGED) != 0).sum() == c["n"] - c["oob"] - c["land"]
+
+
+def test_write_trajectories_from_gpu_records(tmp_path):
+    from scipy.io import netcdf_file
+    from paper_1707_05163_amd import FieldSet, ParticleSet
+    w = SC.foram_footprint(nx=70, ny=60, nz=20, n_particles=500, dt=-1800.0, days=16)
+    m = w.meta
+    fs = FieldSet.from_workload(w)
+    ps = ParticleSet(fs, w.lon0, w.lat0, w.depth0, t0=w.t0)
+    for _ in range(2):  # two calls: the record times carry on
+        ps.execute(8 * DAY, w.dt, DAY, output_stride=2, sink_speed=m["sink_speed"],
+                   dwell_depth=m["dwell_depth"], maxage=2 * DAY, sample=True)
+    recs = ps.records()
+    path = str(tmp_path / "gpu.nc")
+    nobs = ps.write_trajectories(path)
+    assert nobs == int((recs["status"] == 0).sum())
+    with netcdf_file(path, "r", mmap=False) as f:
+        t = f.variables["time"][:].copy()
+        assert f.dimensions["traj"] == int((recs["status"] == 0).any(axis=0).sum())
+        assert set(np.unique(t)) <= set(w.t0 - DAY * np.arange(17))
+        assert (f.variables["trajectory"][:] % 2 == 0).all()
