@@ -127,6 +127,16 @@ struct GemmArgs {
     float *dZ;                 // back-data: FP32 dz out
 };
 
+// Inference of the surrogate network 64 -> 256 x 4 -> 2 in one kernel: X [rows][64]
+// bf16 features, WT[l] bf16 [pad_out][fan_in], bias[l] FP32 [pad_out], Y [rows][2].
+struct MlpFusedArgs {
+    const uint16_t *X;
+    int64_t rows;            // multiple of 32
+    const uint16_t *WT[5];
+    const float *bias[5];
+    float *Y;
+};
+
 // launchers (return hipError_t of the launch)
 hipError_t launch_advect(int store, bool is3d, const AdvectParams &p, uint32_t n_launch,
                          hipStream_t s);
@@ -160,6 +170,7 @@ hipError_t launch_slot_values(int store, bool is3d, const void *slot, const floa
 hipError_t launch_lat_tables(const double *lat, int ny, double *coslat, double *sinlat,
                               hipStream_t s);
 hipError_t launch_gemm(int epi, const GemmArgs &g, hipStream_t s);
+hipError_t launch_mlp_fused(const MlpFusedArgs &a, hipStream_t s);
 hipError_t launch_loss_grad(const float *Y, const float *T, int64_t B, int ldy, float *dZ,
                             uint16_t *dZq, float *loss, hipStream_t s);
 hipError_t launch_colsum(const float *dZ, int64_t B, int N, float *db, hipStream_t s);

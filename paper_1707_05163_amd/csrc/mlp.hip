@@ -188,7 +188,171 @@ __global__ void k_to_bf16(const float *x, int64_t n, uint16_t *y)
         y[i] = bf16_bits(x[i]);
 }
 
+// ---------------------------------------------------------------- fused inference
+// The whole network on one tile of 256 rows per block, activations in registers.
+// Each layer is computed transposed, H^T = W^T A^T, so the weights are the matrix
+// core's A operand (read from LDS, where the block stages one layer at a time) and
+// the activations its B operand: lane l keeps 8 consecutive features of row
+// (l mod 32) for each k-step.  The accumulator of the 32x32x16 product leaves lane
+// l with features 8(v/4) + 4(l/32) + (v mod 4) of that row; two permlane32 swaps per
+// 32-feature block move each half-wave's missing four features across, which is
+// exactly the next layer's B-operand layout.  GELU in the sigmoid form
+// x / (1 + exp(-2u)), u = sqrt(2/pi) (x + 0.044715 x^3), on the hardware exp2 and
+// reciprocal; bf16 rounding by the round-to-nearest-even convert.
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kFusedRows = 256;      // rows per tile: 8 waves x 32
+constexpr int kFusedThreads = 512;
+constexpr int kLdsStride = 256 + 8;  // bf16 per staged weight row (padding against bank conflicts)
+
+__device__ inline float gelu_sigmoid(float x)
+{
+    constexpr float kLog2e = 1.4426950408889634f;
+    const float t = x * x;
+    const float m = x * fmaf(t, -2.f * kC0 * kC1 * kLog2e, -2.f * kC0 * kLog2e);
+    return x * __builtin_amdgcn_rcpf(1.f + __builtin_amdgcn_exp2f(m));
+}
+
+__device__ inline uint32_t pack_bf16(float a, float b)
+{
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2_t{a, b}, bf16x2_t));
+}
+
+// one layer: K inputs (16-wide k-steps in `in`), N (padded) outputs; the accumulators
+// start from the biases of the features each lane holds
+template <int K, int N>
+__device__ inline void fused_layer(const uint16_t *wl, const float *bl, int r, int h,
+                                   const bf16x8 (&in)[16], f32x16 (&acc)[8])
+{
+#pragma unroll
+    for (int nb = 0; nb < N / 32; ++nb) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float4 b = *reinterpret_cast<const float4 *>(bl + nb * 32 + 8 * q + 4 * h);
+            acc[nb][4 * q + 0] = b.x;
+            acc[nb][4 * q + 1] = b.y;
+            acc[nb][4 * q + 2] = b.z;
+            acc[nb][4 * q + 3] = b.w;
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < K / 16; ++s) {
+#pragma unroll
+        for (int nb = 0; nb < N / 32; ++nb) {
+            const bf16x8 w =
+                *reinterpret_cast<const bf16x8 *>(wl + (nb * 32 + r) * kLdsStride + 16 * s + 8 * h);
+            acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, in[s], acc[nb], 0, 0, 0);
+        }
+    }
+}
+
+// GELU + bf16, then the half-wave exchange into the next layer's operands
+__device__ inline void fused_hidden_epilogue(const f32x16 (&acc)[8], bf16x8 (&in)[16])
+{
+#pragma unroll
+    for (int nb = 0; nb < 8; ++nb) {
+        float g[16];
+#pragma unroll
+        for (int v = 0; v < 16; ++v)
+            g[v] = gelu_sigmoid(acc[nb][v]);
+        uint32_t P[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            P[j] = pack_bf16(g[2 * j], g[2 * j + 1]);
+        // lanes 32-63 of the first register trade places with lanes 0-31 of the second
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            auto lo = __builtin_amdgcn_permlane32_swap(P[j], P[j + 2], false, false);
+            P[j] = lo[0];
+            P[j + 2] = lo[1];
+            auto hi = __builtin_amdgcn_permlane32_swap(P[j + 4], P[j + 6], false, false);
+            P[j + 4] = hi[0];
+            P[j + 6] = hi[1];
+        }
+        in[2 * nb] = __builtin_bit_cast(bf16x8, u32x4_t{P[0], P[1], P[2], P[3]});
+        in[2 * nb + 1] = __builtin_bit_cast(bf16x8, u32x4_t{P[4], P[5], P[6], P[7]});
+    }
+}
+
+__device__ inline void stage_layer(uint16_t *wl, float *bl, const uint16_t *WT, const float *bias,
+                                   int N, int K)
+{
+    __syncthreads();  // every wave is done with the previous layer's weights
+    const int chunks = N * K / 8;
+    for (int c = threadIdx.x; c < chunks; c += kFusedThreads) {
+        const int n = c / (K / 8), kk = (c % (K / 8)) * 8;
+        *reinterpret_cast<u32x4_t *>(wl + n * kLdsStride + kk) =
+            *reinterpret_cast<const u32x4_t *>(WT + (size_t)n * K + kk);
+    }
+    for (int c = threadIdx.x; c < N; c += kFusedThreads)
+        bl[c] = bias[c];
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kFusedThreads) void k_mlp_fused(MlpFusedArgs a)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+    uint16_t *wl = reinterpret_cast<uint16_t *>(lds);
+    float *bl = reinterpret_cast<float *>(lds + 256 * kLdsStride * sizeof(uint16_t));
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, r = lane & 31, h = lane >> 5;
+    const int64_t ntile = (a.rows + kFusedRows - 1) / kFusedRows;
+    for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+        const int64_t row = tile * kFusedRows + wave * 32 + r;
+        const bool live = row < a.rows;
+        bf16x8 in[16];
+        f32x16 acc[8];
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+            in[s] = live ? *reinterpret_cast<const bf16x8 *>(a.X + row * 64 + 16 * s + 8 * h)
+                         : bf16x8{};
+        stage_layer(wl, bl, a.WT[0], a.bias[0], 256, 64);
+        fused_layer<64, 256>(wl, bl, r, h, in, acc);
+        fused_hidden_epilogue(acc, in);
+#pragma unroll 1
+        for (int l = 1; l < 4; ++l) {
+            stage_layer(wl, bl, a.WT[l], a.bias[l], 256, 256);
+            fused_layer<256, 256>(wl, bl, r, h, in, acc);
+            fused_hidden_epilogue(acc, in);
+        }
+        stage_layer(wl, bl, a.WT[4], a.bias[4], 32, 256);
+        fused_layer<256, 32>(wl, bl, r, h, in, acc);
+        // outputs 0 and 1 of the row sit in values 0 and 1 of the lower half-wave
+        if (live && h == 0) {
+            a.Y[row * 2 + 0] = acc[0][0];
+            a.Y[row * 2 + 1] = acc[0][1];
+        }
+    }
+}
+
 }  // namespace
+
+hipError_t launch_mlp_fused(const MlpFusedArgs &a, hipStream_t s)
+{
+    if (a.rows <= 0)
+        return hipSuccess;
+    if (a.rows % 32)
+        return hipErrorInvalidValue;
+    const size_t lds = 256 * kLdsStride * sizeof(uint16_t) + 256 * sizeof(float);
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_mlp_fused,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess)
+            return e;
+        attr = true;
+    }
+    int cus = 0, dev = 0;
+    hipError_t e;
+    if ((e = hipGetDevice(&dev)) != hipSuccess ||
+        (e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+        return e;
+    const int64_t ntile = (a.rows + kFusedRows - 1) / kFusedRows;
+    const uint32_t grid = (uint32_t)(ntile < cus ? ntile : cus);
+    hipLaunchKernelGGL(k_mlp_fused, dim3(grid), dim3(kFusedThreads), lds, s, a);
+    return hipGetLastError();
+}
 
 hipError_t launch_gemm(int epi, const GemmArgs &g, hipStream_t s)
 {

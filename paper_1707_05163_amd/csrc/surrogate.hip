@@ -474,9 +474,23 @@ int refresh_bf16(lp_model *m, hipStream_t s)
     return LP_OK;
 }
 
-// forward over `rows` (multiple of 128) rows of m->X; keeps pre-activations if train
+// forward over `rows` (multiple of 128) rows of m->X; keeps pre-activations if train.
+// Inference runs the fused kernel (activations never leave the chip); training runs
+// the layer-by-layer GEMMs, which store what the backward pass needs.
 int forward(lp_model *m, int64_t rows, bool train, hipStream_t s)
 {
+    if (!train) {
+        lp::MlpFusedArgs a{};
+        a.X = m->X;
+        a.rows = rows;
+        for (int l = 0; l < kLayers; ++l) {
+            a.WT[l] = m->WT[l];
+            a.bias[l] = m->b[l];
+        }
+        a.Y = m->Y;
+        SCHECK(lp::launch_mlp_fused(a, s));
+        return LP_OK;
+    }
     const uint16_t *in = m->X;
     for (int l = 0; l < kLayers; ++l) {
         GemmArgs g{};

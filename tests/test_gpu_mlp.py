@@ -78,3 +78,18 @@ def test_training_reduces_loss_on_a_fixed_batch():
     X, T = _batch(1024, seed=11)
     losses = [s.train_step(X, T, lr=3e-3) for _ in range(60)]
     assert losses[-1] < 0.2 * losses[0]
+
+
+def test_fused_inference_matches_layerwise_forward():
+    """The inference kernel (all layers fused, activations in registers) against the
+    training forward (layer-by-layer GEMMs) through the loss both report, on a
+    batch spanning many 256-row tiles (several per block)."""
+    s, W, b = _net()
+    B = 100_096
+    X, T = _batch(B)
+    y = s.forward(X).astype(np.float64)
+    loss_fused = 0.5 * np.mean(np.sum((y - T) ** 2, axis=1))
+    _, loss_layerwise = s.gradients(X, T)
+    assert abs(loss_fused - loss_layerwise) <= 2e-3 * loss_layerwise
+    yo, _ = M.forward(W, b, X[:2048].astype(np.float64), mirror=True)
+    assert _rel(y[:2048], yo) < 2e-3
