@@ -14,6 +14,8 @@
 // Storage types: LP_F64 / LP_F32 snapshots are interpolated in FP64; LP_BF16 and
 // LP_F16_SCALED snapshots are interpolated in FP32 and only the position update
 // runs in FP64.
+#include <type_traits>
+
 #include "lp_internal.h"
 
 namespace lp {
@@ -697,11 +699,24 @@ struct Cell2 {
                             // upper end needs no separate test)
     double rx, ry;          // inverse cell widths
     double cl, sl;          // cos and sin of the lower latitude face
-    R a[2][4];              // earlier snapshot: U, V coefficients
-    R d[2][4];              // later minus earlier
+    R *lc;                  // this lane's LDS slot: U, V coefficients of the earlier
+                            // snapshot [0..7], later minus earlier [8..15]
     bool land;
     bool valid;
 };
+
+// Per-lane LDS slots of the 2D stencil cache: 16 coefficients plus padding, a stride
+// of 144 B (double) or 80 B (float) that keeps every 16-byte read aligned and puts
+// the 16 lanes of one LDS cycle on distinct banks.
+template <class R>
+constexpr int cache_slot() { return sizeof(R) == 8 ? 18 : 20; }
+
+template <class R>
+__device__ inline R *cache_slot_ptr()
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char cache_lds[];
+    return reinterpret_cast<R *>(cache_lds) + threadIdx.x * cache_slot<R>();
+}
 
 template <class R>
 __device__ inline void coeffs(const R f00, const R f10, const R f01, const R f11, R c[4])
@@ -759,17 +774,24 @@ __device__ inline bool reload2(const AdvectParams &P, Cell2<typename Real<ST>::T
         load_node<ST, false>(B, n00 + nx + 1, scb, q11);
 #pragma unroll
         for (int v = 0; v < 2; ++v) {
-            R cb[4];
+            R ca[4], cb[4];
             coeffs<R>(q00[v], q10[v], q01[v], q11[v], cb);
-            coeffs<R>(p00[v], p10[v], p01[v], p11[v], c.a[v]);
+            coeffs<R>(p00[v], p10[v], p01[v], p11[v], ca);
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-                c.d[v][q] = cb[q] - c.a[v][q];
+            for (int q = 0; q < 4; ++q) {
+                c.lc[4 * v + q] = ca[q];
+                c.lc[8 + 4 * v + q] = cb[q] - ca[q];
+            }
         }
     } else {
 #pragma unroll
-        for (int v = 0; v < 2; ++v)
-            coeffs<R>(p00[v], p10[v], p01[v], p11[v], c.a[v]);
+        for (int v = 0; v < 2; ++v) {
+            R ca[4];
+            coeffs<R>(p00[v], p10[v], p01[v], p11[v], ca);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                c.lc[4 * v + q] = ca[q];
+        }
     }
     c.valid = true;
     return true;
@@ -813,15 +835,21 @@ __device__ inline double cos_series(double cl, double sl, double y0, double y, i
     return cl * cd - sl * sd;
 }
 
-template <class R>
+// Metric modes of the cached kernels, fixed at compile time so that a launch carries
+// only the code it runs: flat mesh; spherical with the latitude tables and series;
+// spherical with cells too tall for the series (library cos).
+enum : int { kFlat = 0, kSphTable = 1, kSphLib = 2 };
+
+template <int MET, class R>
 __device__ inline double cos_lat(const Cell2<R> &c, const AdvectParams &P, double y)
 {
-    if (!P.g.coslat)
+    if constexpr (MET == kSphLib)
         return cos(y * kDegToRad);
-    return cos_series(c.cl, c.sl, c.y0, y, P.g.cos_terms);
+    else
+        return cos_series(c.cl, c.sl, c.y0, y, P.g.cos_terms);
 }
 
-template <int ST, bool STEADY, bool SPH>
+template <int ST, bool STEADY, int MET>
 __device__ inline bool stage2(const AdvectParams &P, Cell2<typename Real<ST>::T> &c,
                               const TimeEntry &e, double x, double y, double &kx, double &ky)
 {
@@ -831,14 +859,15 @@ __device__ inline bool stage2(const AdvectParams &P, Cell2<typename Real<ST>::T>
             return false;
     }
     const R xi = (R)((x - c.x0) * c.rx), eta = (R)((y - c.y0) * c.ry);
-    R u = poly<R>(c.a[0], xi, eta), v = poly<R>(c.a[1], xi, eta);
+    const R *q = c.lc;
+    R u = poly<R>(q + 0, xi, eta), v = poly<R>(q + 4, xi, eta);
     if constexpr (!STEADY) {
         const R tau = (R)e.tau;
-        u = fma(tau, poly<R>(c.d[0], xi, eta), u);
-        v = fma(tau, poly<R>(c.d[1], xi, eta), v);
+        u = fma(tau, poly<R>(q + 8, xi, eta), u);
+        v = fma(tau, poly<R>(q + 12, xi, eta), v);
     }
-    if constexpr (SPH) {
-        kx = (double)u * recip(kMetresPerDegree * cos_lat(c, P, y));
+    if constexpr (MET != kFlat) {
+        kx = (double)u * recip(kMetresPerDegree * cos_lat<MET>(c, P, y));
         ky = (double)v * (1.0 / kMetresPerDegree);
     } else {
         kx = (double)u;
@@ -849,7 +878,7 @@ __device__ inline bool stage2(const AdvectParams &P, Cell2<typename Real<ST>::T>
 
 // One particle (position k of the processing order) for all steps of the launch;
 // returns the number of steps it started active.
-template <int ST, bool STEADY, bool SPH>
+template <int ST, bool STEADY, int MET, bool BROWN>
 __device__ inline long long advect_lane_2d(const AdvectParams &P, uint32_t k, uint32_t nact)
 {
     using R = typename Real<ST>::T;
@@ -861,6 +890,7 @@ __device__ inline long long advect_lane_2d(const AdvectParams &P, uint32_t k, ui
             double x = P.x[id], y = P.y[id];
             Cell2<R> c;
             c.valid = false;
+            c.lc = cache_slot_ptr<R>();
             int csa = -1, csb = -1;  // bracket the cached stencils belong to
             const double dt = P.dt, hd = 0.5 * dt, dt6 = dt * (1.0 / 6.0);
             for (int s = 0; s < P.nsteps; ++s) {
@@ -884,7 +914,7 @@ __device__ inline long long advect_lane_2d(const AdvectParams &P, uint32_t k, ui
                         csa = e.sa;
                         csb = e.sb;
                     }
-                    if (!stage2<ST, STEADY, SPH>(P, c, e, x + kx * h, y + ky * h, kx, ky))
+                    if (!stage2<ST, STEADY, MET>(P, c, e, x + kx * h, y + ky * h, kx, ky))
                         goto fail;
                     sx = fma(wq, kx, sx);
                     sy = fma(wq, ky, sy);
@@ -898,7 +928,7 @@ __device__ inline long long advect_lane_2d(const AdvectParams &P, uint32_t k, ui
                         xs = x + (sx + kx) * dt6;
                         ys = y + (sy + ky) * dt6;
                     }
-                    if (P.Kh > 0.0) {
+                    if (BROWN && P.Kh > 0.0) {
                         uint32_t w[4] = {id, (uint32_t)(P.step0 + s), 0u, 0u};
                         philox4x32_10(w, P.run_id, P.seed);
                         const double u1 = unit53(w[0], w[1]), u2 = unit53(w[2], w[3]);
@@ -907,7 +937,7 @@ __device__ inline long long advect_lane_2d(const AdvectParams &P, uint32_t k, ui
                         sincos((2.0 * 3.141592653589793) * u2, &sn, &cs);
                         const double sig = sqrt(2.0 * P.Kh * dt);
                         double dx = sig * (r * cs), dy = sig * (r * sn);
-                        if constexpr (SPH) {
+                        if constexpr (MET != kFlat) {
                             dx = dx / (kMetresPerDegree * cos(ys * kDegToRad));
                             dy = dy / kMetresPerDegree;
                         }
@@ -946,12 +976,12 @@ __device__ inline long long advect_lane_2d(const AdvectParams &P, uint32_t k, ui
     return steps;
 }
 
-template <int ST, bool STEADY, bool SPH>
+template <int ST, bool STEADY, int MET, bool BROWN>
 __global__ __launch_bounds__(kBlock) void k_advect2d(AdvectParams P)
 {
     const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
     const uint32_t k = blk * kBlock + threadIdx.x;
-    long long steps = advect_lane_2d<ST, STEADY, SPH>(P, k, *P.n_active);
+    long long steps = advect_lane_2d<ST, STEADY, MET, BROWN>(P, k, *P.n_active);
     for (int off = 32; off > 0; off >>= 1)
         steps += __shfl_xor(steps, off, 64);
     if ((threadIdx.x & 63) == 0 && steps)
@@ -985,7 +1015,7 @@ __constant__ double kRkfE[6] = {16.0 / 135.0 - 25.0 / 216.0, 0.0,
                                 28561.0 / 56430.0 - 2197.0 / 4104.0, -9.0 / 50.0 + 1.0 / 5.0,
                                 2.0 / 55.0};
 
-template <int ST, bool STEADY, bool SPH>
+template <int ST, bool STEADY, int MET>
 struct CachedLane2 {
     using R = typename Real<ST>::T;
     RkfState s;
@@ -1004,6 +1034,7 @@ struct CachedLane2 {
         x = P.x[id];
         y = P.y[id];
         c.valid = false;
+        c.lc = cache_slot_ptr<R>();
         csa = csb = -1;
         lt.lo = -1;
     }
@@ -1037,7 +1068,7 @@ struct CachedLane2 {
                 csb = ent.sb;
             }
             double kx, ky;
-            if (!stage2<ST, STEADY, SPH>(P, c, ent, x + hs * ax, y + hs * ay, kx, ky)) {
+            if (!stage2<ST, STEADY, MET>(P, c, ent, x + hs * ax, y + hs * ay, kx, ky)) {
                 ++acc;
                 s.st = (uint8_t)(ST_OOB | extra);
                 return true;
@@ -1056,7 +1087,7 @@ struct CachedLane2 {
             }
         }
         double ex = hs * sex, ey = hs * sey;
-        if constexpr (SPH) {
+        if constexpr (MET != kFlat) {
             ex = ex * (kMetresPerDegree * cos(y * kDegToRad));
             ey = ey * kMetresPerDegree;
         }
@@ -1167,13 +1198,13 @@ __global__ __launch_bounds__(kBlock) void k_rkf45(AdvectParams P)
     rkf45_refill<GatherLane<ST, IS3D, STEADY>>(P);
 }
 
-template <int ST, bool STEADY, bool SPH>
+template <int ST, bool STEADY, int MET>
 __global__ __launch_bounds__(kBlock) void k_rkf45_2d(AdvectParams P)
 {
-    rkf45_refill<CachedLane2<ST, STEADY, SPH>>(P);
+    rkf45_refill<CachedLane2<ST, STEADY, MET>>(P);
 }
 
-template <int ST, bool STEADY, bool SPH>
+template <int ST, bool STEADY, int MET, bool BROWN>
 __global__ __launch_bounds__(512) void k_advect2d_batch(const AdvectParams *runs,
                                                         const uint32_t *cstart, int nruns,
                                                         uint32_t total, uint32_t *queues)
@@ -1215,7 +1246,7 @@ __global__ __launch_bounds__(512) void k_advect2d_batch(const AdvectParams *runs
         const int r = __builtin_amdgcn_readfirstlane(lo);
         const AdvectParams &P = runs[r];
         const uint32_t k = (it - cstart[r]) * blockDim.x + threadIdx.x;
-        long long steps = advect_lane_2d<ST, STEADY, SPH>(P, k, *P.n_active);
+        long long steps = advect_lane_2d<ST, STEADY, MET, BROWN>(P, k, *P.n_active);
         for (int off = 32; off > 0; off >>= 1)
             steps += __shfl_xor(steps, off, 64);
         if ((threadIdx.x & 63) == 0 && steps)
@@ -1338,7 +1369,7 @@ __device__ inline bool in_cell3(const Cell3<R> &c, const AdvectParams &P, double
     return c.valid && x >= c.x0 && x < c.ux && y >= c.y0 && y < c.uy && z >= c.z0 && z < c.uz;
 }
 
-template <int ST, bool STEADY, bool SPH>
+template <int ST, bool STEADY, int MET>
 __device__ inline bool stage3(const AdvectParams &P, Cell3<typename Real<ST>::T> &c,
                               const TimeEntry &e, double x, double y, double z, double k[3])
 {
@@ -1356,9 +1387,12 @@ __device__ inline bool stage3(const AdvectParams &P, Cell3<typename Real<ST>::T>
         if constexpr (!STEADY)
             v[q] = fma((R)e.tau, poly3<R>(c.d[q], xi, eta, zeta), v[q]);
     }
-    if constexpr (SPH) {
-        const double cosl = P.g.coslat ? cos_series(c.cl, c.sl, c.y0, y, P.g.cos_terms)
-                                       : cos(y * kDegToRad);
+    if constexpr (MET != kFlat) {
+        double cosl;
+        if constexpr (MET == kSphLib)
+            cosl = cos(y * kDegToRad);
+        else
+            cosl = cos_series(c.cl, c.sl, c.y0, y, P.g.cos_terms);
         k[0] = (double)v[0] * recip(kMetresPerDegree * cosl);
         k[1] = (double)v[1] * (1.0 / kMetresPerDegree);
     } else {
@@ -1369,7 +1403,7 @@ __device__ inline bool stage3(const AdvectParams &P, Cell3<typename Real<ST>::T>
     return true;
 }
 
-template <int ST, bool STEADY, bool SPH>
+template <int ST, bool STEADY, int MET, bool BROWN>
 __global__ __launch_bounds__(kBlock) void k_advect3d(AdvectParams P)
 {
     using R = typename Real<ST>::T;
@@ -1401,7 +1435,7 @@ __global__ __launch_bounds__(kBlock) void k_advect3d(AdvectParams P)
                         csa = e.sa;
                         csb = e.sb;
                     }
-                    if (!stage3<ST, STEADY, SPH>(P, c, e, x + k[0] * h, y + k[1] * h,
+                    if (!stage3<ST, STEADY, MET>(P, c, e, x + k[0] * h, y + k[1] * h,
                                                  z + k[2] * h, k))
                         goto fail;
                     const double wq = q == 0 ? 1.0 : (q == 3 ? 0.0 : 2.0);
@@ -1420,7 +1454,7 @@ __global__ __launch_bounds__(kBlock) void k_advect3d(AdvectParams P)
                         ys = y + (sm[1] + k[1]) * dt6;
                         zs = z + (sm[2] + k[2]) * dt6;
                     }
-                    if (P.Kh > 0.0) {
+                    if (BROWN && P.Kh > 0.0) {
                         uint32_t w[4] = {id, (uint32_t)(P.step0 + s), 0u, 0u};
                         philox4x32_10(w, P.run_id, P.seed);
                         const double u1 = unit53(w[0], w[1]), u2 = unit53(w[2], w[3]);
@@ -1429,7 +1463,7 @@ __global__ __launch_bounds__(kBlock) void k_advect3d(AdvectParams P)
                         sincos((2.0 * 3.141592653589793) * u2, &sn, &cs);
                         const double sig = sqrt(2.0 * P.Kh * dt);
                         double dx = sig * (r * cs), dy = sig * (r * sn);
-                        if constexpr (SPH) {
+                        if constexpr (MET != kFlat) {
                             dx = dx / (kMetresPerDegree * cos(ys * kDegToRad));
                             dy = dy / kMetresPerDegree;
                         }
@@ -1557,6 +1591,37 @@ __global__ void k_record(RecordParams R)
     }
 }
 
+template <bool B> using BoolC = std::integral_constant<bool, B>;
+template <int I> using IntC = std::integral_constant<int, I>;
+
+// Calls f(steady, metric mode, Brownian) with compile-time constants chosen from the
+// launch: the cached kernels are instantiated per combination.
+template <class F>
+hipError_t dispatch_cached(const AdvectParams &p, bool steady, F &&f)
+{
+    const int met = !p.g.spherical ? kFlat : (p.g.coslat ? kSphTable : kSphLib);
+    const bool brown = p.Kh > 0.0;
+    auto with_met = [&](auto stc) {
+        auto with_brown = [&](auto m) {
+            if (brown)
+                f(stc, m, BoolC<true>{});
+            else
+                f(stc, m, BoolC<false>{});
+        };
+        if (met == kFlat)
+            with_brown(IntC<kFlat>{});
+        else if (met == kSphTable)
+            with_brown(IntC<kSphTable>{});
+        else
+            with_brown(IntC<kSphLib>{});
+    };
+    if (steady)
+        with_met(BoolC<true>{});
+    else
+        with_met(BoolC<false>{});
+    return hipGetLastError();
+}
+
 template <int ST, bool IS3D>
 hipError_t launch3(const AdvectParams &p, bool steady, uint32_t n_launch, hipStream_t s)
 {
@@ -1571,34 +1636,21 @@ hipError_t launch3(const AdvectParams &p, bool steady, uint32_t n_launch, hipStr
             hipLaunchKernelGGL((k_advect<ST, IS3D, false>), dim3(blocks), dim3(kBlock), 0, s, p);
         return hipGetLastError();
     }
+    const dim3 g(blocks), b(kBlock);
     if constexpr (!IS3D) {
-        const dim3 g(blocks), b(kBlock);
-        if (p.g.spherical) {
-            if (steady)
-                hipLaunchKernelGGL((k_advect2d<ST, true, true>), g, b, 0, s, p);
-            else
-                hipLaunchKernelGGL((k_advect2d<ST, false, true>), g, b, 0, s, p);
-        } else {
-            if (steady)
-                hipLaunchKernelGGL((k_advect2d<ST, true, false>), g, b, 0, s, p);
-            else
-                hipLaunchKernelGGL((k_advect2d<ST, false, false>), g, b, 0, s, p);
-        }
-        return hipGetLastError();
+        using R = typename Real<ST>::T;
+        const size_t lds = (size_t)kBlock * cache_slot<R>() * sizeof(R);
+        return dispatch_cached(p, steady, [&](auto stc, auto met, auto brown) {
+            hipLaunchKernelGGL((k_advect2d<ST, decltype(stc)::value, decltype(met)::value,
+                                           decltype(brown)::value>),
+                               g, b, lds, s, p);
+        });
     } else {
-        const dim3 g(blocks), b(kBlock);
-        if (p.g.spherical) {
-            if (steady)
-                hipLaunchKernelGGL((k_advect3d<ST, true, true>), g, b, 0, s, p);
-            else
-                hipLaunchKernelGGL((k_advect3d<ST, false, true>), g, b, 0, s, p);
-        } else {
-            if (steady)
-                hipLaunchKernelGGL((k_advect3d<ST, true, false>), g, b, 0, s, p);
-            else
-                hipLaunchKernelGGL((k_advect3d<ST, false, false>), g, b, 0, s, p);
-        }
-        return hipGetLastError();
+        return dispatch_cached(p, steady, [&](auto stc, auto met, auto brown) {
+            hipLaunchKernelGGL((k_advect3d<ST, decltype(stc)::value, decltype(met)::value,
+                                           decltype(brown)::value>),
+                               g, b, 0, s, p);
+        });
     }
 }
 
@@ -1626,10 +1678,11 @@ namespace {
 // Persistent grid: as many blocks as fit on the device at once (no more than the
 // particles need); the eight queues are cleared on the stream first.
 template <class K>
-hipError_t launch_persistent(K kern, const AdvectParams &p, uint32_t n_launch, hipStream_t s)
+hipError_t launch_persistent(K kern, const AdvectParams &p, uint32_t n_launch, hipStream_t s,
+                             size_t lds = 0)
 {
     int per_cu = 0, cus = 0, dev = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlock, 0);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlock, lds);
     if (e != hipSuccess)
         return e;
     if ((e = hipGetDevice(&dev)) != hipSuccess ||
@@ -1640,7 +1693,7 @@ hipError_t launch_persistent(K kern, const AdvectParams &p, uint32_t n_launch, h
     grid = grid < need ? grid : need;
     if ((e = launch_fill_u32(p.queues, 0u, 8, s)) != hipSuccess)
         return e;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, p);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), lds, s, p);
     return hipGetLastError();
 }
 
@@ -1651,11 +1704,14 @@ hipError_t rkf3(const AdvectParams &p, bool steady, uint32_t n_launch, hipStream
         return hipSuccess;
     if constexpr (!IS3D) {
         if (p.cache && !p.nearest) {
-            if (p.g.spherical)
-                return steady ? launch_persistent(k_rkf45_2d<ST, true, true>, p, n_launch, s)
-                              : launch_persistent(k_rkf45_2d<ST, false, true>, p, n_launch, s);
-            return steady ? launch_persistent(k_rkf45_2d<ST, true, false>, p, n_launch, s)
-                          : launch_persistent(k_rkf45_2d<ST, false, false>, p, n_launch, s);
+            using R = typename Real<ST>::T;
+            const size_t lds = (size_t)kBlock * cache_slot<R>() * sizeof(R);
+            hipError_t e = hipSuccess;
+            (void)dispatch_cached(p, steady, [&](auto stc, auto met, auto) {
+                e = launch_persistent(k_rkf45_2d<ST, decltype(stc)::value, decltype(met)::value>,
+                                      p, n_launch, s, lds);
+            });
+            return e;
         }
     }
     return steady ? launch_persistent(k_rkf45<ST, IS3D, true>, p, n_launch, s)
@@ -1722,13 +1778,15 @@ hipError_t launch_lat_tables(const double *lat, int ny, double *coslat, double *
     return hipGetLastError();
 }
 
-template <int ST, bool STEADY, bool SPH>
+template <int ST, bool STEADY, int MET, bool BROWN>
 hipError_t batch3(const AdvectParams *runs, const uint32_t *cstart, int nruns, uint32_t total,
                   uint32_t *queues, int block, hipStream_t s, int *grid_out)
 {
-    auto kern = k_advect2d_batch<ST, STEADY, SPH>;
+    auto kern = k_advect2d_batch<ST, STEADY, MET, BROWN>;
+    using R = typename Real<ST>::T;
+    const size_t lds = (size_t)block * cache_slot<R>() * sizeof(R);
     int per_cu = 0, cus = 0, dev = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, 0);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, lds);
     if (e != hipSuccess)
         return e;
     if ((e = hipGetDevice(&dev)) != hipSuccess ||
@@ -1741,30 +1799,37 @@ hipError_t batch3(const AdvectParams *runs, const uint32_t *cstart, int nruns, u
         grid = (int)(total ? total : 1);
     if (grid_out)
         *grid_out = grid;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, s, runs, cstart, nruns, total, queues);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, s, runs, cstart, nruns, total, queues);
     return hipGetLastError();
 }
 
-hipError_t launch_advect_batch(int store, bool steady, bool spherical, const AdvectParams *runs,
-                               const uint32_t *cstart, int nruns, uint32_t total,
-                               uint32_t *queues, int block, hipStream_t s, int *grid_out)
+hipError_t launch_advect_batch(int store, bool steady, int met, bool brown,
+                               const AdvectParams *runs, const uint32_t *cstart, int nruns,
+                               uint32_t total, uint32_t *queues, int block, hipStream_t s,
+                               int *grid_out)
 {
     hipError_t e = launch_fill_u32(queues, 0u, 8, s);
     if (e != hipSuccess || total == 0)
         return e;
-#define LP_B(ST)                                                                                \
-    if (spherical)                                                                              \
-        return steady ? batch3<ST, true, true>(runs, cstart, nruns, total, queues, block, s, grid_out)  \
-                      : batch3<ST, false, true>(runs, cstart, nruns, total, queues, block, s, grid_out); \
-    return steady ? batch3<ST, true, false>(runs, cstart, nruns, total, queues, block, s, grid_out)     \
-                  : batch3<ST, false, false>(runs, cstart, nruns, total, queues, block, s, grid_out);
+    auto go = [&](auto st) -> hipError_t {
+        constexpr int ST = decltype(st)::value;
+        AdvectParams q{};  // only the mode fields matter to the dispatcher
+        q.g.spherical = met != kFlat;
+        q.g.coslat = met == kSphTable ? reinterpret_cast<const double *>(1) : nullptr;
+        q.Kh = brown ? 1.0 : 0.0;
+        hipError_t r = hipSuccess;
+        (void)dispatch_cached(q, steady, [&](auto stc, auto m, auto b) {
+            r = batch3<ST, decltype(stc)::value, decltype(m)::value, decltype(b)::value>(
+                runs, cstart, nruns, total, queues, block, s, grid_out);
+        });
+        return r;
+    };
     switch (store) {
-    case kF64: { LP_B(kF64) }
-    case kF32: { LP_B(kF32) }
-    case kBF16: { LP_B(kBF16) }
-    case kF16S: { LP_B(kF16S) }
+    case kF64: return go(IntC<kF64>{});
+    case kF32: return go(IntC<kF32>{});
+    case kBF16: return go(IntC<kBF16>{});
+    case kF16S: return go(IntC<kF16S>{});
     }
-#undef LP_B
     return hipErrorInvalidValue;
 }
 

@@ -1198,9 +1198,19 @@ int execute_batch(lp_pset **ps, int32_t nruns, double runtime, double dt, double
             HIPCHECK(hipEventCreate(&e1));
             HIPCHECK(hipEventRecord(e0, stream));
         }
-        HIPCHECK(lp::launch_advect_batch(f0->dtype, f0->npushed == 1, f0->g.spherical != 0,
-                                         b.druns, b.dcstart, nruns, total, b.dqueues, block,
-                                         stream, nullptr));
+        int met = 0;
+        bool brown = false;
+        if (f0->g.spherical) {
+            met = 1;
+            for (int r = 0; r < nruns; ++r)
+                if (!ps[r]->fs->g.coslat)
+                    met = 2;  // some grid has cells too tall for the latitude series
+        }
+        for (int r = 0; r < nruns; ++r)
+            brown = brown || opts[r].Kh > 0.0;
+        HIPCHECK(lp::launch_advect_batch(f0->dtype, f0->npushed == 1, met, brown, b.druns,
+                                         b.dcstart, nruns, total, b.dqueues, block, stream,
+                                         nullptr));
         if (prof) {
             HIPCHECK(hipEventRecord(e1, stream));
             if (kernel_ms) {

@@ -143,9 +143,12 @@ hipError_t launch_advect(int store, bool is3d, const AdvectParams &p, uint32_t n
 hipError_t launch_rkf45(int store, bool is3d, const AdvectParams &p, uint32_t n_launch,
                         hipStream_t s);
 hipError_t launch_record(const RecordParams &p, hipStream_t s);
-hipError_t launch_advect_batch(int store, bool steady, bool spherical, const AdvectParams *runs,
-                               const uint32_t *cstart, int nruns, uint32_t total,
-                               uint32_t *queues, int block, hipStream_t s, int *grid_out);
+// batched launch: met 0 flat, 1 spherical with latitude tables, 2 spherical without;
+// brown: some run has a Brownian term
+hipError_t launch_advect_batch(int store, bool steady, int met, bool brown,
+                               const AdvectParams *runs, const uint32_t *cstart, int nruns,
+                               uint32_t total, uint32_t *queues, int block, hipStream_t s,
+                               int *grid_out);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
 hipError_t launch_iota(uint32_t *p, size_t n, hipStream_t s);
 hipError_t launch_compact(const uint32_t *order_in, const uint32_t *n_in, const uint8_t *status,
