@@ -16,7 +16,7 @@ LP_OK, LP_EINVAL, LP_ENOMEM, LP_EDEVICE, LP_ETIME, LP_ESTATE = 0, -1, -2, -3, -4
 LP_MESH_FLAT, LP_MESH_SPHERICAL = 0, 1
 LP_F64, LP_F32, LP_BF16, LP_F16_SCALED = 0, 1, 2, 3
 LP_DELETE, LP_FREEZE = 0, 1
-LP_ST_OOB, LP_ST_LAND, LP_ST_DELETED = 1, 2, 4
+LP_ST_OOB, LP_ST_LAND, LP_ST_DELETED, LP_ST_AGED = 1, 2, 4, 8
 LP_KERNEL_RK4 = 0
 LP_KERNEL_EULER = 1
 LP_KERNEL_RKF45 = 2
