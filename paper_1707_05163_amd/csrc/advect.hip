@@ -692,14 +692,17 @@ struct GatherLane {
 // leaves the cell or when the time bracket moves on.  The polynomial is the same
 // bilinear interpolant as the corner-weight form (Sect. 2.3), and f_a + tau (f_b -
 // f_a) is the same linear time interpolation (Sect. 2.4); only rounding differs.
-template <class R>
+// The 16 coefficients sit either in the lane's LDS slot (SHARED: fewer registers, so
+// more waves per SIMD) or in registers (when the kernel's other state keeps the
+// occupancy at the same level either way, as with the Brownian term).
+template <class R, bool SHARED>
 struct Cell2 {
     double x0, ux, y0, uy;  // lower faces; exclusive upper faces (for the last cell the
                             // next double above the last node, so the domain's closed
                             // upper end needs no separate test)
     double rx, ry;          // inverse cell widths
     double cl, sl;          // cos and sin of the lower latitude face
-    R *lc;                  // this lane's LDS slot: U, V coefficients of the earlier
+    std::conditional_t<SHARED, R *, R[16]> lc;  // U, V coefficients of the earlier
                             // snapshot [0..7], later minus earlier [8..15]
     bool land;
     bool valid;
@@ -733,8 +736,8 @@ __device__ inline R poly(const R c[4], R xi, R eta)
     return fma(eta, fma(xi, c[3], c[2]), fma(xi, c[1], c[0]));
 }
 
-template <int ST, bool STEADY>
-__device__ inline bool reload2(const AdvectParams &P, Cell2<typename Real<ST>::T> &c, int sa,
+template <int ST, bool STEADY, bool SH>
+__device__ inline bool reload2(const AdvectParams &P, Cell2<typename Real<ST>::T, SH> &c, int sa,
                                int sb, double x, double y)
 {
     using R = typename Real<ST>::T;
@@ -797,8 +800,8 @@ __device__ inline bool reload2(const AdvectParams &P, Cell2<typename Real<ST>::T
     return true;
 }
 
-template <class R>
-__device__ inline bool in_cell(const Cell2<R> &c, const AdvectParams &P, double x, double y)
+template <class R, bool SH>
+__device__ inline bool in_cell(const Cell2<R, SH> &c, const AdvectParams &P, double x, double y)
 {
     return c.valid && x >= c.x0 && x < c.ux && y >= c.y0 && y < c.uy;
 }
@@ -840,8 +843,8 @@ __device__ inline double cos_series(double cl, double sl, double y0, double y, i
 // spherical with cells too tall for the series (library cos).
 enum : int { kFlat = 0, kSphTable = 1, kSphLib = 2 };
 
-template <int MET, class R>
-__device__ inline double cos_lat(const Cell2<R> &c, const AdvectParams &P, double y)
+template <int MET, class R, bool SH>
+__device__ inline double cos_lat(const Cell2<R, SH> &c, const AdvectParams &P, double y)
 {
     if constexpr (MET == kSphLib)
         return cos(y * kDegToRad);
@@ -849,13 +852,13 @@ __device__ inline double cos_lat(const Cell2<R> &c, const AdvectParams &P, doubl
         return cos_series(c.cl, c.sl, c.y0, y, P.g.cos_terms);
 }
 
-template <int ST, bool STEADY, int MET>
-__device__ inline bool stage2(const AdvectParams &P, Cell2<typename Real<ST>::T> &c,
+template <int ST, bool STEADY, int MET, bool SH>
+__device__ inline bool stage2(const AdvectParams &P, Cell2<typename Real<ST>::T, SH> &c,
                               const TimeEntry &e, double x, double y, double &kx, double &ky)
 {
     using R = typename Real<ST>::T;
     if (!in_cell(c, P, x, y)) {
-        if (!reload2<ST, STEADY>(P, c, e.sa, e.sb, x, y))
+        if (!reload2<ST, STEADY, SH>(P, c, e.sa, e.sb, x, y))
             return false;
     }
     const R xi = (R)((x - c.x0) * c.rx), eta = (R)((y - c.y0) * c.ry);
@@ -888,9 +891,10 @@ __device__ inline long long advect_lane_2d(const AdvectParams &P, uint32_t k, ui
         uint8_t st = P.status[id];
         if (st == 0) {
             double x = P.x[id], y = P.y[id];
-            Cell2<R> c;
+            Cell2<R, !BROWN> c;
             c.valid = false;
-            c.lc = cache_slot_ptr<R>();
+            if constexpr (!BROWN)
+                c.lc = cache_slot_ptr<R>();
             int csa = -1, csb = -1;  // bracket the cached stencils belong to
             const double dt = P.dt, hd = 0.5 * dt, dt6 = dt * (1.0 / 6.0);
             for (int s = 0; s < P.nsteps; ++s) {
@@ -914,7 +918,7 @@ __device__ inline long long advect_lane_2d(const AdvectParams &P, uint32_t k, ui
                         csa = e.sa;
                         csb = e.sb;
                     }
-                    if (!stage2<ST, STEADY, MET>(P, c, e, x + kx * h, y + ky * h, kx, ky))
+                    if (!stage2<ST, STEADY, MET, !BROWN>(P, c, e, x + kx * h, y + ky * h, kx, ky))
                         goto fail;
                     sx = fma(wq, kx, sx);
                     sy = fma(wq, ky, sy);
@@ -1020,7 +1024,7 @@ struct CachedLane2 {
     using R = typename Real<ST>::T;
     RkfState s;
     double x, y;
-    Cell2<R> c;
+    Cell2<R, true> c;
     int32_t csa, csb;
     LaneTime lt;
 
@@ -1068,7 +1072,7 @@ struct CachedLane2 {
                 csb = ent.sb;
             }
             double kx, ky;
-            if (!stage2<ST, STEADY, MET>(P, c, ent, x + hs * ax, y + hs * ay, kx, ky)) {
+            if (!stage2<ST, STEADY, MET, true>(P, c, ent, x + hs * ax, y + hs * ay, kx, ky)) {
                 ++acc;
                 s.st = (uint8_t)(ST_OOB | extra);
                 return true;
@@ -1204,10 +1208,14 @@ __global__ __launch_bounds__(kBlock) void k_rkf45_2d(AdvectParams P)
     rkf45_refill<CachedLane2<ST, STEADY, MET>>(P);
 }
 
+// Occupancy target: 4 waves per SIMD (at most 128 VGPRs) for the plain modes, where
+// it costs one spill outside the step loop; 3 for the Brownian term and the library
+// cosine, whose extra state would spill inside it.
 template <int ST, bool STEADY, int MET, bool BROWN>
-__global__ __launch_bounds__(512) void k_advect2d_batch(const AdvectParams *runs,
-                                                        const uint32_t *cstart, int nruns,
-                                                        uint32_t total, uint32_t *queues)
+__global__ __launch_bounds__(512)
+__attribute__((amdgpu_waves_per_eu(BROWN || MET == kSphLib ? 3 : 4))) void k_advect2d_batch(
+    const AdvectParams *__restrict__ runs, const uint32_t *__restrict__ cstart, int nruns,
+    uint32_t total, uint32_t *queues)
 {
     __shared__ uint32_t item_s;
     const uint32_t home = blockIdx.x & 7u;
@@ -1639,8 +1647,9 @@ hipError_t launch3(const AdvectParams &p, bool steady, uint32_t n_launch, hipStr
     const dim3 g(blocks), b(kBlock);
     if constexpr (!IS3D) {
         using R = typename Real<ST>::T;
-        const size_t lds = (size_t)kBlock * cache_slot<R>() * sizeof(R);
         return dispatch_cached(p, steady, [&](auto stc, auto met, auto brown) {
+            const size_t lds =
+                decltype(brown)::value ? 0 : (size_t)kBlock * cache_slot<R>() * sizeof(R);
             hipLaunchKernelGGL((k_advect2d<ST, decltype(stc)::value, decltype(met)::value,
                                            decltype(brown)::value>),
                                g, b, lds, s, p);
@@ -1784,7 +1793,7 @@ hipError_t batch3(const AdvectParams *runs, const uint32_t *cstart, int nruns, u
 {
     auto kern = k_advect2d_batch<ST, STEADY, MET, BROWN>;
     using R = typename Real<ST>::T;
-    const size_t lds = (size_t)block * cache_slot<R>() * sizeof(R);
+    const size_t lds = BROWN ? 0 : (size_t)block * cache_slot<R>() * sizeof(R);
     int per_cu = 0, cus = 0, dev = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, lds);
     if (e != hipSuccess)
