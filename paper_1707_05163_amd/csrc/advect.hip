@@ -692,34 +692,54 @@ struct GatherLane {
 // leaves the cell or when the time bracket moves on.  The polynomial is the same
 // bilinear interpolant as the corner-weight form (Sect. 2.3), and f_a + tau (f_b -
 // f_a) is the same linear time interpolation (Sect. 2.4); only rounding differs.
-// The 16 coefficients sit either in the lane's LDS slot (SHARED: fewer registers, so
-// more waves per SIMD) or in registers (when the kernel's other state keeps the
-// occupancy at the same level either way, as with the Brownian term).
-template <class R, bool SHARED>
+// NL of the 16 coefficients (the last NL) sit in the lane's LDS slot and the others
+// in registers: LDS frees registers, so more waves fit on a SIMD, at the cost of LDS
+// reads every stage; the split is chosen per kernel mode (cache_lds_coefs).
+template <class R, int NL>
 struct Cell2 {
     double x0, ux, y0, uy;  // lower faces; exclusive upper faces (for the last cell the
                             // next double above the last node, so the domain's closed
                             // upper end needs no separate test)
     double rx, ry;          // inverse cell widths
     double cl, sl;          // cos and sin of the lower latitude face
-    std::conditional_t<SHARED, R *, R[16]> lc;  // U, V coefficients of the earlier
-                            // snapshot [0..7], later minus earlier [8..15]
+    // U, V coefficients of the earlier snapshot [0..7], later minus earlier [8..15]
+    R *lc;                  // LDS slot: coefficients 16 - NL .. 15
+    R lr[NL < 16 ? 16 - NL : 1];  // registers: coefficients 0 .. 15 - NL
     bool land;
-    bool valid;
+    __device__ R &coef(int i) { return i < 16 - NL ? lr[i] : lc[i - (16 - NL)]; }
+    __device__ R coef(int i) const { return i < 16 - NL ? lr[i] : lc[i - (16 - NL)]; }
+    // no point is in the cell until the next reload (an empty x range also keeps a
+    // NaN position out)
+    __device__ void invalidate()
+    {
+        x0 = __builtin_inf();
+        ux = -__builtin_inf();
+    }
+    __device__ void clear()
+    {
+        y0 = uy = 0.0;
+        invalidate();
+    }
 };
 
-// Per-lane LDS slots of the 2D stencil cache: 16 coefficients plus padding, a stride
-// of 144 B (double) or 80 B (float) that keeps every 16-byte read aligned and puts
-// the 16 lanes of one LDS cycle on distinct banks.
-template <class R>
-constexpr int cache_slot() { return sizeof(R) == 8 ? 18 : 20; }
+// Per-lane LDS slots of the 2D stencil cache: NL coefficients plus 16 bytes, a stride
+// (144, 80 or 48 B) that keeps every 16-byte read aligned and puts the 16 lanes of one
+// LDS cycle on distinct banks.  Elements of R per lane.
+template <class R, int NL>
+constexpr int cache_slot() { return NL ? (NL * (int)sizeof(R) + 16) / (int)sizeof(R) : 0; }
 
-template <class R>
+template <class R, int NL>
 __device__ inline R *cache_slot_ptr()
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char cache_lds[];
-    return reinterpret_cast<R *>(cache_lds) + threadIdx.x * cache_slot<R>();
+    return reinterpret_cast<R *>(cache_lds) + threadIdx.x * cache_slot<R, NL>();
 }
+
+// How many coefficients the cached 2D kernels keep in LDS: with the Brownian term
+// the kernel holds enough other state that the occupancy is the same either way, so
+// all stay in registers; otherwise the later-minus-earlier half goes to LDS.
+template <int ST, bool BROWN>
+constexpr int cache_lds_coefs() { return BROWN ? 0 : 8; }
 
 template <class R>
 __device__ inline void coeffs(const R f00, const R f10, const R f01, const R f11, R c[4])
@@ -736,8 +756,8 @@ __device__ inline R poly(const R c[4], R xi, R eta)
     return fma(eta, fma(xi, c[3], c[2]), fma(xi, c[1], c[0]));
 }
 
-template <int ST, bool STEADY, bool SH>
-__device__ inline bool reload2(const AdvectParams &P, Cell2<typename Real<ST>::T, SH> &c, int sa,
+template <int ST, bool STEADY, int NL>
+__device__ inline bool reload2(const AdvectParams &P, Cell2<typename Real<ST>::T, NL> &c, int sa,
                                int sb, double x, double y)
 {
     using R = typename Real<ST>::T;
@@ -782,8 +802,8 @@ __device__ inline bool reload2(const AdvectParams &P, Cell2<typename Real<ST>::T
             coeffs<R>(p00[v], p10[v], p01[v], p11[v], ca);
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                c.lc[4 * v + q] = ca[q];
-                c.lc[8 + 4 * v + q] = cb[q] - ca[q];
+                c.coef(4 * v + q) = ca[q];
+                c.coef(8 + 4 * v + q) = cb[q] - ca[q];
             }
         }
     } else {
@@ -793,18 +813,42 @@ __device__ inline bool reload2(const AdvectParams &P, Cell2<typename Real<ST>::T
             coeffs<R>(p00[v], p10[v], p01[v], p11[v], ca);
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-                c.lc[4 * v + q] = ca[q];
+                c.coef(4 * v + q) = ca[q];
         }
     }
-    c.valid = true;
     return true;
 }
 
-template <class R, bool SH>
-__device__ inline bool in_cell(const Cell2<R, SH> &c, const AdvectParams &P, double x, double y)
+template <class R, int NL>
+__device__ inline bool in_cell(const Cell2<R, NL> &c, const AdvectParams &P, double x, double y)
 {
-    return c.valid && x >= c.x0 && x < c.ux && y >= c.y0 && y < c.uy;
+    return x >= c.x0 && x < c.ux && y >= c.y0 && y < c.uy;
 }
+
+// Whether two time-table entries interpolate between the same two snapshots.
+__device__ inline bool same_bracket(const TimeEntry &a, const TimeEntry &b)
+{
+    return a.sa == b.sa && a.sb == b.sb;
+}
+
+// The cached kernels' stencils hold the bracket of the stage before; this says, for
+// stage q of step s, whether the bracket moves on there (or nothing is cached yet:
+// the launch's first stage), so that the stage reloads whatever cell its point is
+// in.  Every active lane of a wave runs the same stages, so the answer is
+// wave-uniform and comes from the table alone: RK4's first stage reuses the entry of
+// the previous step's last stage, its third the second's; Euler's only stage follows
+// the previous step's.
+struct BracketMoves {
+    uint32_t bits;  // bit q: stage q reloads
+    __device__ BracketMoves(const AdvectParams &P, int s, const TimeEntry &e0,
+                            const TimeEntry &e1, const TimeEntry &e2)
+    {
+        const bool q0 = s == 0 || (P.scheme && !same_bracket(P.tab[2 * s - 2], e0));
+        bits = (uint32_t)q0 | ((uint32_t)!same_bracket(e0, e1) << 1) |
+               ((uint32_t)!same_bracket(e1, e2) << 3);
+    }
+    __device__ bool at(int q) const { return (bits >> q) & 1u; }
+};
 
 // 1 / d to within an ulp or two: hardware reciprocal refined by two Newton steps
 __device__ inline double recip(double d)
@@ -843,8 +887,8 @@ __device__ inline double cos_series(double cl, double sl, double y0, double y, i
 // spherical with cells too tall for the series (library cos).
 enum : int { kFlat = 0, kSphTable = 1, kSphLib = 2 };
 
-template <int MET, class R, bool SH>
-__device__ inline double cos_lat(const Cell2<R, SH> &c, const AdvectParams &P, double y)
+template <int MET, class R, int NL>
+__device__ inline double cos_lat(const Cell2<R, NL> &c, const AdvectParams &P, double y)
 {
     if constexpr (MET == kSphLib)
         return cos(y * kDegToRad);
@@ -852,17 +896,21 @@ __device__ inline double cos_lat(const Cell2<R, SH> &c, const AdvectParams &P, d
         return cos_series(c.cl, c.sl, c.y0, y, P.g.cos_terms);
 }
 
-template <int ST, bool STEADY, int MET, bool SH>
-__device__ inline bool stage2(const AdvectParams &P, Cell2<typename Real<ST>::T, SH> &c,
-                              const TimeEntry &e, double x, double y, double &kx, double &ky)
+template <int ST, bool STEADY, int MET, int NL>
+__device__ inline bool stage2(const AdvectParams &P, Cell2<typename Real<ST>::T, NL> &c,
+                              const TimeEntry &e, bool fresh, double x, double y, double &kx,
+                              double &ky)
 {
     using R = typename Real<ST>::T;
-    if (!in_cell(c, P, x, y)) {
-        if (!reload2<ST, STEADY, SH>(P, c, e.sa, e.sb, x, y))
+    if (!in_cell(c, P, x, y) | fresh) {
+        if (!reload2<ST, STEADY, NL>(P, c, e.sa, e.sb, x, y))
             return false;
     }
     const R xi = (R)((x - c.x0) * c.rx), eta = (R)((y - c.y0) * c.ry);
-    const R *q = c.lc;
+    R q[16];
+#pragma unroll
+    for (int i = 0; i < (STEADY ? 8 : 16); ++i)
+        q[i] = c.coef(i);
     R u = poly<R>(q + 0, xi, eta), v = poly<R>(q + 4, xi, eta);
     if constexpr (!STEADY) {
         const R tau = (R)e.tau;
@@ -891,15 +939,16 @@ __device__ inline long long advect_lane_2d(const AdvectParams &P, uint32_t k, ui
         uint8_t st = P.status[id];
         if (st == 0) {
             double x = P.x[id], y = P.y[id];
-            Cell2<R, !BROWN> c;
-            c.valid = false;
-            if constexpr (!BROWN)
-                c.lc = cache_slot_ptr<R>();
-            int csa = -1, csb = -1;  // bracket the cached stencils belong to
-            const double dt = P.dt, hd = 0.5 * dt, dt6 = dt * (1.0 / 6.0);
+            constexpr int NL = cache_lds_coefs<ST, BROWN>();
+            Cell2<R, NL> c;
+            c.clear();
+            if constexpr (NL > 0)
+                c.lc = cache_slot_ptr<R, NL>();
+            const double dt = P.dt, dt6 = dt * (1.0 / 6.0);
             for (int s = 0; s < P.nsteps; ++s) {
                 ++steps;
                 const TimeEntry e0 = P.tab[2 * s], e1 = P.tab[2 * s + 1], e2 = P.tab[2 * s + 2];
+                const BracketMoves moves(P, s, e0, e1, e2);
                 uint8_t err = ST_OOB;
                 // the four stages: offsets 0, dt/2, dt/2, dt from X_n along the previous
                 // slope; weights 1, 2, 2, 1
@@ -911,14 +960,12 @@ __device__ inline long long advect_lane_2d(const AdvectParams &P, uint32_t k, ui
                     // previous slope, and the slope's weight in the sum (stage 4's
                     // slope is added after the loop)
                     const TimeEntry e = q == 0 ? e0 : (q == 3 ? e2 : e1);
-                    const double h = q == 0 ? 0.0 : (q == 3 ? dt : hd);
+                    // (stage 1 adds a zero slope, so its offset is immaterial; the
+                    // half step comes in with the launch, as a scalar operand)
+                    const double h = q == 3 ? dt : P.hdt;
                     const double wq = q == 0 ? 1.0 : (q == 3 ? 0.0 : 2.0);
-                    if (e.sa != csa || e.sb != csb || !P.cache) {
-                        c.valid = false;
-                        csa = e.sa;
-                        csb = e.sb;
-                    }
-                    if (!stage2<ST, STEADY, MET, !BROWN>(P, c, e, x + kx * h, y + ky * h, kx, ky))
+                    if (!stage2<ST, STEADY, MET, NL>(P, c, e, moves.at(q), x + kx * h,
+                                                         y + ky * h, kx, ky))
                         goto fail;
                     sx = fma(wq, kx, sx);
                     sy = fma(wq, ky, sy);
@@ -1024,7 +1071,7 @@ struct CachedLane2 {
     using R = typename Real<ST>::T;
     RkfState s;
     double x, y;
-    Cell2<R, true> c;
+    Cell2<R, 16> c;
     int32_t csa, csb;
     LaneTime lt;
 
@@ -1037,8 +1084,8 @@ struct CachedLane2 {
         s.it = 0;
         x = P.x[id];
         y = P.y[id];
-        c.valid = false;
-        c.lc = cache_slot_ptr<R>();
+        c.clear();
+        c.lc = cache_slot_ptr<R, 16>();
         csa = csb = -1;
         lt.lo = -1;
     }
@@ -1067,12 +1114,13 @@ struct CachedLane2 {
             const double ay = (((a[0] * k0y + a[1] * k1y) + a[2] * k2y) + a[3] * k3y) + a[4] * k4y;
             const TimeEntry ent = bracket_lane(P, s.t + kRkfC[q] * hs, lt);
             if (ent.sa != csa || ent.sb != csb) {
-                c.valid = false;
+                c.invalidate();
                 csa = ent.sa;
                 csb = ent.sb;
             }
             double kx, ky;
-            if (!stage2<ST, STEADY, MET, true>(P, c, ent, x + hs * ax, y + hs * ay, kx, ky)) {
+            if (!stage2<ST, STEADY, MET, 16>(P, c, ent, false, x + hs * ax, y + hs * ay, kx,
+                                               ky)) {
                 ++acc;
                 s.st = (uint8_t)(ST_OOB | extra);
                 return true;
@@ -1274,7 +1322,17 @@ struct Cell3 {
     R a[3][8];
     R d[3][8];
     bool land;
-    bool valid;
+    // as for the 2D cell: an empty x range until the next reload
+    __device__ void invalidate()
+    {
+        x0 = __builtin_inf();
+        ux = -__builtin_inf();
+    }
+    __device__ void clear()
+    {
+        y0 = uy = z0 = uz = 0.0;
+        invalidate();
+    }
 };
 
 template <class R>
@@ -1366,7 +1424,6 @@ __device__ inline bool reload3(const AdvectParams &P, Cell3<typename Real<ST>::T
                 c.d[v][q] = cb[q] - c.a[v][q];
         }
     }
-    c.valid = true;
     return true;
 }
 
@@ -1374,15 +1431,16 @@ template <class R>
 __device__ inline bool in_cell3(const Cell3<R> &c, const AdvectParams &P, double x, double y,
                                 double z)
 {
-    return c.valid && x >= c.x0 && x < c.ux && y >= c.y0 && y < c.uy && z >= c.z0 && z < c.uz;
+    return x >= c.x0 && x < c.ux && y >= c.y0 && y < c.uy && z >= c.z0 && z < c.uz;
 }
 
 template <int ST, bool STEADY, int MET>
 __device__ inline bool stage3(const AdvectParams &P, Cell3<typename Real<ST>::T> &c,
-                              const TimeEntry &e, double x, double y, double z, double k[3])
+                              const TimeEntry &e, bool fresh, double x, double y, double z,
+                              double k[3])
 {
     using R = typename Real<ST>::T;
-    if (!in_cell3(c, P, x, y, z)) {
+    if (!in_cell3(c, P, x, y, z) | fresh) {
         if (!reload3<ST, STEADY>(P, c, e.sa, e.sb, x, y, z))
             return false;
     }
@@ -1425,25 +1483,22 @@ __global__ __launch_bounds__(kBlock) void k_advect3d(AdvectParams P)
         if (st == 0) {
             double x = P.x[id], y = P.y[id], z = P.z[id];
             Cell3<R> c;
-            c.valid = false;
-            int csa = -1, csb = -1;
-            const double dt = P.dt, hd = 0.5 * dt, dt6 = dt * (1.0 / 6.0);
+            c.clear();
+            const double dt = P.dt, dt6 = dt * (1.0 / 6.0);
             for (int s = 0; s < P.nsteps; ++s) {
                 ++steps;
                 const TimeEntry e0 = P.tab[2 * s], e1 = P.tab[2 * s + 1], e2 = P.tab[2 * s + 2];
+                const BracketMoves moves(P, s, e0, e1, e2);
                 uint8_t err = ST_OOB;
                 double k[3] = {0.0, 0.0, 0.0}, sm[3] = {0.0, 0.0, 0.0};
                 const int nst = P.scheme ? 1 : 4;
 #pragma nounroll
                 for (int q = 0; q < nst; ++q) {
                     const TimeEntry e = q == 0 ? e0 : (q == 3 ? e2 : e1);
-                    const double h = q == 0 ? 0.0 : (q == 3 ? dt : hd);
-                    if (e.sa != csa || e.sb != csb) {
-                        c.valid = false;
-                        csa = e.sa;
-                        csb = e.sb;
-                    }
-                    if (!stage3<ST, STEADY, MET>(P, c, e, x + k[0] * h, y + k[1] * h,
+                    // (stage 1 adds a zero slope, so its offset is immaterial; the
+                    // half step comes in with the launch, as a scalar operand)
+                    const double h = q == 3 ? dt : P.hdt;
+                    if (!stage3<ST, STEADY, MET>(P, c, e, moves.at(q), x + k[0] * h, y + k[1] * h,
                                                  z + k[2] * h, k))
                         goto fail;
                     const double wq = q == 0 ? 1.0 : (q == 3 ? 0.0 : 2.0);
@@ -1649,7 +1704,8 @@ hipError_t launch3(const AdvectParams &p, bool steady, uint32_t n_launch, hipStr
         using R = typename Real<ST>::T;
         return dispatch_cached(p, steady, [&](auto stc, auto met, auto brown) {
             const size_t lds =
-                decltype(brown)::value ? 0 : (size_t)kBlock * cache_slot<R>() * sizeof(R);
+                (size_t)kBlock *
+                cache_slot<R, cache_lds_coefs<ST, decltype(brown)::value>()>() * sizeof(R);
             hipLaunchKernelGGL((k_advect2d<ST, decltype(stc)::value, decltype(met)::value,
                                            decltype(brown)::value>),
                                g, b, lds, s, p);
@@ -1714,7 +1770,7 @@ hipError_t rkf3(const AdvectParams &p, bool steady, uint32_t n_launch, hipStream
     if constexpr (!IS3D) {
         if (p.cache && !p.nearest) {
             using R = typename Real<ST>::T;
-            const size_t lds = (size_t)kBlock * cache_slot<R>() * sizeof(R);
+            const size_t lds = (size_t)kBlock * cache_slot<R, 16>() * sizeof(R);
             hipError_t e = hipSuccess;
             (void)dispatch_cached(p, steady, [&](auto stc, auto met, auto) {
                 e = launch_persistent(k_rkf45_2d<ST, decltype(stc)::value, decltype(met)::value>,
@@ -1793,7 +1849,8 @@ hipError_t batch3(const AdvectParams *runs, const uint32_t *cstart, int nruns, u
 {
     auto kern = k_advect2d_batch<ST, STEADY, MET, BROWN>;
     using R = typename Real<ST>::T;
-    const size_t lds = BROWN ? 0 : (size_t)block * cache_slot<R>() * sizeof(R);
+    const size_t lds =
+        (size_t)block * cache_slot<R, cache_lds_coefs<ST, BROWN>()>() * sizeof(R);
     int per_cu = 0, cus = 0, dev = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, lds);
     if (e != hipSuccess)
