@@ -1313,15 +1313,18 @@ __attribute__((amdgpu_waves_per_eu(BROWN || MET == kSphLib ? 3 : 4))) void k_adv
 // ---------------------------------------------------------------- 3D with a stencil cache
 // Same scheme in three dimensions: the trilinear interpolant of U, V, W in the
 // cached cell written as c0 + c1 xi + c2 eta + c3 zeta + c4 xi eta + c5 xi zeta +
-// c6 eta zeta + c7 xi eta zeta, for the earlier snapshot and the difference.
-template <class R>
+// c6 eta zeta + c7 xi eta zeta, for the earlier snapshot and the difference.  With
+// DL the 24 difference coefficients sit in the lane's LDS slot instead of registers.
+template <class R, bool DL>
 struct Cell3 {
     double x0, ux, y0, uy, z0, uz;
     double rx, ry, rz;
     double cl, sl;
     R a[3][8];
-    R d[3][8];
+    R dr[DL ? 1 : 3][8];    // registers (not DL)
+    R *dl;                  // LDS slot (DL): variable v at [8 v .. 8 v + 7]
     bool land;
+    __device__ R &d(int v, int q) { return DL ? dl[8 * v + q] : dr[DL ? 0 : v][q]; }
     // as for the 2D cell: an empty x range until the next reload
     __device__ void invalidate()
     {
@@ -1357,8 +1360,48 @@ __device__ inline R poly3(const R c[8], R xi, R eta, R zeta)
     return fma(xi, tx, r);
 }
 
-template <int ST, bool STEADY>
-__device__ inline bool reload3(const AdvectParams &P, Cell3<typename Real<ST>::T> &c, int sa,
+// LDS slot of the 3D cache: 24 coefficients plus 16 bytes (208 B for double, 112 B
+// for float), conflict-free for 16-byte reads as in 2D.  Elements of R per lane.
+template <class R>
+constexpr int cache3_slot() { return (24 * (int)sizeof(R) + 16) / (int)sizeof(R); }
+
+template <class R>
+__device__ inline R *cache3_slot_ptr()
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char cache_lds[];
+    return reinterpret_cast<R *>(cache_lds) + threadIdx.x * cache3_slot<R>();
+}
+
+// Whether the 3D kernel keeps the difference coefficients in LDS: only for FP64
+// coefficients (FP32 and FP64 fields), where the 48 VGPRs they free, with a 3-wave
+// target, lift the kernel from 2 to 3 waves per SIMD (LDS then allows exactly 3); not
+// with the Brownian term or the library cosine, whose extra state would spill inside
+// the stage loop, and not in the steady case (no differences).
+template <int ST, bool STEADY, int MET, bool BROWN>
+constexpr bool cache3_lds()
+{
+    return !BROWN && !STEADY && MET != kSphLib && sizeof(typename Real<ST>::T) == 8;
+}
+
+// The raw storage word of one 3D node and the value of variable v in it.
+template <int ST> struct NodeWord3 { using T = uint2; };     // BF16, FP16
+template <> struct NodeWord3<kF64> { using T = double4; };
+template <> struct NodeWord3<kF32> { using T = float4; };
+
+template <int ST>
+__device__ inline typename Real<ST>::T node_var(const typename NodeWord3<ST>::T &q, int v,
+                                                const float *sc)
+{
+    if constexpr (ST == kF64 || ST == kF32)
+        return v == 0 ? q.x : (v == 1 ? q.y : q.z);
+    else if constexpr (ST == kBF16)
+        return v == 0 ? bf16_lo(q.x) : (v == 1 ? bf16_hi(q.x) : bf16_lo(q.y));
+    else
+        return (v == 0 ? f16_lo(q.x) : (v == 1 ? f16_hi(q.x) : f16_lo(q.y))) * sc[v];
+}
+
+template <int ST, bool STEADY, bool DL>
+__device__ inline bool reload3(const AdvectParams &P, Cell3<typename Real<ST>::T, DL> &c, int sa,
                                int sb, double x, double y, double z)
 {
     using R = typename Real<ST>::T;
@@ -1385,63 +1428,61 @@ __device__ inline bool reload3(const AdvectParams &P, Cell3<typename Real<ST>::T
     const size_t n000 = (size_t)k * plane + (size_t)j * nx + (size_t)i;
     const size_t off[8] = {0, 1, nx, nx + 1, plane, plane + 1, plane + nx, plane + nx + 1};
     const char *base = static_cast<const char *>(P.f.slots);
+    using W = typename NodeWord3<ST>::T;
+    // the eight nodes' raw words first, converted one variable at a time (fewer live
+    // registers than converting every node up front)
+    W w[8];
     {
-        const char *A = base + (size_t)sa * P.f.slot_bytes;
-        R fa[3][8];
+        const W *A = reinterpret_cast<const W *>(base + (size_t)sa * P.f.slot_bytes);
+        const float *sc = ST == kF16S ? P.f.scales + ((size_t)sa * P.f.nzl + k) * 3 : nullptr;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const float *sc = ST == kF16S ? P.f.scales + ((size_t)sa * P.f.nzl + k + (q >> 2)) * 3
-                                          : nullptr;
-            R v[3];
-            load_node<ST, true>(A, n000 + off[q], sc, v);
-            fa[0][q] = v[0];
-            fa[1][q] = v[1];
-            fa[2][q] = v[2];
-        }
-#pragma unroll
-        for (int v = 0; v < 3; ++v)
-            coeffs3<R>(fa[v], c.a[v]);
-    }
-    if constexpr (!STEADY) {
-        const char *B = base + (size_t)sb * P.f.slot_bytes;
-        R fb[3][8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const float *sc = ST == kF16S ? P.f.scales + ((size_t)sb * P.f.nzl + k + (q >> 2)) * 3
-                                          : nullptr;
-            R v[3];
-            load_node<ST, true>(B, n000 + off[q], sc, v);
-            fb[0][q] = v[0];
-            fb[1][q] = v[1];
-            fb[2][q] = v[2];
-        }
+        for (int q = 0; q < 8; ++q)
+            w[q] = A[n000 + off[q]];
 #pragma unroll
         for (int v = 0; v < 3; ++v) {
-            R cb[8];
-            coeffs3<R>(fb[v], cb);
+            R f[8];
 #pragma unroll
             for (int q = 0; q < 8; ++q)
-                c.d[v][q] = cb[q] - c.a[v][q];
+                f[q] = node_var<ST>(w[q], v, sc + (q >> 2) * 3);
+            coeffs3<R>(f, c.a[v]);
+        }
+    }
+    if constexpr (!STEADY) {
+        const W *B = reinterpret_cast<const W *>(base + (size_t)sb * P.f.slot_bytes);
+        const float *sc = ST == kF16S ? P.f.scales + ((size_t)sb * P.f.nzl + k) * 3 : nullptr;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            w[q] = B[n000 + off[q]];
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+            R f[8], cb[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                f[q] = node_var<ST>(w[q], v, sc + (q >> 2) * 3);
+            coeffs3<R>(f, cb);
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                c.d(v, q) = cb[q] - c.a[v][q];
         }
     }
     return true;
 }
 
-template <class R>
-__device__ inline bool in_cell3(const Cell3<R> &c, const AdvectParams &P, double x, double y,
+template <class R, bool DL>
+__device__ inline bool in_cell3(const Cell3<R, DL> &c, const AdvectParams &P, double x, double y,
                                 double z)
 {
     return x >= c.x0 && x < c.ux && y >= c.y0 && y < c.uy && z >= c.z0 && z < c.uz;
 }
 
-template <int ST, bool STEADY, int MET>
-__device__ inline bool stage3(const AdvectParams &P, Cell3<typename Real<ST>::T> &c,
+template <int ST, bool STEADY, int MET, bool DL>
+__device__ inline bool stage3(const AdvectParams &P, Cell3<typename Real<ST>::T, DL> &c,
                               const TimeEntry &e, bool fresh, double x, double y, double z,
                               double k[3])
 {
     using R = typename Real<ST>::T;
     if (!in_cell3(c, P, x, y, z) | fresh) {
-        if (!reload3<ST, STEADY>(P, c, e.sa, e.sb, x, y, z))
+        if (!reload3<ST, STEADY, DL>(P, c, e.sa, e.sb, x, y, z))
             return false;
     }
     const R xi = (R)((x - c.x0) * c.rx), eta = (R)((y - c.y0) * c.ry);
@@ -1450,8 +1491,13 @@ __device__ inline bool stage3(const AdvectParams &P, Cell3<typename Real<ST>::T>
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
         v[q] = poly3<R>(c.a[q], xi, eta, zeta);
-        if constexpr (!STEADY)
-            v[q] = fma((R)e.tau, poly3<R>(c.d[q], xi, eta, zeta), v[q]);
+        if constexpr (!STEADY) {
+            R dq[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                dq[i] = c.d(q, i);
+            v[q] = fma((R)e.tau, poly3<R>(dq, xi, eta, zeta), v[q]);
+        }
     }
     if constexpr (MET != kFlat) {
         double cosl;
@@ -1470,7 +1516,9 @@ __device__ inline bool stage3(const AdvectParams &P, Cell3<typename Real<ST>::T>
 }
 
 template <int ST, bool STEADY, int MET, bool BROWN>
-__global__ __launch_bounds__(kBlock) void k_advect3d(AdvectParams P)
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(cache3_lds<ST, STEADY, MET, BROWN>() ? 3 : 1))) void k_advect3d(
+    AdvectParams P)
 {
     using R = typename Real<ST>::T;
     const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
@@ -1482,8 +1530,11 @@ __global__ __launch_bounds__(kBlock) void k_advect3d(AdvectParams P)
         uint8_t st = P.status[id];
         if (st == 0) {
             double x = P.x[id], y = P.y[id], z = P.z[id];
-            Cell3<R> c;
+            constexpr bool DL = cache3_lds<ST, STEADY, MET, BROWN>();
+            Cell3<R, DL> c;
             c.clear();
+            if constexpr (DL)
+                c.dl = cache3_slot_ptr<R>();
             const double dt = P.dt, dt6 = dt * (1.0 / 6.0);
             for (int s = 0; s < P.nsteps; ++s) {
                 ++steps;
@@ -1498,7 +1549,7 @@ __global__ __launch_bounds__(kBlock) void k_advect3d(AdvectParams P)
                     // (stage 1 adds a zero slope, so its offset is immaterial; the
                     // half step comes in with the launch, as a scalar operand)
                     const double h = q == 3 ? dt : P.hdt;
-                    if (!stage3<ST, STEADY, MET>(P, c, e, moves.at(q), x + k[0] * h, y + k[1] * h,
+                    if (!stage3<ST, STEADY, MET, DL>(P, c, e, moves.at(q), x + k[0] * h, y + k[1] * h,
                                                  z + k[2] * h, k))
                         goto fail;
                     const double wq = q == 0 ? 1.0 : (q == 3 ? 0.0 : 2.0);
@@ -1711,10 +1762,14 @@ hipError_t launch3(const AdvectParams &p, bool steady, uint32_t n_launch, hipStr
                                g, b, lds, s, p);
         });
     } else {
+        using R = typename Real<ST>::T;
         return dispatch_cached(p, steady, [&](auto stc, auto met, auto brown) {
+            constexpr bool dl = cache3_lds<ST, decltype(stc)::value, decltype(met)::value,
+                                           decltype(brown)::value>();
+            const size_t lds = dl ? (size_t)kBlock * cache3_slot<R>() * sizeof(R) : 0;
             hipLaunchKernelGGL((k_advect3d<ST, decltype(stc)::value, decltype(met)::value,
                                            decltype(brown)::value>),
-                               g, b, 0, s, p);
+                               g, b, lds, s, p);
         });
     }
 }
