@@ -944,7 +944,7 @@ __device__ inline long long advect_lane_2d(const AdvectParams &P, uint32_t k, ui
             c.clear();
             if constexpr (NL > 0)
                 c.lc = cache_slot_ptr<R, NL>();
-            const double dt = P.dt, dt6 = dt * (1.0 / 6.0);
+            const double dt = P.dt, dt6 = P.dt6;
             for (int s = 0; s < P.nsteps; ++s) {
                 ++steps;
                 const TimeEntry e0 = P.tab[2 * s], e1 = P.tab[2 * s + 1], e2 = P.tab[2 * s + 2];
@@ -1028,7 +1028,9 @@ __device__ inline long long advect_lane_2d(const AdvectParams &P, uint32_t k, ui
 }
 
 template <int ST, bool STEADY, int MET, bool BROWN>
-__global__ __launch_bounds__(kBlock) void k_advect2d(AdvectParams P)
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(!BROWN && MET != kSphLib ? 5 : 1))) void k_advect2d(
+    AdvectParams P)
 {
     const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
     const uint32_t k = blk * kBlock + threadIdx.x;
@@ -1535,7 +1537,7 @@ __attribute__((amdgpu_waves_per_eu(cache3_lds<ST, STEADY, MET, BROWN>() ? 3 : 1)
             c.clear();
             if constexpr (DL)
                 c.dl = cache3_slot_ptr<R>();
-            const double dt = P.dt, dt6 = dt * (1.0 / 6.0);
+            const double dt = P.dt, dt6 = P.dt6;
             for (int s = 0; s < P.nsteps; ++s) {
                 ++steps;
                 const TimeEntry e0 = P.tab[2 * s], e1 = P.tab[2 * s + 1], e2 = P.tab[2 * s + 2];

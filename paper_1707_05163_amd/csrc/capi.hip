@@ -953,6 +953,7 @@ int exec_prepare(lp_pset *ps, double runtime, double dt, double outputdt, const 
     P.f.steady = (fs->npushed == 1) ? 1 : 0;
     P.dt = dt;
     P.hdt = 0.5 * dt;
+    P.dt6 = dt * (1.0 / 6.0);
     P.policy = o->recovery == LP_DELETE ? 0 : 1;
     P.cache = o->stencil_cache ? 1 : 0;
     P.scheme = o->kernel == LP_KERNEL_EULER ? 1 : (rkf ? 2 : 0);

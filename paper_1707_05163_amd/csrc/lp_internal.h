@@ -64,6 +64,7 @@ struct AdvectParams {
     const TimeEntry *tab;    // 2*nsteps+1 entries: t_n, t_n+dt/2, t_n+dt, ...
     double dt;
     double hdt;              // dt / 2
+    double dt6;              // dt * (1 / 6), RK4's weight unit
     int64_t step0;           // step index (from t0) of the first step of the launch
     int32_t nsteps;
     int32_t policy;          // 0 delete, 1 freeze
