@@ -87,6 +87,8 @@ def parse():
     p.add_argument("--rkf-tol", type=float, default=1e-3, help="RKF45 tolerance, m per step")
     p.add_argument("--rkf-min-exp", type=int, default=-6)
     p.add_argument("--rkf-max-exp", type=int, default=5)
+    p.add_argument("--kh", type=float, default=0.0,
+                   help="cfg1: Brownian diffusivity in m^2/s (0: plain RK4, the benchmark)")
     p.add_argument("--calibrate-copy", type=float, default=0.0,
                    help="first copy this many GB device-to-device (a plain copy kernel of "
                         "known size, to scale hardware byte counters)")
@@ -580,7 +582,7 @@ def main():
         ps.execute(runtime, w.dt, w.outputdt, output_stride=a.output_stride,
                    sort_every=a.sort_every, profile=profile,
                    stencil_cache=bool(a.stencil_cache), kernel=a.kernel, tol=a.rkf_tol,
-                   min_exp=a.rkf_min_exp, max_exp=a.rkf_max_exp, stream=stream)
+                   min_exp=a.rkf_min_exp, max_exp=a.rkf_max_exp, Kh=a.kh, stream=stream)
 
     for i in range(a.warmup):
         step(psets[i], False)
@@ -610,7 +612,8 @@ def main():
     S = w.outputdt / w.dt
     bytes_per_step = STENCIL_BYTES_2D_F32 * (0.5 if a.dtype != "f32" else 1.0) + STATE_BYTES_2D / S
     default = (a.particles == 1_000_000 and a.days == 30 and a.dtype == "f32"
-               and a.stencil_cache == 1 and a.sort_every == 1 and a.output_stride == 1)
+               and a.stencil_cache == 1 and a.sort_every == 1 and a.output_stride == 1
+               and a.kh == 0.0)
     roof, other = roofline(steps_per_launch, avg_launch_s, bytes_per_step, FLOPS_2D_STEP,
                            measured_traffic("cfg1", default))
     out = {
@@ -629,7 +632,7 @@ def main():
         "config": {"workload": w.name, "grid": f"{w.grid.nx}x{w.grid.ny}", "snapshots": w.fields.nt,
                    "particles": w.n, "rk4_steps": w.nsteps, "dt_s": w.dt,
                    "field_dtype": a.dtype, "output_stride": a.output_stride,
-                   "sort_every": a.sort_every},
+                   "sort_every": a.sort_every, "Kh": a.kh},
         "roofline": roof,
         "roofline_other": other,
         "kernel": {"name": "k_advect2d" if a.stencil_cache else "k_advect", "launches": launches,

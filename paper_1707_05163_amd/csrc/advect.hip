@@ -227,8 +227,10 @@ __device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1)
             k0 += W0;
             k1 += W1;
         }
-        const uint32_t lo0 = M0 * c[0], hi0 = __umulhi(M0, c[0]);
-        const uint32_t lo1 = M1 * c[2], hi1 = __umulhi(M1, c[2]);
+        // one 32 x 32 -> 64-bit product each (a single v_mad_u64_u32)
+        const uint64_t p0 = (uint64_t)M0 * c[0], p1 = (uint64_t)M1 * c[2];
+        const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+        const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
         const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
         c[0] = n0;
         c[1] = lo1;
@@ -243,7 +245,134 @@ __device__ inline double unit53(uint32_t a, uint32_t b)
     return (double)m * 0x1p-53 + 0x1p-54;
 }
 
-template <int ST, bool IS3D, bool STEADY>
+// 1 / d to within an ulp or two: hardware reciprocal refined by two Newton steps
+__device__ inline double recip(double d)
+{
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(fma(-d, r, 1.0), r, r);
+    r = fma(fma(-d, r, 1.0), r, r);
+    return r;
+}
+
+// sin and cos of 2 pi u for u in [0, 1].  The argument is a fraction of a turn, so the
+// reduction to a quarter turn is exact: 4u = q + f with q = rint(4u) and |f| <= 1/2,
+// 2 pi u = q pi/2 + f pi/2.  sin(f pi/2) and cos(f pi/2) come from their Taylor series
+// in f (coefficients (pi/2)^n / n!), cut after the f^17 and f^16 terms (the first
+// terms left out are below 1e-19 and 3e-18 at |f| = 1/2), and the quadrant q mod 4
+// rotates the pair.
+__device__ inline void sincos_turn(double u, double &sn, double &cs)
+{
+    const double t = 4.0 * u;
+    const double q = rint(t);
+    const double f = t - q;  // exact
+    const double f2 = f * f;
+    double ps = 0x1.aaec32af93359p-38;
+    ps = fma(ps, f2, -0x1.6fadb9f155744p-31);
+    ps = fma(ps, f2, 0x1.e8f434d018d63p-25);
+    ps = fma(ps, f2, -0x1.e3074fde8871fp-19);
+    ps = fma(ps, f2, 0x1.50783487ee782p-13);
+    ps = fma(ps, f2, -0x1.32d2cce62bd86p-8);
+    ps = fma(ps, f2, 0x1.466bc6775aae2p-4);
+    ps = fma(ps, f2, -0x1.4abbce625be53p-1);
+    ps = fma(ps, f2, 0x1.921fb54442d18p+0);
+    const double S = ps * f;
+    double pc = 0x1.20c62c2f2d7f5p-34;
+    pc = fma(pc, f2, -0x1.b6e24f44b128fp-28);
+    pc = fma(pc, f2, 0x1.f9d38a3763cc3p-22);
+    pc = fma(pc, f2, -0x1.a6d1f2a204a8cp-16);
+    pc = fma(pc, f2, 0x1.e1f506891babbp-11);
+    pc = fma(pc, f2, -0x1.55d3c7e3cbffap-6);
+    pc = fma(pc, f2, 0x1.03c1f081b5ac4p-2);
+    pc = fma(pc, f2, -0x1.3bd3cc9be45dep+0);
+    const double C = fma(pc, f2, 1.0);
+    const int qi = (int)q;
+    double a = (qi & 1) ? C : S, b = (qi & 1) ? S : C;
+    sn = (qi & 2) ? -a : a;
+    cs = ((qi + 1) & 2) ? -b : b;
+}
+
+// Natural logarithm of u in (0, 1] (the uniforms of unit53).  u = m 2^e with m in
+// [sqrt(1/2), sqrt(2)); log m = 2 atanh(s) with s = (m - 1) / (m + 1), |s| < 0.1716,
+// from the series atanh(s) = s + s^3/3 + s^5/5 + ..., cut after s^19 (the first term
+// left out is below 2.4e-17 relative); e log 2 with log 2 split into a head whose
+// products with |e| < 2^11 are exact and a tail.  Within about two ulps.
+__device__ inline double log_unit(double u)
+{
+    int e;
+    double m = frexp(u, &e);  // m in [1/2, 1)
+    if (m < 0.70710678118654752) {
+        m = 2.0 * m;
+        e -= 1;
+    }
+    const double num = m - 1.0, den = m + 1.0;  // num exact
+    double r = __builtin_amdgcn_rcp(den);
+    r = fma(fma(-den, r, 1.0), r, r);
+    r = fma(fma(-den, r, 1.0), r, r);
+    double sq = num * r;
+    sq = fma(fma(-den, sq, num), r, sq);  // s to within an ulp
+    const double z = sq * sq;
+    double p = 1.0 / 19.0;
+    p = fma(p, z, 1.0 / 17.0);
+    p = fma(p, z, 1.0 / 15.0);
+    p = fma(p, z, 1.0 / 13.0);
+    p = fma(p, z, 1.0 / 11.0);
+    p = fma(p, z, 1.0 / 9.0);
+    p = fma(p, z, 1.0 / 7.0);
+    p = fma(p, z, 1.0 / 5.0);
+    p = fma(p, z, 1.0 / 3.0);
+    const double s2 = 2.0 * sq;
+    const double lm = fma(s2 * z, p, s2);  // log m
+    const double de = (double)e;
+    return fma(de, 0x1.62e42fefa3800p-1, fma(de, 0x1.ef35793c76730p-45, lm));
+}
+
+// Square root of x in [2^-60, 2^60]: the hardware reciprocal square root refined by two
+// Newton steps for 1/sqrt(x), then y = x r with one correction (x - y^2) r / 2.  Within
+// about an ulp.
+__device__ inline double sqrt_mid(double x)
+{
+    double r = __builtin_amdgcn_rsq(x);
+    const double hx = 0.5 * x;
+    r = r * fma(-hx * r, r, 1.5);
+    r = r * fma(-hx * r, r, 1.5);
+    const double y = x * r;
+    return fma(fma(-y, y, x), 0.5 * r, y);
+}
+
+// cos of a latitude in degrees, |lat| <= 90: a quarter turn at most, through the turn
+// form (lat / 360 of a turn; the division rounds once, as lat * pi / 180 does).
+__device__ inline double cos_deg(double lat)
+{
+    double sn, cs;
+    sincos_turn(lat * (1.0 / 360.0), sn, cs);
+    return cs;
+}
+
+// Two standard normals from two uniforms (Box-Muller).
+__device__ inline void box_muller(double u1, double u2, double &n1, double &n2)
+{
+    const double r = sqrt_mid(-2.0 * log_unit(u1));
+    double sn, cs;
+    sincos_turn(u2, sn, cs);
+    n1 = r * cs;
+    n2 = r * sn;
+}
+
+// The random term of Eq. (1) for one step, in metres: sqrt(2 Kh |dt|) times the two
+// normals drawn from the particle's Philox words for (id, step).
+__device__ inline void brownian_metres(const AdvectParams &P, uint32_t id, int64_t step,
+                                       double dt, double &dx, double &dy)
+{
+    uint32_t w[4] = {id, (uint32_t)step, 0u, 0u};
+    philox4x32_10(w, P.run_id, P.seed);
+    double n1, n2;
+    box_muller(unit53(w[0], w[1]), unit53(w[2], w[3]), n1, n2);
+    const double sig = sqrt(2.0 * P.Kh * dt);
+    dx = sig * n1;
+    dy = sig * n2;
+}
+
+template <int ST, bool IS3D, bool STEADY, bool BROWN>
 __device__ inline uint8_t rk4_step(const AdvectParams &P, int s, uint32_t id, double &x,
                                    double &y, double &z, bool horizontal = false)
 {
@@ -277,17 +406,11 @@ __device__ inline uint8_t rk4_step(const AdvectParams &P, int s, uint32_t id, do
         if (horizontal)  // a dwelling particle keeps its depth
             zs = z;
     }
-    if (P.Kh > 0.0) {
-        uint32_t c[4] = {id, (uint32_t)(P.step0 + s), 0u, 0u};
-        philox4x32_10(c, P.run_id, P.seed);
-        const double u1 = unit53(c[0], c[1]), u2 = unit53(c[2], c[3]);
-        const double r = sqrt(-2.0 * log(u1));
-        double sn, cs;
-        sincos((2.0 * 3.141592653589793) * u2, &sn, &cs);
-        const double sig = sqrt(2.0 * P.Kh * dt);
-        double dx = sig * (r * cs), dy = sig * (r * sn);
+    if (BROWN && P.Kh > 0.0) {
+        double dx, dy;
+        brownian_metres(P, id, P.step0 + s, dt, dx, dy);
         if (P.g.spherical) {
-            dx = dx / (kMetresPerDegree * cos(ys * kDegToRad));
+            dx = dx * recip(kMetresPerDegree * cos_deg(ys));
             dy = dy / kMetresPerDegree;
         }
         xs = xs + dx;
@@ -374,7 +497,9 @@ __device__ inline uint8_t behave_pre(const AdvectParams &P, int s, double x, dou
     return 0;
 }
 
-template <int ST, bool IS3D, bool STEADY>
+// The Brownian term is a compile-time mode here as in the cached kernels: its
+// constants would otherwise stay in registers across the step loop of every launch.
+template <int ST, bool IS3D, bool STEADY, bool BROWN>
 __global__ __launch_bounds__(kBlock) void k_advect(AdvectParams P)
 {
     const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
@@ -402,7 +527,8 @@ __global__ __launch_bounds__(kBlock) void k_advect(AdvectParams P)
                         break;
                     }
                 }
-                const uint8_t e = rk4_step<ST, IS3D, STEADY>(P, s, id, x, y, z, horizontal);
+                const uint8_t e =
+                    rk4_step<ST, IS3D, STEADY, BROWN>(P, s, id, x, y, z, horizontal);
                 if (e) {
                     st = (uint8_t)(e | (P.policy == 0 ? ST_DELETED : 0));
                     break;
@@ -850,14 +976,6 @@ struct BracketMoves {
     __device__ bool at(int q) const { return (bits >> q) & 1u; }
 };
 
-// 1 / d to within an ulp or two: hardware reciprocal refined by two Newton steps
-__device__ inline double recip(double d)
-{
-    double r = __builtin_amdgcn_rcp(d);
-    r = fma(fma(-d, r, 1.0), r, r);
-    r = fma(fma(-d, r, 1.0), r, r);
-    return r;
-}
 
 // cos of a latitude inside the cached cell: cos(l0 + dl) = cos l0 cos dl - sin l0 sin dl
 // with dl = lat - l0 and cos dl, sin dl by their Taylor series, cut after 2, 3 or 4
@@ -894,6 +1012,17 @@ __device__ inline double cos_lat(const Cell2<R, NL> &c, const AdvectParams &P, d
         return cos(y * kDegToRad);
     else
         return cos_series(c.cl, c.sl, c.y0, y, P.g.cos_terms);
+}
+
+// 1 / (M cos(lat)) at the end point of a step, for the metric of the Brownian term: the
+// cached cell's series when the latitude is inside the cell's band (where the series
+// holds), else the turn form of the cosine.
+template <int MET, class CellT>
+__device__ inline double inv_metres_lon(const CellT &c, const AdvectParams &P, double y)
+{
+    if (MET == kSphTable && y >= c.y0 && y < c.uy)
+        return recip(kMetresPerDegree * cos_series(c.cl, c.sl, c.y0, y, P.g.cos_terms));
+    return recip(kMetresPerDegree * cos_deg(y));
 }
 
 template <int ST, bool STEADY, int MET, int NL>
@@ -980,16 +1109,10 @@ __device__ inline long long advect_lane_2d(const AdvectParams &P, uint32_t k, ui
                         ys = y + (sy + ky) * dt6;
                     }
                     if (BROWN && P.Kh > 0.0) {
-                        uint32_t w[4] = {id, (uint32_t)(P.step0 + s), 0u, 0u};
-                        philox4x32_10(w, P.run_id, P.seed);
-                        const double u1 = unit53(w[0], w[1]), u2 = unit53(w[2], w[3]);
-                        const double r = sqrt(-2.0 * log(u1));
-                        double sn, cs;
-                        sincos((2.0 * 3.141592653589793) * u2, &sn, &cs);
-                        const double sig = sqrt(2.0 * P.Kh * dt);
-                        double dx = sig * (r * cs), dy = sig * (r * sn);
+                        double dx, dy;
+                        brownian_metres(P, id, P.step0 + s, dt, dx, dy);
                         if constexpr (MET != kFlat) {
-                            dx = dx / (kMetresPerDegree * cos(ys * kDegToRad));
+                            dx = dx * inv_metres_lon<MET>(c, P, ys);
                             dy = dy / kMetresPerDegree;
                         }
                         xs = xs + dx;
@@ -1029,7 +1152,7 @@ __device__ inline long long advect_lane_2d(const AdvectParams &P, uint32_t k, ui
 
 template <int ST, bool STEADY, int MET, bool BROWN>
 __global__ __launch_bounds__(kBlock)
-__attribute__((amdgpu_waves_per_eu(!BROWN && MET != kSphLib ? 5 : 1))) void k_advect2d(
+__attribute__((amdgpu_waves_per_eu(BROWN ? 3 : (MET != kSphLib ? 5 : 1)))) void k_advect2d(
     AdvectParams P)
 {
     const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
@@ -1519,7 +1642,7 @@ __device__ inline bool stage3(const AdvectParams &P, Cell3<typename Real<ST>::T,
 
 template <int ST, bool STEADY, int MET, bool BROWN>
 __global__ __launch_bounds__(kBlock)
-__attribute__((amdgpu_waves_per_eu(cache3_lds<ST, STEADY, MET, BROWN>() ? 3 : 1))) void k_advect3d(
+__attribute__((amdgpu_waves_per_eu(cache3_lds<ST, STEADY, MET, BROWN>() ? 3 : (BROWN ? 2 : 1)))) void k_advect3d(
     AdvectParams P)
 {
     using R = typename Real<ST>::T;
@@ -1571,16 +1694,10 @@ __attribute__((amdgpu_waves_per_eu(cache3_lds<ST, STEADY, MET, BROWN>() ? 3 : 1)
                         zs = z + (sm[2] + k[2]) * dt6;
                     }
                     if (BROWN && P.Kh > 0.0) {
-                        uint32_t w[4] = {id, (uint32_t)(P.step0 + s), 0u, 0u};
-                        philox4x32_10(w, P.run_id, P.seed);
-                        const double u1 = unit53(w[0], w[1]), u2 = unit53(w[2], w[3]);
-                        const double r = sqrt(-2.0 * log(u1));
-                        double sn, cs;
-                        sincos((2.0 * 3.141592653589793) * u2, &sn, &cs);
-                        const double sig = sqrt(2.0 * P.Kh * dt);
-                        double dx = sig * (r * cs), dy = sig * (r * sn);
+                        double dx, dy;
+                        brownian_metres(P, id, P.step0 + s, dt, dx, dy);
                         if constexpr (MET != kFlat) {
-                            dx = dx / (kMetresPerDegree * cos(ys * kDegToRad));
+                            dx = dx * inv_metres_lon<MET>(c, P, ys);
                             dy = dy / kMetresPerDegree;
                         }
                         xs = xs + dx;
@@ -1639,12 +1756,7 @@ __global__ void k_philox_normals(uint32_t run_id, uint32_t seed, int64_t n, cons
         words[4 * i + 3] = w[3];
     }
     if (normals) {
-        const double u1 = unit53(w[0], w[1]), u2 = unit53(w[2], w[3]);
-        const double r = sqrt(-2.0 * log(u1));
-        double sn, cs;
-        sincos((2.0 * 3.141592653589793) * u2, &sn, &cs);
-        normals[2 * i] = r * cs;
-        normals[2 * i + 1] = r * sn;
+        box_muller(unit53(w[0], w[1]), unit53(w[2], w[3]), normals[2 * i], normals[2 * i + 1]);
     }
 }
 
@@ -1746,10 +1858,19 @@ hipError_t launch3(const AdvectParams &p, bool steady, uint32_t n_launch, hipStr
         return hipSuccess;
     // the cached kernels interpolate linearly and run no worked-example kernels
     if (!p.cache || p.nearest || p.behave) {
-        if (steady)
-            hipLaunchKernelGGL((k_advect<ST, IS3D, true>), dim3(blocks), dim3(kBlock), 0, s, p);
+        const bool brown = p.Kh > 0.0;
+        if (steady && brown)
+            hipLaunchKernelGGL((k_advect<ST, IS3D, true, true>), dim3(blocks), dim3(kBlock), 0,
+                               s, p);
+        else if (steady)
+            hipLaunchKernelGGL((k_advect<ST, IS3D, true, false>), dim3(blocks), dim3(kBlock), 0,
+                               s, p);
+        else if (brown)
+            hipLaunchKernelGGL((k_advect<ST, IS3D, false, true>), dim3(blocks), dim3(kBlock), 0,
+                               s, p);
         else
-            hipLaunchKernelGGL((k_advect<ST, IS3D, false>), dim3(blocks), dim3(kBlock), 0, s, p);
+            hipLaunchKernelGGL((k_advect<ST, IS3D, false, false>), dim3(blocks), dim3(kBlock),
+                               0, s, p);
         return hipGetLastError();
     }
     const dim3 g(blocks), b(kBlock);
