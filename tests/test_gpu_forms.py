@@ -35,6 +35,20 @@ def test_philox_words_bit_equal_and_normals():
     assert list(w[0]) == [0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8]
 
 
+def test_box_muller_normals_over_many_draws():
+    """The kernels' own logarithm, square root and quarter-turn sine and cosine against
+    the oracle's library functions over 200 000 draws (tails to |n| ~ 5)."""
+    from paper_1707_05163_amd import philox_normals
+    n = 200_000
+    pid = np.arange(n, dtype=np.uint32)
+    step = np.full(n, 12345, np.uint32)
+    _, normals = philox_normals(7, O.SEED, pid, step)
+    ref = np.array([O.normals(7, O.SEED, int(i), 12345) for i in range(n)])
+    err = np.abs(normals - ref)
+    assert (err <= 4e-15 * (1.0 + np.abs(ref))).all(), err.max()
+    assert np.abs(ref).max() > 4.0
+
+
 def test_paper_brownian_on_gpu():
     w = SI.brownian_uniform_kh()
     log(f"brownian: {w.n} particles x {w.nsteps} steps")
