@@ -332,7 +332,7 @@ def main_foram(a):
                    "snapshots": w.fields.nt, "particles": w.n, "days": 42, "dt_s": w.dt,
                    "kernels": "sink+age+sample+RK4_3D", "maxage_days": 30},
         "roofline": roof, "roofline_other": other,
-        "kernel": {"name": "k_advect (gather, with the worked-example kernels)",
+        "kernel": {"name": "k_advect3d (stencil cache, with the worked-example kernels)",
                    "launches": launches, "avg_launch_ms": round(avg_launch_s * 1e3, 4),
                    "particle_steps_per_launch": spl,
                    "kernel_share_of_step": round(kms / 1e3 / el, 4)},

@@ -1640,7 +1640,10 @@ __device__ inline bool stage3(const AdvectParams &P, Cell3<typename Real<ST>::T,
     return true;
 }
 
-template <int ST, bool STEADY, int MET, bool BROWN>
+// With BEHAVE the worked example's kernels (sinking, age, tracer sample; Sect. 4.3) run
+// ahead of each step as in the gather kernel, with the same code, and the advection
+// keeps the depth of a dwelling particle.
+template <int ST, bool STEADY, int MET, bool BROWN, bool BEHAVE>
 __global__ __launch_bounds__(kBlock)
 __attribute__((amdgpu_waves_per_eu(cache3_lds<ST, STEADY, MET, BROWN>() ? 3 : (BROWN ? 2 : 1)))) void k_advect3d(
     AdvectParams P)
@@ -1655,6 +1658,11 @@ __attribute__((amdgpu_waves_per_eu(cache3_lds<ST, STEADY, MET, BROWN>() ? 3 : (B
         uint8_t st = P.status[id];
         if (st == 0) {
             double x = P.x[id], y = P.y[id], z = P.z[id];
+            double temp = 0.0, age = 0.0;
+            if constexpr (BEHAVE) {
+                temp = P.temp[id];
+                age = P.age[id];
+            }
             constexpr bool DL = cache3_lds<ST, STEADY, MET, BROWN>();
             Cell3<R, DL> c;
             c.clear();
@@ -1666,6 +1674,15 @@ __attribute__((amdgpu_waves_per_eu(cache3_lds<ST, STEADY, MET, BROWN>() ? 3 : (B
                 const TimeEntry e0 = P.tab[2 * s], e1 = P.tab[2 * s + 1], e2 = P.tab[2 * s + 2];
                 const BracketMoves moves(P, s, e0, e1, e2);
                 uint8_t err = ST_OOB;
+                bool horizontal = false;
+                if constexpr (BEHAVE) {
+                    const uint8_t b =
+                        behave_pre<true, STEADY>(P, s, x, y, z, temp, age, horizontal);
+                    if (b) {
+                        st = b;
+                        break;
+                    }
+                }
                 double k[3] = {0.0, 0.0, 0.0}, sm[3] = {0.0, 0.0, 0.0};
                 const int nst = P.scheme ? 1 : 4;
 #pragma nounroll
@@ -1693,6 +1710,8 @@ __attribute__((amdgpu_waves_per_eu(cache3_lds<ST, STEADY, MET, BROWN>() ? 3 : (B
                         ys = y + (sm[1] + k[1]) * dt6;
                         zs = z + (sm[2] + k[2]) * dt6;
                     }
+                    if (BEHAVE && horizontal)  // a dwelling particle keeps its depth
+                        zs = z;
                     if (BROWN && P.Kh > 0.0) {
                         double dx, dy;
                         brownian_metres(P, id, P.step0 + s, dt, dx, dy);
@@ -1731,6 +1750,10 @@ __attribute__((amdgpu_waves_per_eu(cache3_lds<ST, STEADY, MET, BROWN>() ? 3 : (B
             P.x[id] = x;
             P.y[id] = y;
             P.z[id] = z;
+            if constexpr (BEHAVE) {
+                P.temp[id] = temp;
+                P.age[id] = age;
+            }
             if (st)
                 P.status[id] = st;
         }
@@ -1856,8 +1879,10 @@ hipError_t launch3(const AdvectParams &p, bool steady, uint32_t n_launch, hipStr
     const uint32_t blocks = (n_launch + kBlock - 1) / kBlock;
     if (blocks == 0)
         return hipSuccess;
-    // the cached kernels interpolate linearly and run no worked-example kernels
-    if (!p.cache || p.nearest || p.behave) {
+    // the cached kernels interpolate linearly; the worked-example kernels run in the 3D
+    // cached kernel for FP32 / FP64 fields without a Brownian term, else in the gather
+    constexpr bool kBehaveCached = IS3D && (ST == kF32 || ST == kF64);
+    if (!p.cache || p.nearest || (p.behave && (!kBehaveCached || p.Kh > 0.0))) {
         const bool brown = p.Kh > 0.0;
         if (steady && brown)
             hipLaunchKernelGGL((k_advect<ST, IS3D, true, true>), dim3(blocks), dim3(kBlock), 0,
@@ -1890,8 +1915,16 @@ hipError_t launch3(const AdvectParams &p, bool steady, uint32_t n_launch, hipStr
             constexpr bool dl = cache3_lds<ST, decltype(stc)::value, decltype(met)::value,
                                            decltype(brown)::value>();
             const size_t lds = dl ? (size_t)kBlock * cache3_slot<R>() * sizeof(R) : 0;
+            if constexpr (kBehaveCached && !decltype(brown)::value) {
+                if (p.behave) {
+                    hipLaunchKernelGGL((k_advect3d<ST, decltype(stc)::value, decltype(met)::value,
+                                                   false, true>),
+                                       g, b, lds, s, p);
+                    return;
+                }
+            }
             hipLaunchKernelGGL((k_advect3d<ST, decltype(stc)::value, decltype(met)::value,
-                                           decltype(brown)::value>),
+                                           decltype(brown)::value, false>),
                                g, b, lds, s, p);
         });
     }

@@ -65,9 +65,11 @@ def test_foram_backward_sink_age_sample(maxage_days):
     assert np.array_equal(age, st.age)
 
 
-def test_sample_only_keeps_the_plain_trajectory():
+@pytest.mark.parametrize("cache", [True, False])
+def test_sample_only_keeps_the_plain_trajectory(cache):
     """Sampling alone must not change the advection: positions equal to a run
-    without it (same kernel), and the samples match the oracle."""
+    without it (same kernel family: the cached 3D kernel, or the gather kernel), and
+    the samples match the oracle."""
     from paper_1707_05163_amd import FieldSet, ParticleSet
     w = SC.foram_footprint(nx=70, ny=60, nz=20, n_particles=2000, dt=-1800.0, days=4)
     w.depth0 = np.linspace(60.0, 3000.0, w.n)
@@ -75,8 +77,8 @@ def test_sample_only_keeps_the_plain_trajectory():
     a = ParticleSet(fs, w.lon0, w.lat0, w.depth0, t0=w.t0)
     b = ParticleSet(fs, w.lon0, w.lat0, w.depth0, t0=w.t0)
     rt = w.nsteps * abs(w.dt)
-    a.execute(rt, w.dt, DAY, stencil_cache=False)
-    b.execute(rt, w.dt, DAY, sample=True)
+    a.execute(rt, w.dt, DAY, stencil_cache=cache)
+    b.execute(rt, w.dt, DAY, sample=True, stencil_cache=cache)
     ga, gb = a.get(), b.get()
     assert np.array_equal(ga["lon"], gb["lon"]) and np.array_equal(ga["depth"], gb["depth"])
     ofs = O.OracleFieldSet.from_workload(w)
@@ -85,6 +87,30 @@ def test_sample_only_keeps_the_plain_trajectory():
     temp, _ = b.behaviour()
     ok = st.status == 0
     assert np.allclose(temp[ok], st.temp[ok], rtol=1e-9, atol=1e-9)
+
+
+def test_cached_and_gather_behaviour_agree():
+    """The worked example's kernels in the cached 3D kernel and in the gather kernel:
+    the same statuses and ages, positions and samples to the FP64 tolerance."""
+    from paper_1707_05163_amd import FieldSet, ParticleSet
+    w = SC.foram_footprint(nx=70, ny=60, nz=20, n_particles=3000, dt=-1800.0, days=22)
+    w.depth0 = np.linspace(60.0, 3000.0, w.n)  # reach the dwelling depth at different times
+    m = w.meta
+    fs = FieldSet.from_workload(w)
+    out = []
+    for cache in (True, False):
+        ps = ParticleSet(fs, w.lon0, w.lat0, w.depth0, t0=w.t0)
+        ps.execute(w.nsteps * abs(w.dt), w.dt, DAY, sink_speed=m["sink_speed"],
+                   dwell_depth=m["dwell_depth"], maxage=10 * DAY, sample=True,
+                   stencil_cache=cache)
+        out.append((ps.get(), ps.status()[1], ps.behaviour()))
+    (ga, sa, (ta, aa)), (gb, sb, (tb, ab)) = out
+    assert np.array_equal(sa, sb) and np.array_equal(aa, ab)
+    ok = sa == 0
+    assert ok.sum() > 0 and (sa != 0).sum() > 0
+    for k in ("lon", "lat", "depth"):
+        assert np.allclose(ga[k][ok], gb[k][ok], rtol=1e-9, atol=1e-9 * 360.0), k
+    assert np.allclose(ta[ok], tb[ok], rtol=1e-9, atol=1e-9)
 
 
 def test_behaviour_argument_errors():
