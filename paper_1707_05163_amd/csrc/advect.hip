@@ -1369,8 +1369,10 @@ __device__ inline void rkf45_refill(const AdvectParams &P)
     }
 }
 
+// 4 waves per SIMD in 2D (the kernel needs one register more than that allows)
 template <int ST, bool IS3D, bool STEADY>
-__global__ __launch_bounds__(kBlock) void k_rkf45(AdvectParams P)
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(IS3D ? 1 : 4))) void k_rkf45(AdvectParams P)
 {
     rkf45_refill<GatherLane<ST, IS3D, STEADY>>(P);
 }
