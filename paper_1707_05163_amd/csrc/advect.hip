@@ -1082,9 +1082,10 @@ __device__ inline long long advect_lane_2d(const AdvectParams &P, uint32_t k, ui
                 // the four stages: offsets 0, dt/2, dt/2, dt from X_n along the previous
                 // slope; weights 1, 2, 2, 1
                 double kx = 0.0, ky = 0.0, sx = 0.0, sy = 0.0;
-                const int nst = P.scheme ? 1 : 4;
-#pragma nounroll
-                for (int q = 0; q < nst; ++q) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (q > 0 && P.scheme)  // Euler forward: one stage
+                        break;
                     // wave-uniform stage constants: time entry, offset along the
                     // previous slope, and the slope's weight in the sum (stage 4's
                     // slope is added after the loop)
@@ -1152,7 +1153,7 @@ __device__ inline long long advect_lane_2d(const AdvectParams &P, uint32_t k, ui
 
 template <int ST, bool STEADY, int MET, bool BROWN>
 __global__ __launch_bounds__(kBlock)
-__attribute__((amdgpu_waves_per_eu(BROWN ? 3 : (MET != kSphLib ? 5 : 1)))) void k_advect2d(
+__attribute__((amdgpu_waves_per_eu(BROWN ? 3 : (MET != kSphLib ? 4 : 1)))) void k_advect2d(
     AdvectParams P)
 {
     const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
