@@ -67,6 +67,29 @@ def test_paper_brownian_on_gpu():
     assert np.sqrt(0.5 * (g["lon"].var() + g["lat"].var())) == pytest.approx(4160.0, rel=0.01)
 
 
+@pytest.mark.parametrize("nx,cache", [(1440, True), (288, True), (144, True), (36, True),
+                                      (144, False)])
+def test_brownian_on_the_sphere(nx, cache):
+    """The Brownian term on a spherical grid against the oracle, for each way the kernels
+    take cos(lat): the cell's series with 2, 3 or 4 terms (cells of 0.25, 1.25 and 2.5
+    degrees) and the library cosine (10 degree cells), and in the gather kernel."""
+    from paper_1707_05163_amd import FieldSet, ParticleSet
+    w = SC.cfg1_global_eddies(nx=nx, ny=nx // 2, nt=30, n_particles=3000, nsteps=288)
+    log(f"spherical Brownian nx={nx} cache={cache}")
+    fs = FieldSet.from_workload(w)
+    ps = ParticleSet(fs, w.lon0, w.lat0)
+    ps.execute(w.nsteps * w.dt, w.dt, 6 * 3600.0, Kh=50.0, run_id=11, output_stride=1,
+               stencil_cache=cache)
+    recs = ps.records()
+    ofs = O.OracleFieldSet.from_workload(w)
+    st = O.make_state(w.lon0, w.lat0)
+    orecs = O.run(ofs, st, w.dt, w.nsteps * w.dt, 6 * 3600.0, Kh=50.0, run_id=11)
+    for m, o in enumerate(orecs):
+        compare_record(slice_record(recs, m), o, w.grid, 360.0, label=f"nx={nx} rec {m}",
+                       ofs=ofs)
+    assert np.array_equal(ps.status()[1], st.status)
+
+
 def test_brownian_in_eddy_field_with_edge_deletion():
     runs = SC.cfg3_ensemble(n_runs=3, np_min=2000, np_max=4000, nsteps=288)
     from paper_1707_05163_amd import FieldSet, ParticleSet
