@@ -58,6 +58,9 @@ COUNTERS = {
     "advect_sha256": "3569f57753fa27500fe1bbb36d515942f1b5a6cd799dfd172f2a3aff890647f4",
     "cfg1": (163105.5, 65030.3),   # (FETCH_SIZE KiB, WRITE_SIZE KiB) per launch of k_advect2d
     "cfg2": (6474286.6, 1497693.6),  # the same for k_advect3d
+    # (TCC_HIT_sum, TCC_MISS_sum) per launch: L2 requests of the same kernels
+    "cfg1_l2": (3286819.7, 4103237.2),
+    "cfg2_l2": (122351966.5, 135508388.1),
 }
 
 
@@ -129,6 +132,19 @@ def measured_traffic(mode, default_workload):
         return None
     fetch_kib, write_kib = c
     return (fetch_kib * FETCH_SCALE + write_kib * WRITE_SCALE) * 1024.0
+
+
+def measured_counters(mode, default_workload, steps_per_launch):
+    """The counter record of the dominant kernel (HBM bytes per launch, L2 hit rate and
+    L2 requests per particle-step), or None as for measured_traffic."""
+    t = measured_traffic(mode, default_workload)
+    l2 = COUNTERS.get(mode + "_l2")
+    if t is None or l2 is None:
+        return None
+    hit, miss = l2
+    return {"hbm_bytes_per_launch": round(t), "l2_hit_rate": round(hit / (hit + miss), 4),
+            "l2_requests_per_particle_step": round((hit + miss) / steps_per_launch, 5),
+            "source": "profiles/counters_k_advect2d_cfg1_k_advect3d_cfg2.md"}
 
 
 def roofline(steps_per_launch, avg_launch_s, bytes_per_step, flops_per_step,
@@ -232,6 +248,7 @@ def main_cfg2(a):
                    "field_dtype": a.dtype, "stencil_cache": a.stencil_cache,
                    "sort_every": a.sort_every},
         "roofline": roof, "roofline_other": other,
+        "counters": measured_counters("cfg2", default, spl),
         "kernel": {"name": "k_advect3d" if a.stencil_cache else "k_advect", "launches": launches,
                    "avg_launch_ms": round(avg_launch_s * 1e3, 4),
                    "particle_steps_per_launch": spl,
@@ -635,6 +652,7 @@ def main():
                    "sort_every": a.sort_every, "Kh": a.kh},
         "roofline": roof,
         "roofline_other": other,
+        "counters": measured_counters("cfg1", default, steps_per_launch),
         "kernel": {"name": "k_advect2d" if a.stencil_cache else "k_advect", "launches": launches,
                    "avg_launch_ms": round(avg_launch_s * 1e3, 4),
                    "particle_steps_per_launch": steps_per_launch,
