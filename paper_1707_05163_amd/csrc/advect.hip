@@ -863,9 +863,11 @@ __device__ inline R *cache_slot_ptr()
 
 // How many coefficients the cached 2D kernels keep in LDS: with the Brownian term
 // the kernel holds enough other state that the occupancy is the same either way, so
-// all stay in registers; otherwise the later-minus-earlier half goes to LDS.
+// all stay in registers; otherwise all go to LDS (with the unrolled stages, register
+// coefficients cost a copy of themselves at every stage's join of the cached and
+// reloaded paths).
 template <int ST, bool BROWN>
-constexpr int cache_lds_coefs() { return BROWN ? 0 : 8; }
+constexpr int cache_lds_coefs() { return BROWN ? 0 : 16; }
 
 template <class R>
 __device__ inline void coeffs(const R f00, const R f10, const R f01, const R f11, R c[4])
