@@ -829,11 +829,16 @@ struct Cell2 {
     double rx, ry;          // inverse cell widths
     double cl, sl;          // cos and sin of the lower latitude face
     // U, V coefficients of the earlier snapshot [0..7], later minus earlier [8..15]
-    R *lc;                  // LDS slot: coefficients 16 - NL .. 15
+    R *lc;                  // LDS: this lane's first 16-byte group of coefficients
+                            // 16 - NL .. 15 (see cache_slot_ptr)
+    uint32_t gs;            // elements from one of the lane's groups to the next
     R lr[NL < 16 ? 16 - NL : 1];  // registers: coefficients 0 .. 15 - NL
     bool land;
-    __device__ R &coef(int i) { return i < 16 - NL ? lr[i] : lc[i - (16 - NL)]; }
-    __device__ R coef(int i) const { return i < 16 - NL ? lr[i] : lc[i - (16 - NL)]; }
+    static constexpr int G = 16 / (int)sizeof(R);  // coefficients per 16-byte group
+    __device__ R &lds(int j) { return lc[(j / G) * gs + j % G]; }
+    __device__ R lds(int j) const { return lc[(j / G) * gs + j % G]; }
+    __device__ R &coef(int i) { return i < 16 - NL ? lr[i] : lds(i - (16 - NL)); }
+    __device__ R coef(int i) const { return i < 16 - NL ? lr[i] : lds(i - (16 - NL)); }
     // no point is in the cell until the next reload (an empty x range also keeps a
     // NaN position out)
     __device__ void invalidate()
@@ -848,17 +853,25 @@ struct Cell2 {
     }
 };
 
-// Per-lane LDS slots of the 2D stencil cache: NL coefficients plus 16 bytes, a stride
-// (144, 80 or 48 B) that keeps every 16-byte read aligned and puts the 16 lanes of one
-// LDS cycle on distinct banks.  Elements of R per lane.
+// The 2D stencil cache in LDS is an array of 16-byte groups, group g of thread t at
+// (g * blockDim + t) * 16 bytes: a wave's read of one group covers 1 KB of consecutive
+// words (no bank conflicts) and a lane needs no padding, so NL doubles take exactly
+// 8 NL bytes per lane (5 waves per SIMD of 16 coefficients fit the 160 KB).  Elements
+// of R per lane, for the launch's LDS size:
 template <class R, int NL>
-constexpr int cache_slot() { return NL ? (NL * (int)sizeof(R) + 16) / (int)sizeof(R) : 0; }
+constexpr int cache_slot() { return NL; }
 
 template <class R, int NL>
 __device__ inline R *cache_slot_ptr()
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char cache_lds[];
-    return reinterpret_cast<R *>(cache_lds) + threadIdx.x * cache_slot<R, NL>();
+    return reinterpret_cast<R *>(cache_lds) + threadIdx.x * (16 / sizeof(R));
+}
+
+template <class R>
+__device__ inline uint32_t cache_group_stride()
+{
+    return blockDim.x * (16 / (uint32_t)sizeof(R));
 }
 
 // How many coefficients the cached 2D kernels keep in LDS: with the Brownian term
@@ -1003,9 +1016,21 @@ __device__ inline double cos_series(double cl, double sl, double y0, double y, i
 }
 
 // Metric modes of the cached kernels, fixed at compile time so that a launch carries
-// only the code it runs: flat mesh; spherical with the latitude tables and series;
-// spherical with cells too tall for the series (library cos).
-enum : int { kFlat = 0, kSphTable = 1, kSphLib = 2 };
+// only the code it runs: flat mesh; spherical with the latitude tables and a series
+// whose length (3 or 4 terms) is read at run time; spherical with cells too tall for
+// the series (library cos); spherical with the 2-term series (cells up to 0.3 degree,
+// the common fine-grid case, with no branch on the length).
+enum : int { kFlat = 0, kSphTable = 1, kSphLib = 2, kSphTable2 = 3 };
+
+template <int MET>
+constexpr bool met_series() { return MET == kSphTable || MET == kSphTable2; }
+
+template <int MET>
+__device__ inline double cos_series_m(double cl, double sl, double y0, double y,
+                                      const AdvectParams &P)
+{
+    return cos_series(cl, sl, y0, y, MET == kSphTable2 ? 2 : P.g.cos_terms);
+}
 
 template <int MET, class R, int NL>
 __device__ inline double cos_lat(const Cell2<R, NL> &c, const AdvectParams &P, double y)
@@ -1013,7 +1038,7 @@ __device__ inline double cos_lat(const Cell2<R, NL> &c, const AdvectParams &P, d
     if constexpr (MET == kSphLib)
         return cos(y * kDegToRad);
     else
-        return cos_series(c.cl, c.sl, c.y0, y, P.g.cos_terms);
+        return cos_series_m<MET>(c.cl, c.sl, c.y0, y, P);
 }
 
 // 1 / (M cos(lat)) at the end point of a step, for the metric of the Brownian term: the
@@ -1022,8 +1047,8 @@ __device__ inline double cos_lat(const Cell2<R, NL> &c, const AdvectParams &P, d
 template <int MET, class CellT>
 __device__ inline double inv_metres_lon(const CellT &c, const AdvectParams &P, double y)
 {
-    if (MET == kSphTable && y >= c.y0 && y < c.uy)
-        return recip(kMetresPerDegree * cos_series(c.cl, c.sl, c.y0, y, P.g.cos_terms));
+    if (met_series<MET>() && y >= c.y0 && y < c.uy)
+        return recip(kMetresPerDegree * cos_series_m<MET>(c.cl, c.sl, c.y0, y, P));
     return recip(kMetresPerDegree * cos_deg(y));
 }
 
@@ -1073,8 +1098,10 @@ __device__ inline long long advect_lane_2d(const AdvectParams &P, uint32_t k, ui
             constexpr int NL = cache_lds_coefs<ST, BROWN>();
             Cell2<R, NL> c;
             c.clear();
-            if constexpr (NL > 0)
+            if constexpr (NL > 0) {
                 c.lc = cache_slot_ptr<R, NL>();
+                c.gs = cache_group_stride<R>();
+            }
             const double dt = P.dt, dt6 = P.dt6;
             for (int s = 0; s < P.nsteps; ++s) {
                 ++steps;
@@ -1088,19 +1115,21 @@ __device__ inline long long advect_lane_2d(const AdvectParams &P, uint32_t k, ui
                 for (int q = 0; q < 4; ++q) {
                     if (q > 0 && P.scheme)  // Euler forward: one stage
                         break;
-                    // wave-uniform stage constants: time entry, offset along the
-                    // previous slope, and the slope's weight in the sum (stage 4's
-                    // slope is added after the loop)
+                    // stage constants (folded by the unrolling): time entry and
+                    // offset along the previous slope; the slopes are summed with
+                    // weights 1, 2, 2 here and stage 4's is added after the loop
                     const TimeEntry e = q == 0 ? e0 : (q == 3 ? e2 : e1);
-                    // (stage 1 adds a zero slope, so its offset is immaterial; the
-                    // half step comes in with the launch, as a scalar operand)
-                    const double h = q == 3 ? dt : P.hdt;
-                    const double wq = q == 0 ? 1.0 : (q == 3 ? 0.0 : 2.0);
-                    if (!stage2<ST, STEADY, MET, NL>(P, c, e, moves.at(q), x + kx * h,
-                                                         y + ky * h, kx, ky))
+                    const double h = q == 3 ? dt : P.hdt;  // (a scalar operand)
+                    const double px = q == 0 ? x : x + kx * h, py = q == 0 ? y : y + ky * h;
+                    if (!stage2<ST, STEADY, MET, NL>(P, c, e, moves.at(q), px, py, kx, ky))
                         goto fail;
-                    sx = fma(wq, kx, sx);
-                    sy = fma(wq, ky, sy);
+                    if (q == 0) {
+                        sx = kx;
+                        sy = ky;
+                    } else if (q < 3) {
+                        sx = fma(2.0, kx, sx);
+                        sy = fma(2.0, ky, sy);
+                    }
                 }
                 {
                     double xs, ys;
@@ -1153,9 +1182,12 @@ __device__ inline long long advect_lane_2d(const AdvectParams &P, uint32_t k, ui
     return steps;
 }
 
+// Occupancy targets: 5 waves per SIMD for the flat and 2-term spherical modes (their
+// registers and the 16-coefficient LDS cache both fit 5), 4 for the longer series, 3
+// with the Brownian term.
 template <int ST, bool STEADY, int MET, bool BROWN>
-__global__ __launch_bounds__(kBlock)
-__attribute__((amdgpu_waves_per_eu(BROWN ? 3 : (MET != kSphLib ? 4 : 1)))) void k_advect2d(
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
+    BROWN ? 3 : (MET == kSphLib ? 1 : (MET == kSphTable ? 4 : 5))))) void k_advect2d(
     AdvectParams P)
 {
     const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
@@ -1214,6 +1246,7 @@ struct CachedLane2 {
         y = P.y[id];
         c.clear();
         c.lc = cache_slot_ptr<R, 16>();
+        c.gs = cache_group_stride<R>();
         csa = csb = -1;
         lt.lo = -1;
     }
@@ -1634,7 +1667,7 @@ __device__ inline bool stage3(const AdvectParams &P, Cell3<typename Real<ST>::T,
         if constexpr (MET == kSphLib)
             cosl = cos(y * kDegToRad);
         else
-            cosl = cos_series(c.cl, c.sl, c.y0, y, P.g.cos_terms);
+            cosl = cos_series_m<MET>(c.cl, c.sl, c.y0, y, P);
         k[0] = (double)v[0] * recip(kMetresPerDegree * cosl);
         k[1] = (double)v[1] * (1.0 / kMetresPerDegree);
     } else {
@@ -1855,7 +1888,9 @@ template <int I> using IntC = std::integral_constant<int, I>;
 template <class F>
 hipError_t dispatch_cached(const AdvectParams &p, bool steady, F &&f)
 {
-    const int met = !p.g.spherical ? kFlat : (p.g.coslat ? kSphTable : kSphLib);
+    const int met = !p.g.spherical
+                        ? kFlat
+                        : (p.g.coslat ? (p.g.cos_terms == 2 ? kSphTable2 : kSphTable) : kSphLib);
     const bool brown = p.Kh > 0.0;
     auto with_met = [&](auto stc) {
         auto with_brown = [&](auto m) {
@@ -1866,6 +1901,8 @@ hipError_t dispatch_cached(const AdvectParams &p, bool steady, F &&f)
         };
         if (met == kFlat)
             with_brown(IntC<kFlat>{});
+        else if (met == kSphTable2)
+            with_brown(IntC<kSphTable2>{});
         else if (met == kSphTable)
             with_brown(IntC<kSphTable>{});
         else
@@ -2097,7 +2134,10 @@ hipError_t launch_advect_batch(int store, bool steady, int met, bool brown,
         constexpr int ST = decltype(st)::value;
         AdvectParams q{};  // only the mode fields matter to the dispatcher
         q.g.spherical = met != kFlat;
-        q.g.coslat = met == kSphTable ? reinterpret_cast<const double *>(1) : nullptr;
+        q.g.coslat = (met == kSphTable || met == kSphTable2)
+                         ? reinterpret_cast<const double *>(1)
+                         : nullptr;
+        q.g.cos_terms = met == kSphTable2 ? 2 : 3;
         q.Kh = brown ? 1.0 : 0.0;
         hipError_t r = hipSuccess;
         (void)dispatch_cached(q, steady, [&](auto stc, auto m, auto b) {

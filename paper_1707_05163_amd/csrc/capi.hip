@@ -1203,10 +1203,15 @@ int execute_batch(lp_pset **ps, int32_t nruns, double runtime, double dt, double
         int met = 0;
         bool brown = false;
         if (f0->g.spherical) {
-            met = 1;
-            for (int r = 0; r < nruns; ++r)
-                if (!ps[r]->fs->g.coslat)
+            met = 3;  // every grid takes the 2-term latitude series
+            for (int r = 0; r < nruns; ++r) {
+                if (!ps[r]->fs->g.coslat) {
                     met = 2;  // some grid has cells too tall for the latitude series
+                    break;
+                }
+                if (ps[r]->fs->g.cos_terms != 2)
+                    met = 1;
+            }
         }
         for (int r = 0; r < nruns; ++r)
             brown = brown || opts[r].Kh > 0.0;

@@ -145,7 +145,8 @@ hipError_t launch_advect(int store, bool is3d, const AdvectParams &p, uint32_t n
 hipError_t launch_rkf45(int store, bool is3d, const AdvectParams &p, uint32_t n_launch,
                         hipStream_t s);
 hipError_t launch_record(const RecordParams &p, hipStream_t s);
-// batched launch: met 0 flat, 1 spherical with latitude tables, 2 spherical without;
+// batched launch: met 0 flat, 1 spherical with latitude tables, 2 spherical without,
+// 3 spherical with latitude tables and the 2-term series in every run;
 // brown: some run has a Brownian term
 hipError_t launch_advect_batch(int store, bool steady, int met, bool brown,
                                const AdvectParams *runs, const uint32_t *cstart, int nruns,
