@@ -155,10 +155,10 @@ typedef struct {
     int32_t sort_every;   /* re-sort particles by grid tile every k output
                              segments (0 = never) */
     int32_t profile;      /* 1: time each advection launch with HIP events */
-    int32_t stencil_cache;/* 1: each lane keeps its cell's stencil in registers and
-                             reloads it only when it changes cell or snapshot pair;
-                             0: gather the stencil at every stage (same results up
-                             to rounding) */
+    int32_t stencil_cache;/* 1: each lane keeps its cell's stencil (as interpolation
+                             coefficients, in registers and LDS) and reloads it only
+                             when it changes cell or snapshot pair; 0: gather the
+                             stencil at every stage (same results up to rounding) */
     int32_t interp;       /* LP_INTERP_LINEAR or LP_INTERP_NEAREST */
     /* LP_KERNEL_RKF45 (the adaptive scheme named in Sect. 2.1.1; the control
      * rule is this library's reading): each particle steps by |dt| 2^e with its
@@ -171,7 +171,8 @@ typedef struct {
      * maximum).  The last step of each output interval is cut short to land on
      * the output time and leaves e unchanged.  Needs Kh = 0; the batched launch
      * and the autotuner do not take it.  In 2D, stencil_cache = 1 runs the six
-     * stages on the register stencil cache (same results up to rounding). */
+     * stages on the stencil cache (same results up to rounding); the gather form
+     * (stencil_cache = 0) is the faster one at RKF45's long steps. */
     double rkf_tol;       /* > 0, metres per step */
     int32_t rkf_min_exp;  /* in [-30, 0]; |dt| 2^min must still move the clock */
     int32_t rkf_max_exp;  /* in [0, 30] */
@@ -185,7 +186,9 @@ typedef struct {
      * and does not move.  Sample (sample_tracer = 1): the particle's temp becomes
      * the tracer at its position and the step's start time.  While a sinking
      * particle is at its dwelling depth the advection is horizontal only.  Any of
-     * these needs LP_KERNEL_RK4 or LP_KERNEL_EULER; they run on the gather kernels. */
+     * these needs LP_KERNEL_RK4 or LP_KERNEL_EULER.  With stencil_cache = 1 they run
+     * in the cached 3D kernel for FP32/FP64 fields without a Brownian term, else in
+     * the gather kernel (same results up to rounding). */
     double sink_speed;    /* m/s, >= 0 (0 = off) */
     double dwell_depth;   /* m */
     double maxage;        /* s, >= 0 (0 = off) */
