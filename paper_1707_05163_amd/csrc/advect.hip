@@ -1199,14 +1199,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
         atomicAdd(P.psteps, (unsigned long long)steps);
 }
 
-// Persistent batched launch over many independent runs (each with its own grid,
-// snapshots and particles).  The active particles of every run are cut into
-// chunks of blockDim particles; the chunk items are split into 8 contiguous
-// ranges, one per XCD, each with its own atomic counter.  A block takes items from
-// the range of the XCD it runs on and, when that is exhausted, from the others;
-// every block leaves once all 8 ranges are exhausted, so the grid always drains.
 // ---------------------------------------------------------------- 2D RKF45 with the cache
-// The adaptive scheme on the register stencil cache: each of the six Fehlberg
+// The adaptive scheme on the stencil cache (LDS slots): each of the six Fehlberg
 // stages is a stage2() evaluation (the cached bilinear polynomials, reloaded when
 // the stage point leaves the cell or the lane's time bracket moves on).  The stage
 // loop is not unrolled; the tableau rows come from constant memory and the earlier
@@ -1419,6 +1413,12 @@ __global__ __launch_bounds__(kBlock) void k_rkf45_2d(AdvectParams P)
     rkf45_refill<CachedLane2<ST, STEADY, MET>>(P);
 }
 
+// Persistent batched launch over many independent runs (each with its own grid,
+// snapshots and particles).  The active particles of every run are cut into
+// chunks of blockDim particles; the chunk items are split into 8 contiguous
+// ranges, one per XCD, each with its own atomic counter.  A block takes items from
+// the range of the XCD it runs on and, when that is exhausted, from the others;
+// every block leaves once all 8 ranges are exhausted, so the grid always drains.
 // Occupancy target: 4 waves per SIMD (at most 128 VGPRs) for the plain modes, where
 // it costs one spill outside the step loop; 3 for the Brownian term and the library
 // cosine, whose extra state would spill inside it.

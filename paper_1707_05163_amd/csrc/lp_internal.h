@@ -68,7 +68,7 @@ struct AdvectParams {
     int64_t step0;           // step index (from t0) of the first step of the launch
     int32_t nsteps;
     int32_t policy;          // 0 delete, 1 freeze
-    int32_t cache;           // 1: register stencil cache kernels
+    int32_t cache;           // 1: stencil cache kernels
     int32_t scheme;          // 0 RK4, 1 Euler forward
     int32_t nearest;         // 1: nearest-neighbour in space
     double Kh;
