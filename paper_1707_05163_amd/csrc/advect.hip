@@ -260,30 +260,41 @@ __device__ inline double recip(double d)
 // in f (coefficients (pi/2)^n / n!), cut after the f^17 and f^16 terms (the first
 // terms left out are below 1e-19 and 3e-18 at |f| = 1/2), and the quadrant q mod 4
 // rotates the pair.
-__device__ inline void sincos_turn(double u, double &sn, double &cs)
+// The polynomial coefficients of sincos_turn and log_unit, in constant memory: the
+// Brownian kernels read them with scalar loads inside their step loop (an index the
+// compiler cannot prove constant keeps the loads there), so that they do not sit in
+// vector registers across the loop.
+__constant__ double kBmCoef[28] = {
+    // sin(f pi/2) / f, highest power first (9)
+    0x1.aaec32af93359p-38, -0x1.6fadb9f155744p-31, 0x1.e8f434d018d63p-25,
+    -0x1.e3074fde8871fp-19, 0x1.50783487ee782p-13, -0x1.32d2cce62bd86p-8,
+    0x1.466bc6775aae2p-4, -0x1.4abbce625be53p-1, 0x1.921fb54442d18p+0,
+    // (cos(f pi/2) - 1) / f^2, highest power first (8)
+    0x1.20c62c2f2d7f5p-34, -0x1.b6e24f44b128fp-28, 0x1.f9d38a3763cc3p-22,
+    -0x1.a6d1f2a204a8cp-16, 0x1.e1f506891babbp-11, -0x1.55d3c7e3cbffap-6,
+    0x1.03c1f081b5ac4p-2, -0x1.3bd3cc9be45dep+0,
+    // atanh series 1/19 .. 1/3 (9)
+    1.0 / 19.0, 1.0 / 17.0, 1.0 / 15.0, 1.0 / 13.0, 1.0 / 11.0, 1.0 / 9.0, 1.0 / 7.0,
+    1.0 / 5.0, 1.0 / 3.0,
+    // log 2, head and tail (2)
+    0x1.62e42fefa3800p-1, 0x1.ef35793c76730p-45};
+
+__device__ inline void sincos_turn(double u, double &sn, double &cs,
+                                   const double *k = kBmCoef)
 {
     const double t = 4.0 * u;
     const double q = rint(t);
     const double f = t - q;  // exact
     const double f2 = f * f;
-    double ps = 0x1.aaec32af93359p-38;
-    ps = fma(ps, f2, -0x1.6fadb9f155744p-31);
-    ps = fma(ps, f2, 0x1.e8f434d018d63p-25);
-    ps = fma(ps, f2, -0x1.e3074fde8871fp-19);
-    ps = fma(ps, f2, 0x1.50783487ee782p-13);
-    ps = fma(ps, f2, -0x1.32d2cce62bd86p-8);
-    ps = fma(ps, f2, 0x1.466bc6775aae2p-4);
-    ps = fma(ps, f2, -0x1.4abbce625be53p-1);
-    ps = fma(ps, f2, 0x1.921fb54442d18p+0);
+    double ps = k[0];
+#pragma unroll
+    for (int i = 1; i < 9; ++i)
+        ps = fma(ps, f2, k[i]);
     const double S = ps * f;
-    double pc = 0x1.20c62c2f2d7f5p-34;
-    pc = fma(pc, f2, -0x1.b6e24f44b128fp-28);
-    pc = fma(pc, f2, 0x1.f9d38a3763cc3p-22);
-    pc = fma(pc, f2, -0x1.a6d1f2a204a8cp-16);
-    pc = fma(pc, f2, 0x1.e1f506891babbp-11);
-    pc = fma(pc, f2, -0x1.55d3c7e3cbffap-6);
-    pc = fma(pc, f2, 0x1.03c1f081b5ac4p-2);
-    pc = fma(pc, f2, -0x1.3bd3cc9be45dep+0);
+    double pc = k[9];
+#pragma unroll
+    for (int i = 10; i < 17; ++i)
+        pc = fma(pc, f2, k[i]);
     const double C = fma(pc, f2, 1.0);
     const int qi = (int)q;
     double a = (qi & 1) ? C : S, b = (qi & 1) ? S : C;
@@ -296,7 +307,7 @@ __device__ inline void sincos_turn(double u, double &sn, double &cs)
 // from the series atanh(s) = s + s^3/3 + s^5/5 + ..., cut after s^19 (the first term
 // left out is below 2.4e-17 relative); e log 2 with log 2 split into a head whose
 // products with |e| < 2^11 are exact and a tail.  Within about two ulps.
-__device__ inline double log_unit(double u)
+__device__ inline double log_unit(double u, const double *k = kBmCoef)
 {
     int e;
     double m = frexp(u, &e);  // m in [1/2, 1)
@@ -311,19 +322,14 @@ __device__ inline double log_unit(double u)
     double sq = num * r;
     sq = fma(fma(-den, sq, num), r, sq);  // s to within an ulp
     const double z = sq * sq;
-    double p = 1.0 / 19.0;
-    p = fma(p, z, 1.0 / 17.0);
-    p = fma(p, z, 1.0 / 15.0);
-    p = fma(p, z, 1.0 / 13.0);
-    p = fma(p, z, 1.0 / 11.0);
-    p = fma(p, z, 1.0 / 9.0);
-    p = fma(p, z, 1.0 / 7.0);
-    p = fma(p, z, 1.0 / 5.0);
-    p = fma(p, z, 1.0 / 3.0);
+    double p = k[17];
+#pragma unroll
+    for (int i = 18; i < 26; ++i)
+        p = fma(p, z, k[i]);
     const double s2 = 2.0 * sq;
     const double lm = fma(s2 * z, p, s2);  // log m
     const double de = (double)e;
-    return fma(de, 0x1.62e42fefa3800p-1, fma(de, 0x1.ef35793c76730p-45, lm));
+    return fma(de, k[26], fma(de, k[27], lm));
 }
 
 // Square root of x in [2^-60, 2^60]: the hardware reciprocal square root refined by two
@@ -348,25 +354,33 @@ __device__ inline double cos_deg(double lat)
     return cs;
 }
 
-// Two standard normals from two uniforms (Box-Muller).
-__device__ inline void box_muller(double u1, double u2, double &n1, double &n2)
+// Two standard normals from two uniforms (Box-Muller); k: the coefficient table.
+__device__ inline void box_muller(double u1, double u2, double &n1, double &n2,
+                                  const double *k = kBmCoef)
 {
-    const double r = sqrt_mid(-2.0 * log_unit(u1));
+    const double r = sqrt_mid(-2.0 * log_unit(u1, k));
     double sn, cs;
-    sincos_turn(u2, sn, cs);
+    sincos_turn(u2, sn, cs, k);
     n1 = r * cs;
     n2 = r * sn;
 }
 
 // The random term of Eq. (1) for one step, in metres: sqrt(2 Kh |dt|) times the two
 // normals drawn from the particle's Philox words for (id, step).
+// LOOP_LOADS: read the Box-Muller coefficients inside the step loop (P.zero is 0 at
+// run time, but the compiler cannot know it, so the scalar loads stay in the loop
+// instead of the constants occupying vector registers across it).  That pays in the
+// flat Brownian kernels (it takes them from 3 to 4 waves per SIMD); the spherical
+// ones, with the metric's extra state, are faster with the constants in place.
+template <bool LOOP_LOADS>
 __device__ inline void brownian_metres(const AdvectParams &P, uint32_t id, int64_t step,
                                        double dt, double &dx, double &dy)
 {
     uint32_t w[4] = {id, (uint32_t)step, 0u, 0u};
     philox4x32_10(w, P.run_id, P.seed);
     double n1, n2;
-    box_muller(unit53(w[0], w[1]), unit53(w[2], w[3]), n1, n2);
+    box_muller(unit53(w[0], w[1]), unit53(w[2], w[3]), n1, n2,
+               LOOP_LOADS ? kBmCoef + (P.zero & (uint32_t)step) : kBmCoef);
     const double sig = sqrt(2.0 * P.Kh * dt);
     dx = sig * n1;
     dy = sig * n2;
@@ -408,7 +422,7 @@ __device__ inline uint8_t rk4_step(const AdvectParams &P, int s, uint32_t id, do
     }
     if (BROWN && P.Kh > 0.0) {
         double dx, dy;
-        brownian_metres(P, id, P.step0 + s, dt, dx, dy);
+        brownian_metres<false>(P, id, P.step0 + s, dt, dx, dy);
         if (P.g.spherical) {
             dx = dx * recip(kMetresPerDegree * cos_deg(ys));
             dy = dy / kMetresPerDegree;
@@ -1142,7 +1156,7 @@ __device__ inline long long advect_lane_2d(const AdvectParams &P, uint32_t k, ui
                     }
                     if (BROWN && P.Kh > 0.0) {
                         double dx, dy;
-                        brownian_metres(P, id, P.step0 + s, dt, dx, dy);
+                        brownian_metres<MET == kFlat>(P, id, P.step0 + s, dt, dx, dy);
                         if constexpr (MET != kFlat) {
                             dx = dx * inv_metres_lon<MET>(c, P, ys);
                             dy = dy / kMetresPerDegree;
@@ -1752,7 +1766,7 @@ __attribute__((amdgpu_waves_per_eu(cache3_lds<ST, STEADY, MET, BROWN>() ? 3 : (B
                         zs = z;
                     if (BROWN && P.Kh > 0.0) {
                         double dx, dy;
-                        brownian_metres(P, id, P.step0 + s, dt, dx, dy);
+                        brownian_metres<MET == kFlat>(P, id, P.step0 + s, dt, dx, dy);
                         if constexpr (MET != kFlat) {
                             dx = dx * inv_metres_lon<MET>(c, P, ys);
                             dy = dy / kMetresPerDegree;

@@ -71,6 +71,7 @@ struct AdvectParams {
     int32_t cache;           // 1: stencil cache kernels
     int32_t scheme;          // 0 RK4, 1 Euler forward
     int32_t nearest;         // 1: nearest-neighbour in space
+    uint32_t zero;           // always 0 (an offset the compiler cannot fold)
     double Kh;
     uint32_t run_id, seed;
     double *x, *y, *z;       // particle state, id order
