@@ -896,6 +896,19 @@ __device__ inline uint32_t cache_group_stride()
 template <int ST, bool BROWN>
 constexpr int cache_lds_coefs() { return BROWN ? 0 : 16; }
 
+// Metric modes of the cached kernels, fixed at compile time so that a launch carries
+// only the code it runs: flat mesh; spherical with the latitude tables and a series
+// whose length (3 or 4 terms) is read at run time; spherical with cells too tall for
+// the series (library cos); spherical with the 2-term series (cells up to 0.3 degree,
+// the common fine-grid case, with no branch on the length).
+enum : int { kFlat = 0, kSphTable = 1, kSphLib = 2, kSphTable2 = 3 };
+
+// Whether the cached 2D kernels keep the V coefficients in degrees of latitude per
+// second (divided by M at the reload), so that a stage's northward slope needs no
+// product: FP64 coefficients on the sphere.
+template <class R, int MET>
+constexpr bool v_in_degrees() { return sizeof(R) == 8 && MET != kFlat; }
+
 template <class R>
 __device__ inline void coeffs(const R f00, const R f10, const R f01, const R f11, R c[4])
 {
@@ -911,7 +924,7 @@ __device__ inline R poly(const R c[4], R xi, R eta)
     return fma(eta, fma(xi, c[3], c[2]), fma(xi, c[1], c[0]));
 }
 
-template <int ST, bool STEADY, int NL>
+template <int ST, bool STEADY, int MET, int NL>
 __device__ inline bool reload2(const AdvectParams &P, Cell2<typename Real<ST>::T, NL> &c, int sa,
                                int sb, double x, double y)
 {
@@ -928,8 +941,8 @@ __device__ inline bool reload2(const AdvectParams &P, Cell2<typename Real<ST>::T
     c.uy = (j == ay.n - 2) ? nextafter(ay.hi, __builtin_inf()) : ay.c[j + 1];
     c.ry = ay.rw[j];
     if (P.g.coslat) {
-        c.cl = P.g.coslat[j];
-        c.sl = P.g.sinlat[j];
+        c.cl = kMetresPerDegree * P.g.coslat[j];
+        c.sl = kMetresPerDegree * P.g.sinlat[j];
     }
     const size_t nx = (size_t)ax.n;
     c.land = P.g.landcell ? P.g.landcell[(size_t)j * (nx - 1) + (size_t)i] != 0 : false;
@@ -957,8 +970,9 @@ __device__ inline bool reload2(const AdvectParams &P, Cell2<typename Real<ST>::T
             coeffs<R>(p00[v], p10[v], p01[v], p11[v], ca);
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                c.coef(4 * v + q) = ca[q];
-                c.coef(8 + 4 * v + q) = cb[q] - ca[q];
+                const R w = v == 1 && v_in_degrees<R, MET>() ? (R)(1.0 / kMetresPerDegree) : (R)1;
+                c.coef(4 * v + q) = ca[q] * w;
+                c.coef(8 + 4 * v + q) = (cb[q] - ca[q]) * w;
             }
         }
     } else {
@@ -967,8 +981,10 @@ __device__ inline bool reload2(const AdvectParams &P, Cell2<typename Real<ST>::T
             R ca[4];
             coeffs<R>(p00[v], p10[v], p01[v], p11[v], ca);
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-                c.coef(4 * v + q) = ca[q];
+            for (int q = 0; q < 4; ++q) {
+                const R w = v == 1 && v_in_degrees<R, MET>() ? (R)(1.0 / kMetresPerDegree) : (R)1;
+                c.coef(4 * v + q) = ca[q] * w;
+            }
         }
     }
     return true;
@@ -1029,13 +1045,6 @@ __device__ inline double cos_series(double cl, double sl, double y0, double y, i
     return cl * cd - sl * sd;
 }
 
-// Metric modes of the cached kernels, fixed at compile time so that a launch carries
-// only the code it runs: flat mesh; spherical with the latitude tables and a series
-// whose length (3 or 4 terms) is read at run time; spherical with cells too tall for
-// the series (library cos); spherical with the 2-term series (cells up to 0.3 degree,
-// the common fine-grid case, with no branch on the length).
-enum : int { kFlat = 0, kSphTable = 1, kSphLib = 2, kSphTable2 = 3 };
-
 template <int MET>
 constexpr bool met_series() { return MET == kSphTable || MET == kSphTable2; }
 
@@ -1046,14 +1055,18 @@ __device__ inline double cos_series_m(double cl, double sl, double y0, double y,
     return cos_series(cl, sl, y0, y, MET == kSphTable2 ? 2 : P.g.cos_terms);
 }
 
+// Metres per degree of longitude at latitude y inside the cached cell, M cos(lat): the
+// cells keep M cos and M sin of their lower face, so the series gives the product.
 template <int MET, class R, int NL>
-__device__ inline double cos_lat(const Cell2<R, NL> &c, const AdvectParams &P, double y)
+__device__ inline double metres_lon(const Cell2<R, NL> &c, const AdvectParams &P, double y)
 {
     if constexpr (MET == kSphLib)
-        return cos(y * kDegToRad);
+        return kMetresPerDegree * cos(y * kDegToRad);
     else
         return cos_series_m<MET>(c.cl, c.sl, c.y0, y, P);
 }
+
+
 
 // 1 / (M cos(lat)) at the end point of a step, for the metric of the Brownian term: the
 // cached cell's series when the latitude is inside the cell's band (where the series
@@ -1062,7 +1075,7 @@ template <int MET, class CellT>
 __device__ inline double inv_metres_lon(const CellT &c, const AdvectParams &P, double y)
 {
     if (met_series<MET>() && y >= c.y0 && y < c.uy)
-        return recip(kMetresPerDegree * cos_series_m<MET>(c.cl, c.sl, c.y0, y, P));
+        return recip(cos_series_m<MET>(c.cl, c.sl, c.y0, y, P));
     return recip(kMetresPerDegree * cos_deg(y));
 }
 
@@ -1073,7 +1086,7 @@ __device__ inline bool stage2(const AdvectParams &P, Cell2<typename Real<ST>::T,
 {
     using R = typename Real<ST>::T;
     if (!in_cell(c, P, x, y) | fresh) {
-        if (!reload2<ST, STEADY, NL>(P, c, e.sa, e.sb, x, y))
+        if (!reload2<ST, STEADY, MET, NL>(P, c, e.sa, e.sb, x, y))
             return false;
     }
     const R xi = (R)((x - c.x0) * c.rx), eta = (R)((y - c.y0) * c.ry);
@@ -1088,8 +1101,8 @@ __device__ inline bool stage2(const AdvectParams &P, Cell2<typename Real<ST>::T,
         v = fma(tau, poly<R>(q + 12, xi, eta), v);
     }
     if constexpr (MET != kFlat) {
-        kx = (double)u * recip(kMetresPerDegree * cos_lat<MET>(c, P, y));
-        ky = (double)v * (1.0 / kMetresPerDegree);
+        kx = (double)u * recip(metres_lon<MET>(c, P, y));
+        ky = v_in_degrees<R, MET>() ? (double)v : (double)v * (1.0 / kMetresPerDegree);
     } else {
         kx = (double)u;
         ky = (double)v;
@@ -1123,8 +1136,11 @@ __device__ inline long long advect_lane_2d(const AdvectParams &P, uint32_t k, ui
                 const BracketMoves moves(P, s, e0, e1, e2);
                 uint8_t err = ST_OOB;
                 // the four stages: offsets 0, dt/2, dt/2, dt from X_n along the previous
-                // slope; weights 1, 2, 2, 1
+                // slope; weights 1, 2, 2, 1.  A stage whose point is off the grid leaves
+                // its slope as it was and the later stages run on (their loads stay in
+                // bounds: a reload only reads the cell it located); the step then fails.
                 double kx = 0.0, ky = 0.0, sx = 0.0, sy = 0.0;
+                bool ok = true;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     if (q > 0 && P.scheme)  // Euler forward: one stage
@@ -1135,8 +1151,7 @@ __device__ inline long long advect_lane_2d(const AdvectParams &P, uint32_t k, ui
                     const TimeEntry e = q == 0 ? e0 : (q == 3 ? e2 : e1);
                     const double h = q == 3 ? dt : P.hdt;  // (a scalar operand)
                     const double px = q == 0 ? x : x + kx * h, py = q == 0 ? y : y + ky * h;
-                    if (!stage2<ST, STEADY, MET, NL>(P, c, e, moves.at(q), px, py, kx, ky))
-                        goto fail;
+                    ok = stage2<ST, STEADY, MET, NL>(P, c, e, moves.at(q), px, py, kx, ky) & ok;
                     if (q == 0) {
                         sx = kx;
                         sy = ky;
@@ -1145,6 +1160,8 @@ __device__ inline long long advect_lane_2d(const AdvectParams &P, uint32_t k, ui
                         sy = fma(2.0, ky, sy);
                     }
                 }
+                if (!ok)
+                    goto fail;
                 {
                     double xs, ys;
                     if (P.scheme) {  // Euler forward
@@ -1549,15 +1566,16 @@ __device__ inline R *cache3_slot_ptr()
     return reinterpret_cast<R *>(cache_lds) + threadIdx.x * cache3_slot<R>();
 }
 
-// Whether the 3D kernel keeps the difference coefficients in LDS: only for FP64
-// coefficients (FP32 and FP64 fields), where the 48 VGPRs they free, with a 3-wave
-// target, lift the kernel from 2 to 3 waves per SIMD (LDS then allows exactly 3); not
-// with the Brownian term or the library cosine, whose extra state would spill inside
-// the stage loop, and not in the steady case (no differences).
+// Whether the 3D kernel keeps the difference coefficients in LDS.  FP64 coefficients
+// (FP32 and FP64 fields): the 48 VGPRs they free lift the kernel from 2 to 3 waves per
+// SIMD (LDS then allows exactly 3).  FP32 coefficients (BF16 and scaled FP16 fields):
+// the 24 VGPRs they free allow 4 waves (112 B per lane, 112 KB per CU).  Not with the
+// Brownian term or the library cosine, whose extra state would spill inside the stage
+// loop, and not in the steady case (no differences).
 template <int ST, bool STEADY, int MET, bool BROWN>
 constexpr bool cache3_lds()
 {
-    return !BROWN && !STEADY && MET != kSphLib && sizeof(typename Real<ST>::T) == 8;
+    return !BROWN && !STEADY && MET != kSphLib;
 }
 
 // The raw storage word of one 3D node and the value of variable v in it.
@@ -1597,8 +1615,8 @@ __device__ inline bool reload3(const AdvectParams &P, Cell3<typename Real<ST>::T
     c.uz = (k == az.n - 2) ? nextafter(az.hi, __builtin_inf()) : az.c[k + 1];
     c.rz = az.rw[k];
     if (P.g.coslat) {
-        c.cl = P.g.coslat[j];
-        c.sl = P.g.sinlat[j];
+        c.cl = kMetresPerDegree * P.g.coslat[j];
+        c.sl = kMetresPerDegree * P.g.sinlat[j];
     }
     const size_t nx = (size_t)ax.n, plane = nx * (size_t)ay.n;
     c.land = P.g.landcell ? P.g.landcell[(size_t)j * (nx - 1) + (size_t)i] != 0 : false;
@@ -1677,12 +1695,12 @@ __device__ inline bool stage3(const AdvectParams &P, Cell3<typename Real<ST>::T,
         }
     }
     if constexpr (MET != kFlat) {
-        double cosl;
+        double mlon;  // M cos(lat)
         if constexpr (MET == kSphLib)
-            cosl = cos(y * kDegToRad);
+            mlon = kMetresPerDegree * cos(y * kDegToRad);
         else
-            cosl = cos_series_m<MET>(c.cl, c.sl, c.y0, y, P);
-        k[0] = (double)v[0] * recip(kMetresPerDegree * cosl);
+            mlon = cos_series_m<MET>(c.cl, c.sl, c.y0, y, P);
+        k[0] = (double)v[0] * recip(mlon);
         k[1] = (double)v[1] * (1.0 / kMetresPerDegree);
     } else {
         k[0] = (double)v[0];
@@ -1694,10 +1712,11 @@ __device__ inline bool stage3(const AdvectParams &P, Cell3<typename Real<ST>::T,
 
 // With BEHAVE the worked example's kernels (sinking, age, tracer sample; Sect. 4.3) run
 // ahead of each step as in the gather kernel, with the same code, and the advection
-// keeps the depth of a dwelling particle.
+// keeps the depth of a dwelling particle.  Occupancy targets: 3 waves per SIMD with
+// FP64 coefficients in LDS, 4 with FP32 ones, else 2 (Brownian) or 1.
 template <int ST, bool STEADY, int MET, bool BROWN, bool BEHAVE>
 __global__ __launch_bounds__(kBlock)
-__attribute__((amdgpu_waves_per_eu(cache3_lds<ST, STEADY, MET, BROWN>() ? 3 : (BROWN ? 2 : 1)))) void k_advect3d(
+__attribute__((amdgpu_waves_per_eu(cache3_lds<ST, STEADY, MET, BROWN>() ? (sizeof(typename Real<ST>::T) == 8 ? 3 : 4) : (BROWN ? 2 : 1)))) void k_advect3d(
     AdvectParams P)
 {
     using R = typename Real<ST>::T;
@@ -1737,20 +1756,22 @@ __attribute__((amdgpu_waves_per_eu(cache3_lds<ST, STEADY, MET, BROWN>() ? 3 : (B
                 }
                 double k[3] = {0.0, 0.0, 0.0}, sm[3] = {0.0, 0.0, 0.0};
                 const int nst = P.scheme ? 1 : 4;
+                bool ok = true;  // as in 2D: a failed stage leaves its slope, the step fails
 #pragma nounroll
                 for (int q = 0; q < nst; ++q) {
                     const TimeEntry e = q == 0 ? e0 : (q == 3 ? e2 : e1);
                     // (stage 1 adds a zero slope, so its offset is immaterial; the
                     // half step comes in with the launch, as a scalar operand)
                     const double h = q == 3 ? dt : P.hdt;
-                    if (!stage3<ST, STEADY, MET, DL>(P, c, e, moves.at(q), x + k[0] * h, y + k[1] * h,
-                                                 z + k[2] * h, k))
-                        goto fail;
+                    ok = stage3<ST, STEADY, MET, DL>(P, c, e, moves.at(q), x + k[0] * h,
+                                                     y + k[1] * h, z + k[2] * h, k) & ok;
                     const double wq = q == 0 ? 1.0 : (q == 3 ? 0.0 : 2.0);
 #pragma unroll
                     for (int v = 0; v < 3; ++v)
                         sm[v] = fma(wq, k[v], sm[v]);
                 }
+                if (!ok)
+                    goto fail;
                 {
                     double xs, ys, zs;
                     if (P.scheme) {  // Euler forward
