@@ -392,9 +392,11 @@ __device__ inline uint8_t rk4_step(const AdvectParams &P, int s, uint32_t id, do
 {
     const TimeEntry e0 = P.tab[2 * s], e1 = P.tab[2 * s + 1], e2 = P.tab[2 * s + 2];
     const double dt = P.dt, hd = 0.5 * dt;
-    double k1[3], k2[3], k3[3], k4[3];
-    if (!sample<ST, IS3D, STEADY>(P, e0, x, y, z, k1))
-        return ST_OOB;
+    // a stage whose point is off the grid leaves its slope at zero and the later
+    // stages run on (a sample only reads the cell it located); the step then fails
+    double k1[3] = {0.0, 0.0, 0.0}, k2[3] = {0.0, 0.0, 0.0}, k3[3] = {0.0, 0.0, 0.0},
+           k4[3] = {0.0, 0.0, 0.0};
+    bool ok = sample<ST, IS3D, STEADY>(P, e0, x, y, z, k1);
     double xs, ys, zs = z;
     if (P.scheme) {  // Euler forward
         xs = x + k1[0] * dt;
@@ -402,20 +404,19 @@ __device__ inline uint8_t rk4_step(const AdvectParams &P, int s, uint32_t id, do
         if constexpr (IS3D)
             zs = z + k1[2] * dt;
     } else {
-        if (!sample<ST, IS3D, STEADY>(P, e1, x + k1[0] * hd, y + k1[1] * hd, z + k1[2] * hd,
-                                      k2))
-            return ST_OOB;
-        if (!sample<ST, IS3D, STEADY>(P, e1, x + k2[0] * hd, y + k2[1] * hd, z + k2[2] * hd,
-                                      k3))
-            return ST_OOB;
-        if (!sample<ST, IS3D, STEADY>(P, e2, x + k3[0] * dt, y + k3[1] * dt, z + k3[2] * dt,
-                                      k4))
-            return ST_OOB;
+        ok = sample<ST, IS3D, STEADY>(P, e1, x + k1[0] * hd, y + k1[1] * hd, z + k1[2] * hd,
+                                      k2) & ok;
+        ok = sample<ST, IS3D, STEADY>(P, e1, x + k2[0] * hd, y + k2[1] * hd, z + k2[2] * hd,
+                                      k3) & ok;
+        ok = sample<ST, IS3D, STEADY>(P, e2, x + k3[0] * dt, y + k3[1] * dt, z + k3[2] * dt,
+                                      k4) & ok;
         xs = x + ((((k1[0] + 2.0 * k2[0]) + 2.0 * k3[0]) + k4[0]) * dt) / 6.0;
         ys = y + ((((k1[1] + 2.0 * k2[1]) + 2.0 * k3[1]) + k4[1]) * dt) / 6.0;
         if constexpr (IS3D)
             zs = z + ((((k1[2] + 2.0 * k2[2]) + 2.0 * k3[2]) + k4[2]) * dt) / 6.0;
     }
+    if (!ok)
+        return ST_OOB;
     if constexpr (IS3D) {
         if (horizontal)  // a dwelling particle keeps its depth
             zs = z;
@@ -677,7 +678,8 @@ __device__ inline bool rkf45_attempt(const AdvectParams &P, double t, double h,
                                      const double p[3], double p4[3], double ev[3],
                                      LaneTime &lt)
 {
-    double k[6][3];
+    double k[6][3] = {};
+    bool ok = true;  // as in the RK4 step: a failed stage leaves a zero slope
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
         double q[3];
@@ -690,8 +692,7 @@ __device__ inline bool rkf45_attempt(const AdvectParams &P, double t, double h,
             q[d] = p[d] + h * s;
         }
         const TimeEntry te = bracket_lane(P, t + Fehlberg::c[i] * h, lt);
-        if (!sample<ST, IS3D, STEADY>(P, te, q[0], q[1], q[2], k[i]))
-            return false;
+        ok = sample<ST, IS3D, STEADY>(P, te, q[0], q[1], q[2], k[i]) & ok;
     }
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -708,7 +709,7 @@ __device__ inline bool rkf45_attempt(const AdvectParams &P, double t, double h,
         p4[2] = p[2];
         ev[2] = 0.0;
     }
-    return true;
+    return ok;
 }
 
 // The step control shared by both RKF45 lanes: an attempt whose error length is
