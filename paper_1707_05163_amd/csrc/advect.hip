@@ -1113,7 +1113,7 @@ __device__ inline bool stage2(const AdvectParams &P, Cell2<typename Real<ST>::T,
 
 // One particle (position k of the processing order) for all steps of the launch;
 // returns the number of steps it started active.
-template <int ST, bool STEADY, int MET, bool BROWN>
+template <int ST, bool STEADY, int MET, bool BROWN, uint32_t BS>
 __device__ inline long long advect_lane_2d(const AdvectParams &P, uint32_t k, uint32_t nact)
 {
     using R = typename Real<ST>::T;
@@ -1128,7 +1128,9 @@ __device__ inline long long advect_lane_2d(const AdvectParams &P, uint32_t k, ui
             c.clear();
             if constexpr (NL > 0) {
                 c.lc = cache_slot_ptr<R, NL>();
-                c.gs = cache_group_stride<R>();
+                // a block size known at compile time makes every group's offset an
+                // immediate of the LDS read
+                c.gs = BS ? BS * (16 / (uint32_t)sizeof(R)) : cache_group_stride<R>();
             }
             const double dt = P.dt, dt6 = P.dt6;
             for (int s = 0; s < P.nsteps; ++s) {
@@ -1224,7 +1226,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
 {
     const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
     const uint32_t k = blk * kBlock + threadIdx.x;
-    long long steps = advect_lane_2d<ST, STEADY, MET, BROWN>(P, k, *P.n_active);
+    long long steps = advect_lane_2d<ST, STEADY, MET, BROWN, kBlock>(P, k, *P.n_active);
     for (int off = 32; off > 0; off >>= 1)
         steps += __shfl_xor(steps, off, 64);
     if ((threadIdx.x & 63) == 0 && steps)
@@ -1497,7 +1499,7 @@ __attribute__((amdgpu_waves_per_eu(BROWN || MET == kSphLib ? 3 : 4))) void k_adv
         const int r = __builtin_amdgcn_readfirstlane(lo);
         const AdvectParams &P = runs[r];
         const uint32_t k = (it - cstart[r]) * blockDim.x + threadIdx.x;
-        long long steps = advect_lane_2d<ST, STEADY, MET, BROWN>(P, k, *P.n_active);
+        long long steps = advect_lane_2d<ST, STEADY, MET, BROWN, 0>(P, k, *P.n_active);
         for (int off = 32; off > 0; off >>= 1)
             steps += __shfl_xor(steps, off, 64);
         if ((threadIdx.x & 63) == 0 && steps)
