@@ -831,8 +831,9 @@ struct GatherLane {
 // earlier snapshot and for the difference (later - earlier).  A stage point in the
 // cached cell then costs only arithmetic: the stencil is reloaded when the point
 // leaves the cell or when the time bracket moves on.  The polynomial is the same
-// bilinear interpolant as the corner-weight form (Sect. 2.3), and f_a + tau (f_b -
-// f_a) is the same linear time interpolation (Sect. 2.4); only rounding differs.
+// bilinear interpolant as the corner-weight form (Sect. 2.3), and (1 - tau) f_a +
+// tau f_b, taken on the coefficients or on the values, is the linear time
+// interpolation (Sect. 2.4); only rounding differs.
 // NL of the 16 coefficients (the last NL) sit in the lane's LDS slot and the others
 // in registers: LDS frees registers, so more waves fit on a SIMD, at the cost of LDS
 // reads every stage; the split is chosen per kernel mode (cache_lds_coefs).
@@ -843,7 +844,7 @@ struct Cell2 {
                             // upper end needs no separate test)
     double rx, ry;          // inverse cell widths
     double cl, sl;          // cos and sin of the lower latitude face
-    // U, V coefficients of the earlier snapshot [0..7], later minus earlier [8..15]
+    // U, V coefficients of the earlier snapshot [0..7] and of the later one [8..15]
     R *lc;                  // LDS: this lane's first 16-byte group of coefficients
                             // 16 - NL .. 15 (see cache_slot_ptr)
     uint32_t gs;            // elements from one of the lane's groups to the next
@@ -973,7 +974,7 @@ __device__ inline bool reload2(const AdvectParams &P, Cell2<typename Real<ST>::T
             for (int q = 0; q < 4; ++q) {
                 const R w = v == 1 && v_in_degrees<R, MET>() ? (R)(1.0 / kMetresPerDegree) : (R)1;
                 c.coef(4 * v + q) = ca[q] * w;
-                c.coef(8 + 4 * v + q) = (cb[q] - ca[q]) * w;
+                c.coef(8 + 4 * v + q) = cb[q] * w;
             }
         }
     } else {
@@ -1080,6 +1081,36 @@ __device__ inline double inv_metres_lon(const CellT &c, const AdvectParams &P, d
     return recip(kMetresPerDegree * cos_deg(y));
 }
 
+// The U and V coefficients at a stage's time, (1 - tau) earlier + tau later: exactly the
+// earlier snapshot's at tau = 0 and the later one's at tau = 1, so a time that falls on a
+// snapshot gives the same coefficients whichever of its two brackets the table names.
+template <bool STEADY, class R, int NL>
+__device__ inline void coefs_at(const Cell2<R, NL> &c, double tau_d, R tc[8])
+{
+    const R tau = (R)tau_d, omt = (R)1 - tau;
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+        tc[i] = STEADY ? c.coef(i) : fma(tau, c.coef(8 + i), omt * c.coef(i));
+}
+
+// U and V at (xi, eta) and a stage's time from the two snapshots' values, with the
+// same endpoint property (fewer operations when the coefficients are not kept).
+template <bool STEADY, class R, int NL>
+__device__ inline void values_at(const Cell2<R, NL> &c, double tau_d, R xi, R eta, R &u, R &v)
+{
+    R q[16];
+#pragma unroll
+    for (int i = 0; i < (STEADY ? 8 : 16); ++i)
+        q[i] = c.coef(i);
+    u = poly<R>(q + 0, xi, eta);
+    v = poly<R>(q + 4, xi, eta);
+    if constexpr (!STEADY) {
+        const R tau = (R)tau_d, omt = (R)1 - tau;
+        u = fma(tau, poly<R>(q + 8, xi, eta), omt * u);
+        v = fma(tau, poly<R>(q + 12, xi, eta), omt * v);
+    }
+}
+
 template <int ST, bool STEADY, int MET, int NL>
 __device__ inline bool stage2(const AdvectParams &P, Cell2<typename Real<ST>::T, NL> &c,
                               const TimeEntry &e, bool fresh, double x, double y, double &kx,
@@ -1091,16 +1122,8 @@ __device__ inline bool stage2(const AdvectParams &P, Cell2<typename Real<ST>::T,
             return false;
     }
     const R xi = (R)((x - c.x0) * c.rx), eta = (R)((y - c.y0) * c.ry);
-    R q[16];
-#pragma unroll
-    for (int i = 0; i < (STEADY ? 8 : 16); ++i)
-        q[i] = c.coef(i);
-    R u = poly<R>(q + 0, xi, eta), v = poly<R>(q + 4, xi, eta);
-    if constexpr (!STEADY) {
-        const R tau = (R)e.tau;
-        u = fma(tau, poly<R>(q + 8, xi, eta), u);
-        v = fma(tau, poly<R>(q + 12, xi, eta), v);
-    }
+    R u, v;
+    values_at<STEADY>(c, e.tau, xi, eta, u, v);
     if constexpr (MET != kFlat) {
         kx = (double)u * recip(metres_lon<MET>(c, P, y));
         ky = v_in_degrees<R, MET>() ? (double)v : (double)v * (1.0 / kMetresPerDegree);
@@ -1109,6 +1132,41 @@ __device__ inline bool stage2(const AdvectParams &P, Cell2<typename Real<ST>::T,
         ky = (double)v;
     }
     return true;
+}
+
+// A stage of the cached RK4 lane on the coefficients at the stage's time, tc = (1 - tau)
+// earlier + tau later: U in tc[0..3], V in tc[4..7].  With keep, tc stands
+// from the stage before, whose time entry was the same, unless the point leaves the
+// cached cell (or the bracket moves), so such a stage reads no LDS.  A point off the
+// grid leaves the cell as it was and returns false.
+template <int ST, bool STEADY, int MET, int NL>
+__device__ inline bool stage2_tc(const AdvectParams &P, Cell2<typename Real<ST>::T, NL> &c,
+                                 const TimeEntry &e, bool fresh, bool keep, double x, double y,
+                                 typename Real<ST>::T tc[8], double &kx, double &ky)
+{
+    using R = typename Real<ST>::T;
+    bool ok = true;
+    const bool moved = !in_cell(c, P, x, y) | fresh;
+    if (moved)
+        ok = reload2<ST, STEADY, MET, NL>(P, c, e.sa, e.sb, x, y);
+    const R xi = (R)((x - c.x0) * c.rx), eta = (R)((y - c.y0) * c.ry);
+    R u, v;
+    if constexpr (NL == 0) {  // coefficients in registers: nothing is kept
+        values_at<STEADY>(c, e.tau, xi, eta, u, v);
+    } else {
+        if (moved | !keep)
+            coefs_at<STEADY>(c, e.tau, tc);
+        u = poly<R>(tc + 0, xi, eta);
+        v = poly<R>(tc + 4, xi, eta);
+    }
+    if constexpr (MET != kFlat) {
+        kx = (double)u * recip(metres_lon<MET>(c, P, y));
+        ky = v_in_degrees<R, MET>() ? (double)v : (double)v * (1.0 / kMetresPerDegree);
+    } else {
+        kx = (double)u;
+        ky = (double)v;
+    }
+    return ok;
 }
 
 // One particle (position k of the processing order) for all steps of the launch;
@@ -1132,6 +1190,7 @@ __device__ inline long long advect_lane_2d(const AdvectParams &P, uint32_t k, ui
                 // immediate of the LDS read
                 c.gs = BS ? BS * (16 / (uint32_t)sizeof(R)) : cache_group_stride<R>();
             }
+            R tc[8] = {};  // coefficients at the last stage's time
             const double dt = P.dt, dt6 = P.dt6;
             for (int s = 0; s < P.nsteps; ++s) {
                 ++steps;
@@ -1154,7 +1213,11 @@ __device__ inline long long advect_lane_2d(const AdvectParams &P, uint32_t k, ui
                     const TimeEntry e = q == 0 ? e0 : (q == 3 ? e2 : e1);
                     const double h = q == 3 ? dt : P.hdt;  // (a scalar operand)
                     const double px = q == 0 ? x : x + kx * h, py = q == 0 ? y : y + ky * h;
-                    ok = stage2<ST, STEADY, MET, NL>(P, c, e, moves.at(q), px, py, kx, ky) & ok;
+                    // stage 3 has stage 2's time entry; RK4's stage 1 has the previous
+                    // step's stage 4's (its bracket cannot have moved since)
+                    const bool keep = NL > 0 && (q == 2 || (true && q == 0 && !P.scheme));
+                    ok = stage2_tc<ST, STEADY, MET, NL>(P, c, e, moves.at(q), keep, px, py, tc,
+                                                        kx, ky) & ok;
                     if (q == 0) {
                         sx = kx;
                         sy = ky;
@@ -1216,12 +1279,13 @@ __device__ inline long long advect_lane_2d(const AdvectParams &P, uint32_t k, ui
     return steps;
 }
 
-// Occupancy targets: 5 waves per SIMD for the flat and 2-term spherical modes (their
-// registers and the 16-coefficient LDS cache both fit 5), 4 for the longer series, 3
-// with the Brownian term.
+// Occupancy targets: 4 waves per SIMD with the LDS cache (the 8 coefficients at the
+// stage time that the lane keeps between stages take the registers of a fifth wave;
+// the LDS saved, a quarter to a half of the reads, is worth more), 3 with the Brownian
+// term.
 template <int ST, bool STEADY, int MET, bool BROWN>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
-    BROWN ? 3 : (MET == kSphLib ? 1 : (MET == kSphTable ? 4 : 5))))) void k_advect2d(
+    BROWN ? 3 : (MET == kSphLib ? 1 : 4)))) void k_advect2d(
     AdvectParams P)
 {
     const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
