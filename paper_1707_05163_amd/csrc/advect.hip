@@ -862,9 +862,14 @@ struct Cell2 {
         x0 = __builtin_inf();
         ux = -__builtin_inf();
     }
+    // a fresh cell: every field defined (a stage whose point is off the grid still
+    // evaluates the cell it has, and discards the result)
     __device__ void clear()
     {
-        y0 = uy = 0.0;
+        y0 = uy = rx = ry = cl = sl = 0.0;
+        for (int i = 0; i < (NL < 16 ? 16 - NL : 1); ++i)
+            lr[i] = (R)0;
+        land = false;
         invalidate();
     }
 };
@@ -1594,7 +1599,8 @@ struct Cell3 {
     }
     __device__ void clear()
     {
-        y0 = uy = z0 = uz = 0.0;
+        y0 = uy = z0 = uz = rx = ry = rz = cl = sl = 0.0;
+        land = false;
         invalidate();
     }
 };
