@@ -57,11 +57,11 @@ STATE_BYTES_RKF45_2D = STATE_BYTES_2D + 2  # plus the step exponent read and wri
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 COUNTERS = {
     "advect_sha256": "f338af327caac6fa7390568f546b69096cc389316718d27546de293455fcb027",
-    "cfg1": (211055.0, 64638.3),   # (FETCH_SIZE KiB, WRITE_SIZE KiB) per launch of k_advect2d
-    "cfg2": (6390454.2, 1177473.5),  # the same for k_advect3d
+    "cfg1": (210366.6, 64621.5),   # (FETCH_SIZE KiB, WRITE_SIZE KiB) per launch of k_advect2d
+    "cfg2": (7886266.0, 483794.6),  # the same for k_advect3d
     # (TCC_HIT_sum, TCC_MISS_sum) per launch: L2 requests of the same kernels
-    "cfg1_l2": (4347333.9, 4968034.2),
-    "cfg2_l2": (28023035.7, 132581809.5),
+    "cfg1_l2": (4340222.8, 4954312.5),
+    "cfg2_l2": (93154042.7, 128760403.3),
 }
 
 
@@ -75,10 +75,10 @@ def parse():
     p.add_argument("--dtype", default="f32", choices=["f32", "bf16", "f16s"])
     p.add_argument("--output-stride", type=int, default=1)
     p.add_argument("--sort-every", type=int, default=None,
-                   help="re-sort by grid tile every k output segments (default: 10 for the "
-                        "cached RK4 kernel on cfg1, where the stencil cache makes the kernel "
-                        "almost indifferent to order and a sort costs 3%% of a segment; 1 "
-                        "elsewhere)")
+                   help="re-sort by grid tile every k output segments, 0 never (default: the "
+                        "measured best for the cached RK4 kernels, 10 on cfg1 and 0 on cfg2 and "
+                        "foram, whose 3D kernel runs faster on the generators' random order "
+                        "than on the tile order; 1 elsewhere)")
     p.add_argument("--cpu-baseline", type=int, default=1)
     p.add_argument("--cpu-sample-stride", type=int, default=10,
                    help="cfg1: the oracle's CPU timing follows every k-th particle for the "
@@ -106,12 +106,13 @@ def parse():
                    help="cfg2: oracle error report on ids = 0 mod this (0 = skip)")
     a = p.parse_args()
     if a.sort_every is None:
-        a.sort_every = (CFG1_SORT_EVERY if (a.config == "cfg1" and a.kernel == "rk4"
-                                            and a.stencil_cache != 0) else 1)
+        cached_rk4 = a.kernel == "rk4" and a.stencil_cache != 0
+        a.sort_every = SORT_EVERY.get(a.config, 1) if cached_rk4 else 1
     return a
 
 
-CFG1_SORT_EVERY = 10
+# default sort cadence of the cached RK4 runs (output segments between sorts, 0 never)
+SORT_EVERY = {"cfg1": 10, "cfg2": 0, "foram": 0}
 
 
 def cpu_baseline(w, stride: int):
@@ -254,7 +255,7 @@ def main_cfg2(a):
     half = a.dtype != "f32"
     bytes_per_step = (96 if half else 192) + 56.0 / S
     default = (a.particles == 1_000_000 and a.days == 30 and a.dtype == "f32"
-               and a.stencil_cache == 1 and a.sort_every == 1)
+               and a.stencil_cache == 1 and a.sort_every == SORT_EVERY["cfg2"])
     roof, other = roofline(spl, avg_launch_s, bytes_per_step, FLOPS_3D_STEP,
                            measured_traffic("cfg2", default))
     out = {
@@ -336,7 +337,7 @@ def main_foram(a):
     def step(ps, profile):
         ps.execute(runtime, w.dt, DAY_S, output_stride=1, sink_speed=m["sink_speed"],
                    dwell_depth=m["dwell_depth"], maxage=m["maxage"], sample=True,
-                   profile=profile, stream=stream)
+                   sort_every=a.sort_every, profile=profile, stream=stream)
 
     for i in range(a.warmup):
         step(psets[i], False)
@@ -649,7 +650,7 @@ def main():
     S = w.outputdt / w.dt
     bytes_per_step = STENCIL_BYTES_2D_F32 * (0.5 if a.dtype != "f32" else 1.0) + STATE_BYTES_2D / S
     default = (a.particles == 1_000_000 and a.days == 30 and a.dtype == "f32"
-               and a.stencil_cache == 1 and a.sort_every == CFG1_SORT_EVERY
+               and a.stencil_cache == 1 and a.sort_every == SORT_EVERY["cfg1"]
                and a.output_stride == 1 and a.kh == 0.0)
     roof, other = roofline(steps_per_launch, avg_launch_s, bytes_per_step, FLOPS_2D_STEP,
                            measured_traffic("cfg1", default))
