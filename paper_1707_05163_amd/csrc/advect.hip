@@ -1220,7 +1220,7 @@ __device__ inline long long advect_lane_2d(const AdvectParams &P, uint32_t k, ui
                     const double px = q == 0 ? x : x + kx * h, py = q == 0 ? y : y + ky * h;
                     // stage 3 has stage 2's time entry; RK4's stage 1 has the previous
                     // step's stage 4's (its bracket cannot have moved since)
-                    const bool keep = NL > 0 && (q == 2 || (true && q == 0 && !P.scheme));
+                    const bool keep = NL > 0 && (q == 2 || (q == 0 && !P.scheme));
                     ok = stage2_tc<ST, STEADY, MET, NL>(P, c, e, moves.at(q), keep, px, py, tc,
                                                         kx, ky) & ok;
                     if (q == 0) {
