@@ -227,13 +227,14 @@ int pset_execute_batch(lp_pset **ps, int32_t nruns, double runtime, double dt, d
 
 typedef struct {
     int32_t block, stencil_cache, sort_every; /* chosen launch shape */
-    double ms;                                /* kernel time of the winning trial */
+    double ms;                                /* device time of the winning trial */
 } lp_tune;
 
 /* Autotuner for pset_execute_batch: times every combination of block size (128,
  * 256, 512), stencil cache (on, off) and sorting (every segment, never) over
- * trial_steps steps of dt from the current state, restores the state after each
- * trial, and returns the fastest.  The choice is cached in the JSON file at
+ * trial_steps steps of dt from the current state (the whole trial segment on the
+ * device: its sort and preparation included, not the kernel alone), restores the
+ * state after each trial, and returns the fastest.  The choice is cached in the JSON file at
  * cache_path (NULL = no cache) under a key made of the storage type, mesh, run
  * count and the log2 of the mean grid size and of the particle count; a cached
  * entry is returned without trials.  Synchronises. */

@@ -1426,6 +1426,12 @@ extern "C" int pset_autotune_batch(lp_pset **ps, int32_t nruns, double dt, int32
     lp_tune b{};
     b.ms = 1e300;
     int rc = LP_OK;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess) {
+        if (t0) (void)hipEventDestroy(t0);
+        for (auto &sv : saved) free_state(sv);
+        return fail(LP_EDEVICE, "event creation failed");
+    }
     const int blocks[] = {128, 256, 512};
     for (int cache = 1; cache >= 0 && rc == LP_OK; --cache)
         for (int sort = 0; sort <= 1 && rc == LP_OK; ++sort)
@@ -1436,12 +1442,22 @@ extern "C" int pset_autotune_batch(lp_pset **ps, int32_t nruns, double dt, int32
                     x.output_stride = 0;
                     x.profile = 0;
                 }
-                double ms = 0.0;
-                // sorting before the trial counts: the trial is one segment
+                // the trial is one segment, timed whole on the device: the sort ahead of
+                // it (sort = 1) and the per-run preparation count, not the kernel alone
                 for (int r = 0; r < nruns; ++r)
                     ps[r]->segs_since_sort = sort ? 1 << 30 : 0;
+                float fms = 0.f;
+                if (hipEventRecord(t0, nullptr) != hipSuccess) {
+                    rc = fail(LP_EDEVICE, "event record failed");
+                    break;
+                }
                 rc = execute_batch(ps, nruns, trial_steps * dt, dt, 0.0, o.data(), nullptr, blk,
-                                   false, &ms);
+                                   false, nullptr);
+                if (rc == LP_OK && (hipEventRecord(t1, nullptr) != hipSuccess ||
+                                    hipEventSynchronize(t1) != hipSuccess ||
+                                    hipEventElapsedTime(&fms, t0, t1) != hipSuccess))
+                    rc = fail(LP_EDEVICE, "trial timing failed");
+                const double ms = fms;
                 for (int r = 0; r < nruns && rc == LP_OK; ++r)
                     rc = restore_state(ps[r], saved[r]);
                 if (rc)
@@ -1453,6 +1469,8 @@ extern "C" int pset_autotune_batch(lp_pset **ps, int32_t nruns, double dt, int32
                     b.sort_every = sort;
                 }
             }
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
     for (auto &s : saved)
         free_state(s);
     if (rc)
