@@ -44,3 +44,17 @@ def test_counter_record_only_for_the_default_workload():
     if bench.COUNTERS["advect_sha256"] == bench._advect_digest():
         c = bench.measured_counters("cfg1", True, 288e6)
         assert 0.0 < c["l2_hit_rate"] < 1.0 and c["hbm_bytes_per_launch"] > 0
+
+
+def test_sort_cadence_defaults(monkeypatch):
+    def parsed(*argv):
+        monkeypatch.setattr(sys, "argv", ["bench.py", *argv])
+        return bench.parse().sort_every
+    assert parsed() == bench.SORT_EVERY["cfg1"]
+    assert parsed("--config", "cfg2") == bench.SORT_EVERY["cfg2"]
+    assert parsed("--config", "foram") == bench.SORT_EVERY["foram"]
+    # the gather kernel and RKF45 sort every segment; an explicit value always wins
+    assert parsed("--stencil-cache", "0") == 1
+    assert parsed("--kernel", "rkf45") == 1
+    assert parsed("--config", "cfg3") == 1
+    assert parsed("--sort-every", "3") == 3
