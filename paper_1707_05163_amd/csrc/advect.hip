@@ -1365,6 +1365,7 @@ struct CachedLane2 {
         double k0x = 0.0, k0y = 0.0, k1x = 0.0, k1y = 0.0, k2x = 0.0, k2y = 0.0;
         double k3x = 0.0, k3y = 0.0, k4x = 0.0, k4y = 0.0;
         double s4x = 0.0, s4y = 0.0, sex = 0.0, sey = 0.0;
+        bool ok = true;  // as in the RK4 lane: a failed stage sets the flag, the loop runs on
 #pragma nounroll
         for (int q = 0; q < 6; ++q) {
             const double *a = kRkfA[q];
@@ -1376,13 +1377,9 @@ struct CachedLane2 {
                 csa = ent.sa;
                 csb = ent.sb;
             }
-            double kx, ky;
-            if (!stage2<ST, STEADY, MET, 16>(P, c, ent, false, x + hs * ax, y + hs * ay, kx,
-                                               ky)) {
-                ++acc;
-                s.st = (uint8_t)(ST_OOB | extra);
-                return true;
-            }
+            double kx = 0.0, ky = 0.0;
+            ok = stage2<ST, STEADY, MET, 16>(P, c, ent, false, x + hs * ax, y + hs * ay, kx,
+                                             ky) & ok;
             s4x = s4x + kRkfB4[q] * kx;
             s4y = s4y + kRkfB4[q] * ky;
             sex = sex + kRkfE[q] * kx;
@@ -1395,6 +1392,11 @@ struct CachedLane2 {
             case 4: k4x = kx; k4y = ky; break;
             default: break;
             }
+        }
+        if (!ok) {
+            ++acc;
+            s.st = (uint8_t)(ST_OOB | extra);
+            return true;
         }
         double ex = hs * sex, ey = hs * sey;
         if constexpr (MET != kFlat) {
