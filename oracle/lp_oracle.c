@@ -20,7 +20,7 @@
  *   - the alternative integrators named in Sect. 2.1.1: Euler forward and the
  *     adaptive Runge-Kutta-Fehlberg pair RKF45 (Fehlberg, NASA TR R-315, 1969),
  *     with the step-size control read below;
- *   - the custom kernels of the worked example (Sect. 4.3): sinking, age with
+ *   - the custom kernels of the worked example (Sect. 3.3): sinking, age with
  *     deletion at a maximum age, and sampling of a tracer (temperature), run
  *     before the advection of each step.
  *
@@ -395,7 +395,9 @@ static void rk4_step(const or_fieldset *fs, const or_options *opt, double t_org,
     if (opt->Kh > 0.0) {
         double nn[2];
         or_normals(opt->run_id, opt->seed, pid, (uint32_t)n, nn);
-        double sig = sqrt(2.0 * opt->Kh * dt);
+        /* sigma = sqrt(2 Kh dt) with dt a duration (Sect. 4.2.7): |dt| when running
+         * backward in time */
+        double sig = sqrt(2.0 * opt->Kh * fabs(dt));
         double dx = sig * nn[0], dy = sig * nn[1];
         if (fs->spherical) {
             dx = dx / (OR_M * cos(ys * OR_D));

@@ -381,7 +381,7 @@ __device__ inline void brownian_metres(const AdvectParams &P, uint32_t id, int64
     double n1, n2;
     box_muller(unit53(w[0], w[1]), unit53(w[2], w[3]), n1, n2,
                LOOP_LOADS ? kBmCoef + (P.zero & (uint32_t)step) : kBmCoef);
-    const double sig = sqrt(2.0 * P.Kh * dt);
+    const double sig = sqrt(2.0 * P.Kh * fabs(dt));
     dx = sig * n1;
     dy = sig * n2;
 }
@@ -1785,7 +1785,7 @@ __device__ inline bool stage3(const AdvectParams &P, Cell3<typename Real<ST>::T,
     return true;
 }
 
-// With BEHAVE the worked example's kernels (sinking, age, tracer sample; Sect. 4.3) run
+// With BEHAVE the worked example's kernels (sinking, age, tracer sample; Sect. 3.3) run
 // ahead of each step as in the gather kernel, with the same code, and the advection
 // keeps the depth of a dwelling particle.  Occupancy targets: 3 waves per SIMD with
 // FP64 coefficients in LDS, 4 with FP32 ones, else 2 (Brownian) or 1.
