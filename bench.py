@@ -1,16 +1,23 @@
 #!/usr/bin/env python3
 """Benchmark of the RK4 advection hot path on one MI355X.
 
-Workload (default): 2D time-varying eddy field on the global 0.25 degree grid
-(1440 x 720), 30 daily float32 U, V snapshots (periodic, 30% land), 1,000,000
-particles seeded in ocean cells, RK4 with dt = 300 s for 30 days (8640 steps),
-daily output records of every particle, delete on leaving the grid or landing.
-One benchmark step is that whole 30-day run (sort, advection, compaction and
-records), with the field snapshots and start positions already in HBM.
+Workload (default): the 3D field on the global 0.1 degree grid with 50 stretched
+depth levels (3600 x 1800 x 50), 11 daily float32 U, V, W snapshots built in HBM
+and streamed through a three-slot ring (two resident, one being converted: the
+paper's execute-one-day-then-advancetime loop), 10,000,000 particles, RK4_3D with
+dt = 600 s for 10 days (1440 steps), daily records of every 100th particle.  One
+benchmark step is that whole 10-day run (snapshot pushes, advection, compaction
+and records) with the source snapshots and start positions already in HBM.
 
 Prints one JSON line: particle-steps/s, the roofline of the dominant kernel
-(measured with HIP events on the launch stream) and the FP64 oracle timed on the
-host cores on a bounded sample of the same workload.
+(algorithmic FP64 flops per launch over the launch time measured with HIP events
+on the launch stream, against the FP64 vector peak; with the stencil cache the
+kernel is bound by instruction issue, not by HBM), the algorithmic-byte rate and
+reuse factor beside it, the counted HBM bytes and VALU issue rate from the
+recorded rocprofv3 counters while the kernel source matches them, the error in km
+of each output time against the FP64 oracle, and the FP64 oracle timed on the
+host cores (all cores and one) on a bounded sample of the same workload.
+Other workloads: --config cfg1 | cfg3 | cfg4 | foram.
 """
 
 from __future__ import annotations
@@ -29,6 +36,10 @@ sys.path.insert(0, ROOT)
 DAY_S = 86400.0
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector (FMA = 2 flops)
+# Vector instruction issue: 256 CUs x 4 SIMDs, each issuing one wave64 VALU
+# instruction every 4 cycles at 2.4 GHz (a wave64 FP64 FMA is 128 flops, so this is
+# the FP64 peak counted in instructions: 78.6e12 / 128).
+VALU_ISSUE_PEAK = 1024 * 2.4e9 / 4.0
 
 # Algorithmic cost of one 2D spherical RK4 particle-step with linear time
 # interpolation (see the design notes): bytes of the four-corner stencil of U, V
@@ -47,14 +58,16 @@ FLOPS_RKF45_ATTEMPT_2D = 448
 STENCIL_BYTES_RKF45_2D_F32 = 6 * 64
 STATE_BYTES_RKF45_2D = STATE_BYTES_2D + 2  # plus the step exponent read and written
 
-# HBM traffic of the dominant kernel, from two rocprofv3 --pmc passes (FETCH_SIZE,
-# then WRITE_SIZE, KiB per dispatch) over each mode's default workload.  FETCH_SIZE
-# counts half the bytes that a conversion kernel of known size reads, so it is
-# scaled by 2.0; WRITE_SIZE matches a fill of known size (factor 1.0).  The figures
-# belong to the kernel source they were taken on: `traffic` turns null as soon as
-# the digest of advect.hip's code (comments and whitespace dropped) differs from the
-# one recorded here.
+# Counter record of the dominant kernel, from rocprofv3 --pmc passes (one counter set
+# per run) over each mode's default workload: FETCH_SIZE and WRITE_SIZE in KiB per
+# dispatch (FETCH_SIZE counts half the bytes that a conversion kernel of known size
+# reads, so it is scaled by 2.0; WRITE_SIZE matches a fill of known size, factor 1.0),
+# the L2 hits and misses, and the wave-level VALU and SALU instruction counts.  The
+# figures belong to the kernel source they were taken on: they are reported only
+# while the digest of advect.hip's code (comments and whitespace dropped) equals the
+# one recorded here, and come from the summary named in COUNTER_SOURCE.
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
+COUNTER_SOURCE = "profiles/counters_k_advect2d_cfg1_k_advect3d_cfg2.md"
 COUNTERS = {
     "advect_sha256": "c6eacb9e4bbbe86380a4a7327d32e7ce36b1016a9da6bf2e0aa4f3e9dcc91347",
     "cfg1": (212085.3, 64644.6),   # (FETCH_SIZE KiB, WRITE_SIZE KiB) per launch of k_advect2d
@@ -62,6 +75,9 @@ COUNTERS = {
     # (TCC_HIT_sum, TCC_MISS_sum) per launch: L2 requests of the same kernels
     "cfg1_l2": (4336449.5, 4988771.5),
     "cfg2_l2": (93123076.4, 128761846.2),
+    # (SQ_INSTS_VALU, SQ_INSTS_SALU) wave instructions per launch
+    "cfg1_sq": (9.381e8, 5.457e8),
+    "cfg2_sq": (9.751e9, 7.314e9),
 }
 
 
@@ -70,8 +86,14 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=3)
     p.add_argument("--warmup", type=int, default=1)
-    p.add_argument("--particles", type=int, default=1_000_000)
-    p.add_argument("--days", type=int, default=30)
+    p.add_argument("--config", default="cfg2",
+                   choices=["cfg1", "cfg2", "cfg3", "cfg4", "foram"],
+                   help="workload (default cfg2: 3D, 10M particles, 3600x1800x50, 10 days)")
+    p.add_argument("--particles", type=int, default=None,
+                   help="particle count (default: the workload's own: cfg1 1M, cfg2 10M, "
+                        "cfg4 4M, foram 1M)")
+    p.add_argument("--days", type=int, default=None,
+                   help="simulated days (default: cfg1 30, cfg2 10, cfg4 30)")
     p.add_argument("--dtype", default="f32", choices=["f32", "bf16", "f16s"])
     p.add_argument("--output-stride", type=int, default=1)
     p.add_argument("--sort-every", type=int, default=None,
@@ -83,8 +105,9 @@ def parse():
     p.add_argument("--cpu-sample-stride", type=int, default=10,
                    help="cfg1: the oracle's CPU timing follows every k-th particle for the "
                         "whole run (about 10 s on 16 cores at k = 10)")
-    p.add_argument("--config", default="cfg1",
-                   choices=["cfg1", "cfg2", "cfg3", "cfg4", "foram"])
+    p.add_argument("--cpu-1thread-stride", type=int, default=16,
+                   help="the one-thread oracle timing follows every k-th particle of the "
+                        "all-core sample")
     p.add_argument("--train-segments", type=int, default=50_000_000)
     p.add_argument("--train-iters", type=int, default=12_000)
     p.add_argument("--residual-m", default="50",
@@ -103,7 +126,11 @@ def parse():
                    help="first copy this many GB device-to-device (a plain copy kernel of "
                         "known size, to scale hardware byte counters)")
     p.add_argument("--error-stride", type=int, default=100,
-                   help="cfg2: oracle error report on ids = 0 mod this (0 = skip)")
+                   help="cfg2: records and the oracle's error report on ids = 0 mod this "
+                        "(0 = no records, no error report)")
+    p.add_argument("--host-stream", type=int, default=0,
+                   help="cfg2: 1 = push every snapshot from pinned host memory (PCIe) "
+                        "instead of from HBM, and report the end-to-end rate")
     a = p.parse_args()
     if a.sort_every is None:
         cached_rk4 = a.kernel == "rk4" and a.stencil_cache != 0
@@ -115,21 +142,47 @@ def parse():
 SORT_EVERY = {"cfg1": 10, "cfg2": 0, "foram": 0}
 
 
-def cpu_baseline(w, stride: int):
-    """The FP64 oracle, as it stands, on every `stride`-th particle of the same
-    workload for the full run, on all host cores."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def time_oracle(fs, w, ids, nsteps, threads):
+    """The FP64 oracle, as it stands, advancing the particles `ids` of workload w by
+    nsteps steps on `threads` host threads; returns (particle-steps, seconds, state)."""
     from oracle import oracle as O
-    ids = np.arange(0, w.n, stride)
-    ofs = O.OracleFieldSet.from_workload(w)
-    st = O.make_state(w.lon0[ids], w.lat0[ids], pid=ids.astype(np.uint32))
-    threads = O.max_threads()
+    z = None if w.depth0 is None else w.depth0[ids]
+    st = O.make_state(w.lon0[ids], w.lat0[ids], z, pid=ids.astype(np.uint32), t_org=w.t0)
     t = time.perf_counter()
-    rc = O.advance(ofs, st, w.dt, w.nsteps, nthreads=threads)
+    rc = O.advance(fs, st, w.dt, nsteps, nthreads=threads)
     el = time.perf_counter() - t
     assert rc == 0
-    return dict(value=st.psteps / el, unit="particle-steps/s", cores=threads, kind="oracle",
-                sample=f"every {stride}th particle ({ids.size}) for the full {w.nsteps} steps, "
-                       f"{st.psteps} particle-steps in {el:.2f} s")
+    return st.psteps, el, st
+
+
+def cpu_baseline(w, stride: int, stride1: int, nsteps=None, fs=None):
+    """The FP64 oracle on every `stride`-th particle of the workload for the whole run
+    on all host cores, and on every (stride * stride1)-th particle on one core."""
+    from oracle import oracle as O
+    fs = fs or O.OracleFieldSet.from_workload(w)
+    nsteps = w.nsteps if nsteps is None else nsteps
+    threads = O.max_threads()
+    ids = np.arange(0, w.n, stride)
+    ps_all, el_all, _ = time_oracle(fs, w, ids, nsteps, threads)
+    ids1 = np.arange(0, w.n, stride * stride1)
+    ps_1, el_1, _ = time_oracle(fs, w, ids1, nsteps, 1)
+    return dict(value=ps_all / el_all, unit="particle-steps/s", cores=threads, kind="oracle",
+                sample=f"every {stride}th particle ({ids.size}) for the full {nsteps} steps: "
+                       f"{ps_all} particle-steps in {el_all:.2f} s on {threads} threads; one "
+                       f"thread: every {stride * stride1}th particle ({ids1.size}), {ps_1} "
+                       f"particle-steps in {el_1:.2f} s",
+                value_1thread=ps_1 / el_1, cpu_model=cpu_model(), nproc=os.cpu_count())
 
 
 def _advect_digest():
@@ -145,45 +198,66 @@ def _advect_digest():
     return hashlib.sha256(code.encode()).hexdigest()
 
 
+def _counters_valid(mode, default_workload):
+    return (default_workload and mode in COUNTERS
+            and COUNTERS["advect_sha256"] == _advect_digest())
+
+
 def measured_traffic(mode, default_workload):
     """HBM bytes per launch of the dominant kernel from the recorded counter passes,
     or None (other workload, or the kernel source changed since they were taken)."""
-    c = COUNTERS.get(mode)
-    if not default_workload or c is None or COUNTERS["advect_sha256"] != _advect_digest():
+    if not _counters_valid(mode, default_workload):
         return None
-    fetch_kib, write_kib = c
+    fetch_kib, write_kib = COUNTERS[mode]
     return (fetch_kib * FETCH_SCALE + write_kib * WRITE_SCALE) * 1024.0
 
 
-def measured_counters(mode, default_workload, steps_per_launch):
-    """The counter record of the dominant kernel (HBM bytes per launch, L2 hit rate and
-    L2 requests per particle-step), or None as for measured_traffic."""
+def measured_counters(mode, default_workload, steps_per_launch, avg_launch_s):
+    """The counter record of the dominant kernel (HBM bytes per launch, L2 hit rate, L2
+    requests per particle-step, VALU and SALU issue against the issue peak, the
+    latter over the live launch time), or None as for measured_traffic."""
     t = measured_traffic(mode, default_workload)
     l2 = COUNTERS.get(mode + "_l2")
-    if t is None or l2 is None:
+    sq = COUNTERS.get(mode + "_sq")
+    if t is None or l2 is None or sq is None:
         return None
     hit, miss = l2
-    return {"hbm_bytes_per_launch": round(t), "l2_hit_rate": round(hit / (hit + miss), 4),
+    valu, salu = sq
+    return {"source": COUNTER_SOURCE, "hbm_bytes_per_launch": round(t),
+            "hbm_frac": round(t / avg_launch_s / 1e9 / HBM_PEAK_GBS, 4),
+            "l2_hit_rate": round(hit / (hit + miss), 4),
             "l2_requests_per_particle_step": round((hit + miss) / steps_per_launch, 5),
-            "source": "profiles/counters_k_advect2d_cfg1_k_advect3d_cfg2.md"}
+            "valu_per_particle_step": round(valu * 64 / steps_per_launch, 1),
+            "salu_per_particle_step": round(salu * 64 / steps_per_launch, 1),
+            "valu_issue_frac": round(valu / avg_launch_s / VALU_ISSUE_PEAK, 4),
+            "salu_issue_frac": round(salu / avg_launch_s / VALU_ISSUE_PEAK, 4)}
 
 
 def roofline(steps_per_launch, avg_launch_s, bytes_per_step, flops_per_step,
              traffic_bytes=None):
-    """Roofline of the dominant kernel.  `achieved` is the method's algorithmic bytes
-    (or flops) per launch over the HIP-event launch time; `traffic` is the counted
-    HBM bytes per launch over the same time, in GB/s, when counters are on record."""
+    """Roofline of the dominant kernel and the algorithmic-byte figures beside it.
+
+    `roofline`: the method's algorithmic FP64 flops per launch over the HIP-event
+    launch time, against the FP64 vector peak ("alu": with the per-lane stencil cache
+    the kernels are bound by instruction issue and latency, not by HBM); `traffic`
+    is the counted HBM bytes per launch over the same time, in GB/s, when a counter
+    record matches the source.  `alg_bytes`: the method's stencil and state bytes per
+    launch over the launch time against the HBM peak; above 1 it counts reuse of one
+    stencil across many steps, which `reuse_factor` (algorithmic over counted bytes)
+    states."""
     hbm_ach = steps_per_launch * bytes_per_step / avg_launch_s / 1e9
     alu_ach = steps_per_launch * flops_per_step / avg_launch_s / 1e12
     traffic = None if traffic_bytes is None else round(traffic_bytes / avg_launch_s / 1e9, 2)
-    hbm = {"bound": "hbm", "achieved": round(hbm_ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": round(hbm_ach / HBM_PEAK_GBS, 4), "traffic": traffic}
-    alu = {"bound": "alu", "achieved": round(alu_ach, 3), "peak": FP64_VECTOR_PEAK_TFLOPS,
-           "unit": "TFLOP/s", "frac": round(alu_ach / FP64_VECTOR_PEAK_TFLOPS, 4),
-           "traffic": None}
-    # The path's roofline is defined on the method's algorithmic bytes per particle-step
-    # (its stencil and particle state) against HBM; the FP64 figure rides along.
-    return hbm, alu
+    roof = {"bound": "alu", "achieved": round(alu_ach, 3), "peak": FP64_VECTOR_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(alu_ach / FP64_VECTOR_PEAK_TFLOPS, 4),
+            "traffic": traffic, "traffic_unit": "GB/s (counted HBM bytes, counter record)",
+            "flops_per_particle_step": flops_per_step}
+    alg = {"achieved": round(hbm_ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "alg_bytes_frac": round(hbm_ach / HBM_PEAK_GBS, 4),
+           "bytes_per_particle_step": round(bytes_per_step, 3),
+           "reuse_factor": None if traffic_bytes is None else
+           round(steps_per_launch * bytes_per_step / traffic_bytes, 2)}
+    return roof, alg
 
 
 def great_circle_km(lon1, lat1, lon2, lat2):
@@ -195,21 +269,28 @@ def great_circle_km(lon1, lat1, lon2, lat2):
 
 
 def main_cfg2(a):
-    """3D: 10M particles on 3600 x 1800 x 50, 11 daily snapshots built in HBM and
-    streamed through a three-slot ring (two resident, one being converted), the
-    paper's execute-one-day-then-advancetime loop."""
+    """3D: 10M particles on 3600 x 1800 x 50, 11 daily snapshots built in HBM (or, with
+    --host-stream 1, held in host memory and pushed over PCIe) and streamed through a
+    three-slot ring (two resident, one being converted), the paper's
+    execute-one-day-then-advancetime loop (Sect. 3.1, Sect. 3.4)."""
     import torch
     from paper_1707_05163_amd import FieldSet, ParticleSet
     from synthetic import configs as SC
 
     torch.cuda.set_device(0)
-    w = SC.cfg2_global_3d(n_particles=a.particles if a.particles != 1_000_000 else 10_000_000)
-    days = min(a.days, w.fields.nt - 1)
+    n = a.particles if a.particles is not None else 10_000_000
+    w = SC.cfg2_global_3d(n_particles=n)
+    days = min(a.days if a.days is not None else 10, w.fields.nt - 1)
+    host = bool(a.host_stream)
     print(f"[bench] workload {w.name}: {w.n} particles x {days * 144} steps, "
-          f"{w.fields.nt} snapshots, building fields in HBM", file=sys.stderr, flush=True)
+          f"{w.fields.nt} snapshots, building fields in {'host memory' if host else 'HBM'}",
+          file=sys.stderr, flush=True)
     cache = {}
     snaps = [SC.cfg2_snapshot_torch(w, s, "cuda", cache) for s in range(w.fields.nt)]
     del cache
+    if host:  # the same values, held in (pageable) host memory
+        snaps = [tuple(x.cpu().numpy() for x in sn) for sn in snaps]
+        torch.cuda.empty_cache()
     lon0 = torch.from_numpy(w.lon0).cuda()
     lat0 = torch.from_numpy(w.lat0).cuda()
     dep0 = torch.from_numpy(w.depth0).cuda()
@@ -254,60 +335,78 @@ def main_cfg2(a):
     S = 144
     half = a.dtype != "f32"
     bytes_per_step = (96 if half else 192) + 56.0 / S
-    default = (a.particles == 1_000_000 and a.days == 30 and a.dtype == "f32"
-               and a.stencil_cache == 1 and a.sort_every == SORT_EVERY["cfg2"])
-    roof, other = roofline(spl, avg_launch_s, bytes_per_step, FLOPS_3D_STEP,
-                           measured_traffic("cfg2", default))
+    default = (n == 10_000_000 and days == 10 and a.dtype == "f32" and not host
+               and a.stencil_cache == 1 and a.sort_every == SORT_EVERY["cfg2"]
+               and a.error_stride == 100)
+    roof, alg = roofline(spl, avg_launch_s, bytes_per_step, FLOPS_3D_STEP,
+                         measured_traffic("cfg2", default))
     out = {
         "metric": "RK4 particle-steps/s", "value": rate, "unit": "particle-steps/s",
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": total / a.steps * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64" if a.dtype == "f32" else "f64+" + a.dtype,
         "data": "synthetic",
-        "config": {"workload": w.name, "grid": "3600x1800x50", "snapshots": w.fields.nt,
-                   "ring_slots": 3, "particles": w.n, "rk4_steps": days * 144, "dt_s": w.dt,
-                   "field_dtype": a.dtype, "stencil_cache": a.stencil_cache,
-                   "sort_every": a.sort_every},
-        "roofline": roof, "roofline_other": other,
-        "counters": measured_counters("cfg2", default, spl),
+        "config": {"workload": f"cfg2_3d_3600x1800x50_{w.n}_fp32_fields_fp64_positions"
+                   if a.dtype == "f32" else f"cfg2_3d_3600x1800x50_{w.n}_{a.dtype}_fields",
+                   "grid": "3600x1800x50", "snapshots": w.fields.nt, "ring_slots": 3,
+                   "snapshot_source": "host (PCIe)" if host else "HBM",
+                   "particles": w.n, "rk4_steps": days * 144, "dt_s": w.dt,
+                   "field_dtype": a.dtype, "positions": "f64",
+                   "stencil_cache": a.stencil_cache, "sort_every": a.sort_every,
+                   "record_stride": stride},
+        "roofline": roof, "alg_bytes": alg,
+        "counters": measured_counters("cfg2", default, spl, avg_launch_s),
         "kernel": {"name": "k_advect3d" if a.stencil_cache else "k_advect", "launches": launches,
                    "avg_launch_ms": round(avg_launch_s * 1e3, 4),
                    "particle_steps_per_launch": spl,
-                   "kernel_share_of_step": round(kms / 1e3 / total, 4)},
+                   "kernel_share_of_step": round(kms / 1e3 / total, 4),
+                   "kernel_only_particle_steps_per_s": spl / avg_launch_s},
     }
     if stride:
-        # error in km against the FP64 oracle on the unquantised float32 fields
+        # error in km against the FP64 oracle on the unquantised float32 fields, at
+        # every output time, on the recorded subset ids = 0 mod stride
         from oracle import oracle as O
         print("[bench] oracle on the error subset", file=sys.stderr, flush=True)
         recs = last[0].records()
         ids = np.arange(0, w.n, stride)
-        shape = (days + 1,) + tuple(snaps[0][0].shape)
+        shape = (days + 1,) + tuple(np.shape(snaps[0][0]))
         U, V, W = (np.empty(shape, np.float32) for _ in range(3))
         for q in range(days + 1):
-            U[q] = snaps[q][0].cpu().numpy()
-            V[q] = snaps[q][1].cpu().numpy()
-            W[q] = snaps[q][2].cpu().numpy()
+            for arr, v in ((U, 0), (V, 1), (W, 2)):
+                x = snaps[q][v]
+                arr[q] = x if isinstance(x, np.ndarray) else x.cpu().numpy()
         ofs = O.OracleFieldSet(w.grid.lon, w.grid.lat, w.grid.depth, w.fields.times[: days + 1],
                                U, V, W, spherical=True)
         st = O.make_state(w.lon0[ids], w.lat0[ids], w.depth0[ids], pid=ids.astype(np.uint32))
+        threads = O.max_threads()
         t = time.perf_counter()
-        rc = O.advance(ofs, st, w.dt, days * 144, nthreads=O.max_threads())
+        orecs = O.run(ofs, st, w.dt, days * 86400.0, 86400.0, nthreads=threads)
         ot = time.perf_counter() - t
-        assert rc == 0
-        g_lon, g_lat = recs["lon"][-1], recs["lat"][-1]
-        both = (st.status == 0) & (recs["status"][-1] == 0)
-        km = great_circle_km(g_lon[both], g_lat[both], st.x[both], st.y[both])
+        per_day = []
+        for m, o in enumerate(orecs):
+            both = (o["status"] == 0) & (recs["status"][m] == 0)
+            km = great_circle_km(recs["lon"][m][both], recs["lat"][m][both], o["lon"][both],
+                                 o["lat"][both])
+            dz = np.abs(recs["depth"][m][both] - o["depth"][both])
+            per_day.append({"day": m, "median": float(np.median(km)),
+                            "p95": float(np.percentile(km, 95)), "max": float(km.max()),
+                            "depth_max_m": float(dz.max()),
+                            "status_mismatch": int((o["status"] != recs["status"][m]).sum())})
+        fin = per_day[-1]
         out["error_km_vs_fp64_oracle"] = {
-            "subset": f"ids = 0 mod {stride} ({ids.size})", "compared": int(both.sum()),
-            "status_mismatch": int((st.status != recs["status"][-1]).sum()),
-            "median": float(np.median(km)), "p95": float(np.percentile(km, 95)),
-            "max": float(km.max()), "depth_max_m": float(np.abs(recs["depth"][-1][both] - st.z[both]).max())}
+            "subset": f"ids = 0 mod {stride} ({ids.size})", "median": fin["median"],
+            "p95": fin["p95"], "max": fin["max"], "depth_max_m": fin["depth_max_m"],
+            "status_mismatch": fin["status_mismatch"], "per_output_time": per_day}
         if a.cpu_baseline:
-            out["cpu_baseline"] = dict(value=st.psteps / ot, unit="particle-steps/s",
-                                       cores=O.max_threads(), kind="oracle",
-                                       sample=f"ids = 0 mod {stride} ({ids.size}) for "
-                                              f"{days * 144} steps: {st.psteps} particle-steps "
-                                              f"in {ot:.2f} s")
+            ids1 = ids[:: a.cpu_1thread_stride]
+            ps1, el1, _ = time_oracle(ofs, w, ids1, days * 144, 1)
+            out["cpu_baseline"] = dict(
+                value=st.psteps / ot, unit="particle-steps/s", cores=threads, kind="oracle",
+                sample=f"ids = 0 mod {stride} ({ids.size}) for {days * 144} steps: "
+                       f"{st.psteps} particle-steps in {ot:.2f} s on {threads} threads; one "
+                       f"thread: ids = 0 mod {stride * a.cpu_1thread_stride} ({ids1.size}), "
+                       f"{ps1} particle-steps in {el1:.2f} s",
+                value_1thread=ps1 / el1, cpu_model=cpu_model(), nproc=os.cpu_count())
     print(json.dumps(out), flush=True)
 
 
@@ -321,7 +420,7 @@ def main_foram(a):
     from synthetic import configs as SC
 
     torch.cuda.set_device(0)
-    n = a.particles if a.particles != 1_000_000 else 1_000_000
+    n = a.particles if a.particles is not None else 1_000_000
     w = SC.foram_footprint(n_particles=n)
     m = w.meta
     print(f"[bench] foram: {w.n} particles x {w.nsteps} steps backward, "
@@ -360,7 +459,7 @@ def main_foram(a):
     # per step: the 3D RK4 stencil (192 B) plus the tracer's trilinear stencil at two
     # snapshots (8 x 2 x 4 B) and the state (position, temp, age, status) per record
     bytes_per_step = 192 + 64 + 72.0 / (DAY_S / abs(w.dt))
-    roof, other = roofline(spl, avg_launch_s, bytes_per_step, FLOPS_3D_STEP + 40)
+    roof, alg = roofline(spl, avg_launch_s, bytes_per_step, FLOPS_3D_STEP + 40)
     out = {
         "metric": "RK4 particle-steps/s", "value": psteps / el, "unit": "particle-steps/s",
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": el / a.steps * 1e3,
@@ -369,7 +468,7 @@ def main_foram(a):
         "config": {"workload": w.name, "grid": f"{w.grid.nx}x{w.grid.ny}x{w.grid.nz}",
                    "snapshots": w.fields.nt, "particles": w.n, "days": 42, "dt_s": w.dt,
                    "kernels": "sink+age+sample+RK4_3D", "maxage_days": 30},
-        "roofline": roof, "roofline_other": other,
+        "roofline": roof, "alg_bytes": alg,
         "kernel": {"name": "k_advect3d (stencil cache, with the worked-example kernels)",
                    "launches": launches, "avg_launch_ms": round(avg_launch_s * 1e3, 4),
                    "particle_steps_per_launch": spl,
@@ -439,8 +538,8 @@ def main_cfg3(a):
     rate = psteps / total
     avg_launch_s = kms / 1e3 / launches
     spl = psteps / launches
-    roof, other = roofline(spl, avg_launch_s, STENCIL_BYTES_2D_F32 + STATE_BYTES_2D / 288.0,
-                           FLOPS_2D_STEP + FLOPS_BROWNIAN)
+    roof, alg = roofline(spl, avg_launch_s, STENCIL_BYTES_2D_F32 + STATE_BYTES_2D / 288.0,
+                         FLOPS_2D_STEP + FLOPS_BROWNIAN)
     out = {
         "metric": "RK4 particle-steps/s", "value": rate, "unit": "particle-steps/s",
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
@@ -449,7 +548,7 @@ def main_cfg3(a):
         "config": {"workload": "cfg3_ensemble_64_runs", "runs": len(ws), "particles": ntot,
                    "rk4_steps": ws[0].nsteps, "dt_s": ws[0].dt, "Kh": ws[0].Kh,
                    "autotuned": best, "autotune_s": round(tune_s, 3)},
-        "roofline": roof, "roofline_other": other,
+        "roofline": roof, "alg_bytes": alg,
         "kernel": {"name": "k_advect2d_batch", "launches": launches,
                    "avg_launch_ms": round(avg_launch_s * 1e3, 4),
                    "particle_steps_per_launch": spl},
@@ -470,13 +569,14 @@ def main_cfg4(a):
     from oracle import oracle as O
 
     torch.cuda.set_device(0)
-    n = a.particles if a.particles != 1_000_000 else 4_000_000
+    n = a.particles if a.particles is not None else 4_000_000
     w = SC.cfg4_surrogate_field(n_particles=n)
     fs = FieldSet.from_workload(w)
     lon0 = torch.from_numpy(w.lon0).cuda()
     lat0 = torch.from_numpy(w.lat0).cuda()
     stream = torch.cuda.current_stream()
-    runtime = a.days * 86400.0
+    days = a.days if a.days is not None else 30
+    runtime = days * 86400.0
     print(f"[bench] cfg4: training on {a.train_segments} segments, {a.train_iters} steps",
           file=sys.stderr, flush=True)
     model = Surrogate(seed=1)
@@ -526,7 +626,7 @@ def main_cfg4(a):
         "value": fine_s / surr[0][2], "unit": "x", "n_gpus": 1, "steps": 1, "warmup": 0,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "bf16-mfma+f64", "data": "synthetic",
-        "config": {"workload": w.name, "particles": n, "days": a.days, "segment_steps": 24,
+        "config": {"workload": w.name, "particles": n, "days": days, "segment_steps": 24,
                    "dt_s": w.dt, "residual_m": thresholds},
         "times_s": dict({"fine_rk4": fine_s, "coarse_rk4": coarse_s},
                         **{f"surrogate_{thr:g}m": s_ for thr, _, s_, _ in surr}),
@@ -547,7 +647,7 @@ def report_rkf45(a, w, el, psteps, retried, kms, launches, psets):
     attempts = psteps + retried
     per_launch = attempts / launches
     bytes_per_attempt = STENCIL_BYTES_RKF45_2D_F32 + STATE_BYTES_RKF45_2D * w.n / per_launch
-    roof, other = roofline(per_launch, avg_launch_s, bytes_per_attempt, FLOPS_RKF45_ATTEMPT_2D)
+    roof, alg = roofline(per_launch, avg_launch_s, bytes_per_attempt, FLOPS_RKF45_ATTEMPT_2D)
     ex = np.concatenate([p.step_exponents() for p in psets])
     days = w.nsteps * w.dt / 86400.0
     out = {
@@ -560,7 +660,7 @@ def report_rkf45(a, w, el, psteps, retried, kms, launches, psets):
                    "base_dt_s": w.dt, "tol_m": a.rkf_tol, "exp_range": [a.rkf_min_exp,
                                                                           a.rkf_max_exp],
                    "stencil_cache": a.stencil_cache},
-        "roofline": roof, "roofline_other": other,
+        "roofline": roof, "alg_bytes": alg,
         "kernel": {"name": "k_rkf45_2d" if a.stencil_cache else "k_rkf45",
                    "launches": launches, "avg_launch_ms": round(avg_launch_s * 1e3, 4),
                    "attempts_per_launch": per_launch,
@@ -604,8 +704,10 @@ def main():
     from synthetic import configs as SC
 
     torch.cuda.set_device(0)
-    nsteps = a.days * 288
-    w = SC.cfg1_global_eddies(n_particles=a.particles, nsteps=nsteps)
+    days = a.days if a.days is not None else 30
+    n = a.particles if a.particles is not None else 1_000_000
+    nsteps = days * 288
+    w = SC.cfg1_global_eddies(n_particles=n, nsteps=nsteps)
     print(f"[bench] workload {w.name}: {w.n} particles x {w.nsteps} steps, "
           f"{w.fields.nt} snapshots {w.grid.nx}x{w.grid.ny}", file=sys.stderr, flush=True)
     fs = FieldSet.from_workload(w, dtype=a.dtype)
@@ -649,11 +751,11 @@ def main():
     steps_per_launch = psteps / launches
     S = w.outputdt / w.dt
     bytes_per_step = STENCIL_BYTES_2D_F32 * (0.5 if a.dtype != "f32" else 1.0) + STATE_BYTES_2D / S
-    default = (a.particles == 1_000_000 and a.days == 30 and a.dtype == "f32"
+    default = (n == 1_000_000 and days == 30 and a.dtype == "f32"
                and a.stencil_cache == 1 and a.sort_every == SORT_EVERY["cfg1"]
                and a.output_stride == 1 and a.kh == 0.0)
-    roof, other = roofline(steps_per_launch, avg_launch_s, bytes_per_step, FLOPS_2D_STEP,
-                           measured_traffic("cfg1", default))
+    roof, alg = roofline(steps_per_launch, avg_launch_s, bytes_per_step, FLOPS_2D_STEP,
+                         measured_traffic("cfg1", default))
     out = {
         "metric": "RK4 particle-steps/s",
         "value": rate,
@@ -672,8 +774,8 @@ def main():
                    "field_dtype": a.dtype, "output_stride": a.output_stride,
                    "sort_every": a.sort_every, "Kh": a.kh},
         "roofline": roof,
-        "roofline_other": other,
-        "counters": measured_counters("cfg1", default, steps_per_launch),
+        "alg_bytes": alg,
+        "counters": measured_counters("cfg1", default, steps_per_launch, avg_launch_s),
         "kernel": {"name": "k_advect2d" if a.stencil_cache else "k_advect", "launches": launches,
                    "avg_launch_ms": round(avg_launch_s * 1e3, 4),
                    "particle_steps_per_launch": steps_per_launch,
@@ -681,7 +783,7 @@ def main():
     }
     if a.cpu_baseline:
         print("[bench] timing the FP64 oracle on the host", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(w, a.cpu_sample_stride)
+        out["cpu_baseline"] = cpu_baseline(w, a.cpu_sample_stride, a.cpu_1thread_stride)
     print(json.dumps(out), flush=True)
 
 

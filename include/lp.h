@@ -114,9 +114,9 @@ int fieldset_push_snapshot_f64(lp_fieldset *fs, double t, const double *U, const
 /* Same with float arrays already in device memory (no host copy). */
 int fieldset_push_snapshot_device(lp_fieldset *fs, double t, const float *dU, const float *dV,
                                   const float *dW, void *stream);
-/* A scalar tracer (the temperature of the worked example, Sect. 4.3) for the
- * resident snapshot at time t: a host float array laid out like U ([max(nz,1)][ny]
- * [nx]), interpolated like the velocity.  The tracer belongs to that snapshot: when
+/* A scalar tracer (the temperature of the worked example, Sect. 3.1 and
+ * Sect. 3.3) for the resident snapshot at time t: a host float array laid out like
+ * U ([max(nz,1)][ny][nx]), interpolated like the velocity.  The tracer belongs to that snapshot: when
  * a later push takes its slot, the slot has no tracer until this is called again.
  * LP_ESTATE if no resident snapshot has time t.  Synchronises the upload. */
 int fieldset_push_tracer(lp_fieldset *fs, double t, const float *T, void *stream);
@@ -147,8 +147,10 @@ int pset_create_device(lp_fieldset *fs, int64_t n, const double *dlon, const dou
 typedef struct {
     int32_t kernel;       /* LP_KERNEL_RK4, LP_KERNEL_EULER or LP_KERNEL_RKF45 */
     int32_t recovery;     /* LP_DELETE or LP_FREEZE */
-    double Kh;            /* > 0: add a Brownian displacement sqrt(2 Kh dt) N(0,1)
-                             per horizontal component after each step (Sect. 4.2.7) */
+    double Kh;            /* > 0: add a Brownian displacement sqrt(2 Kh |dt|) N(0,1)
+                             metres per horizontal component after each step's RK4
+                             end point X* (Sect. 4.2.7); on a spherical mesh the
+                             metres become degrees with the metric at lat(X*) */
     uint32_t run_id, seed;/* Philox4x32-10 key (run_id, seed); counter (id, step) */
     int32_t output_stride;/* record every k-th particle id at each output time;
                              0 = no records */
@@ -176,7 +178,7 @@ typedef struct {
     double rkf_tol;       /* > 0, metres per step */
     int32_t rkf_min_exp;  /* in [-30, 0]; |dt| 2^min must still move the clock */
     int32_t rkf_max_exp;  /* in [0, 30] */
-    /* The worked example's custom kernels (Sect. 4.3), run in this order before
+    /* The worked example's custom kernels (Sect. 3.3), run in this order before
      * the advection of each step (the paper prints their code only as figures;
      * this is the library's reading).  Sinking (3D, sink_speed > 0): a particle
      * deeper than dwell_depth moves by sink_speed * dt, not past dwell_depth (so a
@@ -241,9 +243,16 @@ typedef struct {
 int pset_autotune_batch(lp_pset **ps, int32_t nruns, double dt, int32_t trial_steps,
                         const lp_exec_opts *opts, const char *cache_path, lp_tune *best);
 
-/* Counts (and, if status != NULL, the n status bytes in id order).  Syncs. */
+/* The particles' error states (Sect. 2.1.2: an error type such as out-of-bounds,
+ * mapped to a recovery action; the worked example deletes particles that leave
+ * the domain, Sect. 3.4): counts of active, out-of-bounds, land and deleted
+ * particles, the particle-steps taken and the set's time and step, and, if
+ * status != NULL, the n status bytes (LP_ST_* bits) in id order.  Synchronises
+ * the stream of the last execute. */
 int pset_status(lp_pset *ps, lp_counts *c, uint8_t *status);
-/* Positions and cell indices (-1 outside the grid) in id order; any output
+/* The particles' state variables lon, lat (and depth) (Sect. 2.1.2: particle.lon,
+ * particle.lat; Sect. 3.2) and the grid cell of each position (-1 outside the
+ * grid), in id order whatever order the device processed them in; any output
  * pointer may be NULL.  Synchronises. */
 int pset_get(lp_pset *ps, double *lon, double *lat, double *depth, int32_t *ci, int32_t *cj,
              int32_t *ck);
@@ -256,8 +265,11 @@ int pset_get_behaviour(lp_pset *ps, double *temp, double *age);
 int pset_records_behaviour(lp_pset *ps, double *temp, double *age);
 /* The n RKF45 step exponents e (step |dt| 2^e) in id order.  Synchronises. */
 int pset_get_step_exponents(lp_pset *ps, int8_t *e);
-/* Output records: *nrec records of *nper = ceil(n / output_stride) particles
- * (ids 0, k, 2k, ...), record-major.  Call with NULL arrays to get the sizes.
+/* Output records, taken at every output interval of an execute (Sect. 2.2 and
+ * Sect. 3.4: the execute call's output interval; Sect. 3.5: positions stored on
+ * the fly, one long vector per variable): *nrec records of *nper =
+ * ceil(n / output_stride) particles (ids 0, k, 2k, ...), record-major, each with
+ * position, status and cell indices.  Call with NULL arrays to get the sizes.
  * Synchronises. */
 int pset_records(lp_pset *ps, int64_t *nrec, int64_t *nper, double *lon, double *lat,
                  double *depth, uint8_t *status, int32_t *ci, int32_t *cj, int32_t *ck);

@@ -1039,9 +1039,14 @@ int exec_segment_post(lp_pset *ps, ExecPlan &plan, size_t k, hipStream_t stream)
 int exec_finish(lp_pset *ps, ExecPlan &plan, hipStream_t stream)
 {
     lp_fieldset *fs = ps->fs;
+    // release[s] must cover every reader of slot s, also readers on other streams
+    // (two particle sets may share one field set): chain the earlier readers in
+    // before recording, so that a push waits for all of them
     for (int s = 0; s < fs->capacity; ++s)
-        if (plan.used[s])
+        if (plan.used[s]) {
+            HIPCHECK(hipStreamWaitEvent(stream, fs->release[s], 0));
             HIPCHECK(hipEventRecord(fs->release[s], stream));
+        }
     HIPCHECK(hipMemcpyAsync(ps->hcount, ps->dcount + ps->cur, sizeof(uint32_t),
                             hipMemcpyDeviceToHost, stream));
     HIPCHECK(hipEventRecord(ps->count_ev, stream));

@@ -39,18 +39,39 @@ def test_kernel_digest_ignores_comments_but_not_code(tmp_path, monkeypatch):
 
 def test_counter_record_only_for_the_default_workload():
     assert bench.measured_traffic("cfg1", False) is None
-    assert bench.measured_counters("cfg1", False, 288e6) is None
+    assert bench.measured_counters("cfg1", False, 288e6, 2e-3) is None
     assert bench.measured_traffic("cfg3", True) is None
     if bench.COUNTERS["advect_sha256"] == bench._advect_digest():
-        c = bench.measured_counters("cfg1", True, 288e6)
+        c = bench.measured_counters("cfg2", True, 1.44e9, 30e-3)
         assert 0.0 < c["l2_hit_rate"] < 1.0 and c["hbm_bytes_per_launch"] > 0
+        assert 0.0 < c["valu_issue_frac"] < 1.0 and c["source"].startswith("profiles/")
+
+
+def test_default_workload_is_the_3d_ten_million_particle_run(monkeypatch):
+    monkeypatch.setattr(sys, "argv", ["bench.py"])
+    a = bench.parse()
+    assert a.config == "cfg2" and a.dtype == "f32" and a.particles is None
+    assert a.days is None and a.error_stride == 100 and a.host_stream == 0
+
+
+def test_roofline_fields_recompute():
+    spl, t = 1.44e9, 28e-3
+    roof, alg = bench.roofline(spl, t, 192 + 56 / 144, bench.FLOPS_3D_STEP, 16.6e9)
+    assert roof["bound"] == "alu" and roof["unit"] == "TFLOP/s"
+    assert abs(roof["achieved"] - spl * bench.FLOPS_3D_STEP / t / 1e12) < 1e-3
+    assert abs(roof["frac"] - roof["achieved"] / 78.6) < 1e-4
+    assert abs(roof["traffic"] - 16.6e9 / t / 1e9) < 0.01
+    assert abs(alg["alg_bytes_frac"] - spl * (192 + 56 / 144) / t / 8e12) < 1e-4
+    assert abs(alg["reuse_factor"] - spl * (192 + 56 / 144) / 16.6e9) < 0.01
+    assert abs(bench.VALU_ISSUE_PEAK * 128 - 78.6e12) / 78.6e12 < 1e-3
 
 
 def test_sort_cadence_defaults(monkeypatch):
     def parsed(*argv):
         monkeypatch.setattr(sys, "argv", ["bench.py", *argv])
         return bench.parse().sort_every
-    assert parsed() == bench.SORT_EVERY["cfg1"]
+    assert parsed() == bench.SORT_EVERY["cfg2"]
+    assert parsed("--config", "cfg1") == bench.SORT_EVERY["cfg1"]
     assert parsed("--config", "cfg2") == bench.SORT_EVERY["cfg2"]
     assert parsed("--config", "foram") == bench.SORT_EVERY["foram"]
     # the gather kernel and RKF45 sort every segment; an explicit value always wins

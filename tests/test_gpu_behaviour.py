@@ -1,4 +1,4 @@
-"""The worked example's kernels (Sect. 4.3: sinking, age with deletion at maxage,
+"""The worked example's kernels (Sect. 3.3: sinking, age with deletion at maxage,
 tracer sampling) on the GPU against the FP64 oracle, on the synthetic stand-in
 for the foraminifera experiment run backward in time."""
 

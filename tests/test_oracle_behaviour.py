@@ -1,4 +1,4 @@
-"""Pins of the oracle's worked-example kernels (Sect. 4.3): sinking at a fixed
+"""Pins of the oracle's worked-example kernels (Sect. 3.3): sinking at a fixed
 speed to (or, backward in time, back up to) the dwelling depth, age with deletion
 at the maximum age, and sampling of a tracer at the particle, run before the RK4
 advection of each step.  Checked against closed forms on fields whose answers are
