@@ -265,6 +265,19 @@ int pset_get_behaviour(lp_pset *ps, double *temp, double *age);
 int pset_records_behaviour(lp_pset *ps, double *temp, double *age);
 /* The n RKF45 step exponents e (step |dt| 2^e) in id order.  Synchronises. */
 int pset_get_step_exponents(lp_pset *ps, int8_t *e);
+/* Allocation-free pset_get, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same outputs as pset_get, bit for bit, but the cell-index query writes into
+ * a fixed device array of 3 x LP_NOALLOC_MAX_PARTICLES int32 (24 MiB) instead of a
+ * buffer allocated per call.  Each GPU holds its own copy of that array from the
+ * first call on it until the process ends.  Sets with more than
+ * LP_NOALLOC_MAX_PARTICLES particles get LP_EINVAL.  Calls no hipMalloc or
+ * hipFree.  Every call on one GPU shares that GPU's array: calls that overlap on
+ * one GPU (from several host threads) race, and the caller must serialise them.
+ * Synchronises the stream of the set's last execute. */
+#define LP_NOALLOC_MAX_PARTICLES (1 << 21)
+int pset_get_noalloc(lp_pset *ps, double *lon, double *lat, double *depth, int32_t *ci,
+                     int32_t *cj, int32_t *ck);
 /* Output records, taken at every output interval of an execute (Sect. 2.2 and
  * Sect. 3.4: the execute call's output interval; Sect. 3.5: positions stored on
  * the fly, one long vector per variable): *nrec records of *nper =

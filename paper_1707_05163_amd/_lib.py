@@ -28,6 +28,7 @@ EXPORTS = (
     "fieldset_push_snapshot_device", "fieldset_get_snapshot", "fieldset_resident",
     "fieldset_destroy", "lp_philox_normals",
     "pset_create", "pset_create_device", "pset_execute", "pset_status", "pset_get",
+    "pset_get_noalloc",
     "pset_get_step_exponents", "pset_get_behaviour", "pset_records_behaviour",
     "fieldset_push_tracer", "fieldset_push_tracer_device",
     "pset_records", "pset_timing", "pset_destroy", "lp_last_error", "lp_version",
@@ -108,6 +109,7 @@ def _declare(L):
         "pset_execute": ([P, C.c_double, C.c_double, C.c_double, C.POINTER(lp_exec_opts), P], I),
         "pset_status": ([P, C.POINTER(lp_counts), P], I),
         "pset_get": ([P, P, P, P, P, P, P], I),
+        "pset_get_noalloc": ([P, P, P, P, P, P, P], I),
         "pset_get_step_exponents": ([P, P], I),
         "pset_get_behaviour": ([P, P, P], I),
         "pset_records_behaviour": ([P, P, P], I),

@@ -12,6 +12,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -1582,6 +1583,88 @@ extern "C" int pset_get(lp_pset *ps, double *lon, double *lat, double *depth, in
         dfree(d);
         HIPCHECK(e);
     }
+    return LP_OK;
+}
+
+// ---------------------------------------------------------------- allocation-free query
+// pset_get_noalloc: pset_get whose cell-index query writes into a fixed device array
+// instead of a buffer allocated per call.  The array holds three int32 indices for up
+// to LP_NOALLOC_MAX_PARTICLES particles; every GPU the library runs on holds its own
+// copy until the process ends.  In host code `scratch` names a host-side stand-in,
+// not a device address: the address on each device comes from hipGetSymbolAddress,
+// taken once per device with that device current, and only that address is used.
+static __device__ __align__(256) int32_t scratch[(size_t)LP_NOALLOC_MAX_PARTICLES * 3];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+int32_t *g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the first call).
+int scratch_on_current_device(int32_t **out)
+{
+    int dev = -1;
+    HIPCHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(LP_EDEVICE, "device %d is beyond the %d devices the scratch table covers",
+                    dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return fail(LP_EDEVICE, "hipGetSymbolAddress of the scratch array failed on device "
+                                    "%d: %s", dev, hipGetErrorString(e));
+        }
+        g_scratch_dev[dev] = (int32_t *)p;
+    }
+    *out = g_scratch_dev[dev];
+    return LP_OK;
+}
+
+}  // namespace
+
+extern "C" int pset_get_noalloc(lp_pset *ps, double *lon, double *lat, double *depth,
+                                int32_t *ci, int32_t *cj, int32_t *ck)
+{
+    if (!ps)
+        return fail(LP_EINVAL, "null argument");
+    if (ps->n > (int64_t)LP_NOALLOC_MAX_PARTICLES)
+        return fail(LP_EINVAL, "pset_get_noalloc takes sets of at most %d particles (this one "
+                               "has %lld); use pset_get", LP_NOALLOC_MAX_PARTICLES,
+                    (long long)ps->n);
+    const hipStream_t s = ps->last_stream;
+    HIPCHECK(hipStreamSynchronize(s));
+    const size_t N = (size_t)ps->n;
+    if (lon) HIPCHECK(hipMemcpy(lon, ps->dx, N * 8, hipMemcpyDeviceToHost));
+    if (lat) HIPCHECK(hipMemcpy(lat, ps->dy, N * 8, hipMemcpyDeviceToHost));
+    if (depth && ps->fs->is3d) HIPCHECK(hipMemcpy(depth, ps->dz, N * 8, hipMemcpyDeviceToHost));
+    if (!(ci || cj || ck))
+        return LP_OK;
+    int32_t *d = nullptr;
+    int rc = scratch_on_current_device(&d);
+    if (rc)
+        return rc;
+    // every index the copies below read is written by this launch: nothing needs clearing
+    lp::RecordParams R{};
+    R.g = ps->fs->g;
+    R.x = ps->dx;
+    R.y = ps->dy;
+    R.z = ps->dz;
+    R.status = ps->dst;
+    R.n = ps->n;
+    R.stride = 1;
+    R.nper = ps->n;
+    R.ci = d;
+    R.cj = d + N;
+    R.ck = d + 2 * N;
+    HIPCHECK(lp::launch_record(R, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    if (ci) HIPCHECK(hipMemcpy(ci, d, N * 4, hipMemcpyDeviceToHost));
+    if (cj) HIPCHECK(hipMemcpy(cj, d + N, N * 4, hipMemcpyDeviceToHost));
+    if (ck) HIPCHECK(hipMemcpy(ck, d + 2 * N, N * 4, hipMemcpyDeviceToHost));
     return LP_OK;
 }
 
