@@ -103,15 +103,21 @@ int fieldset_create(const lp_grid_desc *g, lp_fieldset **out);
  * nz >= 2) are host float arrays [max(nz,1)][ny][nx], i fastest, in m/s (W
  * positive downward).  Times must increase from push to push.  When all slots
  * are full the oldest snapshot is replaced, after the kernels that read it have
- * finished.  The upload and the conversion to the storage type run on the
- * field set's own upload stream; a later pset_execute waits for them.  The
- * host arrays may be reused when the call returns. */
+ * finished.  The arrays go to the device through two pinned staging chunks of
+ * the library's (up to 256 MiB each, allocated at the first push): host threads
+ * fill one chunk while the other is copied to the device on the field set's own
+ * upload stream, which then converts the snapshot to the storage type.  The call
+ * returns once the last chunk is queued, without waiting for the device copies;
+ * a later pset_execute waits for them.  The host arrays may be reused when the
+ * call returns.  LP_ENOMEM if the pinned staging cannot be allocated. */
 int fieldset_push_snapshot(lp_fieldset *fs, double t, const float *U, const float *V,
                            const float *W, void *stream);
 /* Same with double host arrays (LP_F64 storage keeps them exact). */
 int fieldset_push_snapshot_f64(lp_fieldset *fs, double t, const double *U, const double *V,
                                const double *W, void *stream);
-/* Same with float arrays already in device memory (no host copy). */
+/* Same with float arrays already in device memory (no host copy).  Work the
+ * caller queues on `stream` after this call runs after the arrays have been read,
+ * so they may then be freed or overwritten in stream order. */
 int fieldset_push_snapshot_device(lp_fieldset *fs, double t, const float *dU, const float *dV,
                                   const float *dW, void *stream);
 /* A scalar tracer (the temperature of the worked example, Sect. 3.1 and

@@ -14,6 +14,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <utility>
 #include <vector>
 
@@ -278,6 +279,12 @@ extern "C" void fieldset_destroy(lp_fieldset *fs)
     dfree(fs->dtmp);
     dfree(fs->dstage);
     dfree(fs->dstage64);
+    if (fs->hpin)
+        (void)hipHostFree(fs->hpin);
+    for (auto e : fs->pin_ev)
+        if (e) (void)hipEventDestroy(e);
+    if (fs->src_done)
+        (void)hipEventDestroy(fs->src_done);
     for (auto e : fs->ready)
         if (e) (void)hipEventDestroy(e);
     for (auto e : fs->release)
@@ -286,6 +293,74 @@ extern "C" void fieldset_destroy(lp_fieldset *fs)
         (void)hipStreamDestroy(fs->up);
     delete fs;
 }
+
+namespace {
+
+constexpr size_t kPinChunk = (size_t)256 << 20;  // bytes per pinned staging chunk
+
+// memcpy on several host threads (large copies only; one thread below 32 MiB)
+void parallel_copy(char *dst, const char *src, size_t len)
+{
+    const size_t per = (size_t)16 << 20;
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const size_t nt = std::min<size_t>(std::min<size_t>(8, hw), std::max<size_t>(1, len / per));
+    if (nt <= 1) {
+        std::memcpy(dst, src, len);
+        return;
+    }
+    std::vector<std::thread> th;
+    const size_t step = (len + nt - 1) / nt;
+    for (size_t t = 1; t < nt; ++t) {
+        const size_t a = t * step, b = std::min(len, a + step);
+        if (a < b)
+            th.emplace_back([=] { std::memcpy(dst + a, src + a, b - a); });
+    }
+    std::memcpy(dst, src, std::min(len, step));
+    for (auto &x : th)
+        x.join();
+}
+
+// Host arrays src[0..nvar) of `bytes` each into consecutive device staging at dst, on
+// the field set's upload stream, through two pinned chunks: a chunk is refilled by
+// the host only after its previous host-to-device copy has finished, so the host
+// copy of one chunk overlaps the DMA of the other.  Returns once the last chunk is
+// queued; the host arrays are not read after that, the DMAs run on.
+int upload_from_host(lp_fieldset *fs, const void *const *src, int nvar, size_t bytes, char *dst)
+{
+    if (!fs->hpin) {
+        const size_t chunk = std::min(kPinChunk, (bytes + 4095) & ~(size_t)4095);
+        if (hipHostMalloc((void **)&fs->hpin, 2 * chunk, hipHostMallocDefault) != hipSuccess) {
+            fs->hpin = nullptr;
+            (void)hipGetLastError();
+            return fail(LP_ENOMEM, "pinned staging of %zu bytes failed", 2 * chunk);
+        }
+        fs->pin_chunk = chunk;
+        for (auto &e : fs->pin_ev)
+            if (!e)
+                HIPCHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
+    const size_t chunk = fs->pin_chunk;
+    int k = fs->pin_next;
+    for (int q = 0; q < nvar; ++q)
+        for (size_t off = 0; off < bytes; off += chunk) {
+            const size_t len = std::min(chunk, bytes - off);
+            if (fs->pin_pending[k]) {  // its previous DMA must have read the chunk
+                HIPCHECK(hipEventSynchronize(fs->pin_ev[k]));
+                fs->pin_pending[k] = false;
+            }
+            char *buf = fs->hpin + (size_t)k * chunk;
+            parallel_copy(buf, (const char *)src[q] + off, len);
+            HIPCHECK(hipMemcpyAsync(dst + (size_t)q * bytes + off, buf, len,
+                                    hipMemcpyHostToDevice, fs->up));
+            HIPCHECK(hipEventRecord(fs->pin_ev[k], fs->up));
+            fs->pin_pending[k] = true;
+            k ^= 1;
+        }
+    fs->pin_next = k;
+    return LP_OK;
+}
+
+}  // namespace
 
 static int push_common(lp_fieldset *fs, double t, const void *U, const void *V, const void *W,
                        bool device_src, bool f64, void *stream)
@@ -326,10 +401,19 @@ static int push_common(lp_fieldset *fs, double t, const void *U, const void *V, 
     HIPCHECK(hipStreamWaitEvent(fs->up, fs->release[slot], 0));
     const void *src[3] = {U, V, W};
     const size_t esz = f64 ? sizeof(double) : sizeof(float);
-    const hipMemcpyKind kind = device_src ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-    for (int q = 0; q < nvar; ++q) {
-        void *dst = f64 ? (void *)(fs->dstage64 + q * nvals) : (void *)(fs->dstage + q * nvals);
-        HIPCHECK(hipMemcpyAsync(dst, src[q], nvals * esz, kind, fs->up));
+    char *dst = f64 ? (char *)fs->dstage64 : (char *)fs->dstage;
+    if (device_src) {
+        for (int q = 0; q < nvar; ++q)
+            HIPCHECK(hipMemcpyAsync(dst + (size_t)q * nvals * esz, src[q], nvals * esz,
+                                    hipMemcpyDeviceToDevice, fs->up));
+        if (stream) {  // work the caller queues on `stream` later may reuse the source
+            if (!fs->src_done)
+                HIPCHECK(hipEventCreateWithFlags(&fs->src_done, hipEventDisableTiming));
+            HIPCHECK(hipEventRecord(fs->src_done, fs->up));
+            HIPCHECK(hipStreamWaitEvent((hipStream_t)stream, fs->src_done, 0));
+        }
+    } else if ((rc = upload_from_host(fs, src, nvar, nvals * esz, dst))) {
+        return rc;
     }
     char *slotp = fs->dslots + (size_t)slot * fs->slot_bytes;
     float *scales = fs->dscales + (size_t)slot * fs->nzl * 3;
@@ -346,8 +430,6 @@ static int push_common(lp_fieldset *fs, double t, const void *U, const void *V, 
                                         fs->dtmp, fs->up);
     HIPCHECK(e);
     HIPCHECK(hipEventRecord(fs->ready[slot], fs->up));
-    if (!device_src)
-        HIPCHECK(hipStreamSynchronize(fs->up));  // the host arrays may be reused now
     if (fs->npushed == 0)
         fs->first_t = t;
     fs->slot_t[slot] = t;

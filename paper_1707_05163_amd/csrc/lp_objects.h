@@ -33,6 +33,14 @@ struct lp_fieldset {
     float *dtmp = nullptr;
     float *dstage = nullptr;
     double *dstage64 = nullptr;
+    // pinned host staging of pushes from host memory: two chunks of pin_chunk bytes,
+    // each with the event of its last host-to-device copy
+    char *hpin = nullptr;
+    size_t pin_chunk = 0;
+    hipEvent_t pin_ev[2] = {nullptr, nullptr};
+    bool pin_pending[2] = {false, false};
+    int pin_next = 0;
+    hipEvent_t src_done = nullptr;  // device-source pushes: the source has been read
     hipStream_t up = nullptr;
     std::vector<hipEvent_t> ready, release;
     std::vector<double> slot_t;

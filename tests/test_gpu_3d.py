@@ -106,3 +106,46 @@ def test_push_from_device_equals_push_from_host():
     ga, gb = a.get(), b.get()
     for k in ("lon", "lat", "depth"):
         assert np.array_equal(ga[k], gb[k])
+
+
+def test_host_push_through_pinned_staging_equals_device_push():
+    """Snapshots pushed from host memory (through the library's two pinned staging
+    chunks, several chunks per variable here) hold the same values and give the same
+    trajectories, bit for bit, as the same snapshots pushed from device memory, through
+    a ring of three slots; the host arrays may be overwritten as soon as a push
+    returns."""
+    import torch
+    from paper_1707_05163_amd import FieldSet, ParticleSet
+    w = SC.cfg2_global_3d(nx=1800, ny=900, nz=50, nt=4, n_particles=20000, nsteps=144)
+    log(f"host vs device push: {w.grid.nx}x{w.grid.ny}x{w.grid.nz}, 324 MB per variable")
+    cache = {}
+    dev = [SC.cfg2_snapshot_torch(w, s, "cuda", cache) for s in range(4)]
+    torch.cuda.synchronize()
+    fa = FieldSet(w.grid.lon, w.grid.lat, w.grid.depth, "spherical", "f32", 3, 0.0)
+    fb = FieldSet(w.grid.lon, w.grid.lat, w.grid.depth, "spherical", "f32", 3, 0.0)
+
+    def push(s):
+        host = [x.cpu().numpy() for x in dev[s]]
+        fa.push_snapshot(w.fields.times[s], *host)
+        for h in host:  # the library holds its own copy once the call has returned
+            h.fill(np.nan)
+        fb.push_snapshot(w.fields.times[s], *dev[s])
+
+    for s in range(3):
+        push(s)
+    a = ParticleSet(fa, w.lon0, w.lat0, w.depth0)
+    b = ParticleSet(fb, w.lon0, w.lat0, w.depth0)
+    a.execute(86400.0, w.dt, 86400.0, output_stride=1)
+    b.execute(86400.0, w.dt, 86400.0, output_stride=1)
+    push(3)
+    a.execute(2 * 86400.0, w.dt, 86400.0, output_stride=1)
+    b.execute(2 * 86400.0, w.dt, 86400.0, output_stride=1)
+    ra, rb = a.records(), b.records()
+    for k in ("lon", "lat", "depth", "status", "ci", "cj", "ck"):
+        assert np.array_equal(ra[k], rb[k]), k
+    assert (ra["status"][-1] == 0).sum() > 0.9 * w.n
+    for s in (1, 2, 3):
+        ua, va, wa = fa.get_snapshot(w.fields.times[s])
+        ub, vb, wb = fb.get_snapshot(w.fields.times[s])
+        assert np.array_equal(ua, ub) and np.array_equal(va, vb) and np.array_equal(wa, wb)
+    assert np.array_equal(ua, dev[3][0].cpu().numpy())
