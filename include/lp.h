@@ -201,6 +201,17 @@ typedef struct {
     double dwell_depth;   /* m */
     double maxage;        /* s, >= 0 (0 = off) */
     int32_t sample_tracer;/* 1: sample the field set's tracer every step */
+    int32_t graph;        /* pset_execute_batch only (every run the same): 1 = each output
+                             segment's launches (sorts, descriptor upload, the batched
+                             advection, compactions, records) are captured into a HIP
+                             graph and launched as one; the executable graph is made at
+                             the first segment and updated in place for the later ones
+                             (made anew when a segment's launches differ, e.g. a sort);
+                             same results as 0, bit for bit */
+    int32_t sort_steps;   /* > 0: re-sort every sort_steps steps instead: each output
+                             segment is advanced in launches of at most sort_steps steps,
+                             each after a sort (sort_every is then ignored); not with
+                             RKF45.  Results do not depend on the sort cadence */
 } lp_exec_opts;
 
 /* Advance every active particle by runtime/|dt| steps of dt, taking an output
@@ -234,15 +245,16 @@ int pset_execute_batch(lp_pset **ps, int32_t nruns, double runtime, double dt, d
                        const lp_exec_opts *opts, int32_t block, void *stream);
 
 typedef struct {
-    int32_t block, stencil_cache, sort_every; /* chosen launch shape */
+    int32_t block, stencil_cache, sort_every, sort_steps; /* chosen launch shape */
     double ms;                                /* device time of the winning trial */
 } lp_tune;
 
 /* Autotuner for pset_execute_batch: times every combination of block size (128,
- * 256, 512), stencil cache (on, off) and sorting (every segment, never) over
- * trial_steps steps of dt from the current state (the whole trial segment on the
- * device: its sort and preparation included, not the kernel alone), restores the
- * state after each trial, and returns the fastest.  The choice is cached in the JSON file at
+ * 256, 512), stencil cache (on, off) and sort cadence (never, once per output
+ * segment, every 64, 16 or 4 steps) over max(trial_steps, 128) steps of dt from
+ * the current state (the whole trial segment on the device: its sorts and
+ * preparation included, not the kernel alone), restores the state after each
+ * trial, and returns the fastest.  The choice is cached in the JSON file at
  * cache_path (NULL = no cache) under a key made of the storage type, mesh, run
  * count and the log2 of the mean grid size and of the particle count; a cached
  * entry is returned without trials.  Synchronises. */

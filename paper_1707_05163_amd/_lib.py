@@ -53,7 +53,7 @@ class lp_exec_opts(C.Structure):
                 ("stencil_cache", C.c_int32), ("interp", C.c_int32),
                 ("rkf_tol", C.c_double), ("rkf_min_exp", C.c_int32), ("rkf_max_exp", C.c_int32),
                 ("sink_speed", C.c_double), ("dwell_depth", C.c_double), ("maxage", C.c_double),
-                ("sample_tracer", C.c_int32)]
+                ("sample_tracer", C.c_int32), ("graph", C.c_int32), ("sort_steps", C.c_int32)]
 
 
 class lp_counts(C.Structure):
@@ -64,7 +64,7 @@ class lp_counts(C.Structure):
 
 class lp_tune(C.Structure):
     _fields_ = [("block", C.c_int32), ("stencil_cache", C.c_int32), ("sort_every", C.c_int32),
-                ("ms", C.c_double)]
+                ("sort_steps", C.c_int32), ("ms", C.c_double)]
 
 
 class lp_surrogate_cfg(C.Structure):

@@ -185,12 +185,13 @@ class ParticleSet:
              stencil_cache: bool = True, kernel: str = "rk4", interp: str = "linear",
              tol: float = RKF_TOL, min_exp: int = RKF_MIN_EXP, max_exp: int = RKF_MAX_EXP,
              sink_speed: float = 0.0, dwell_depth: float = 0.0, maxage: float = 0.0,
-             sample: bool = False):
+             sample: bool = False, graph: bool = False, sort_steps: int = 0):
         return L.lp_exec_opts(_KERNEL[kernel], _RECOVERY[recovery], float(Kh), int(run_id),
                               int(seed) & 0xFFFFFFFF, int(output_stride), int(sort_every),
                               int(bool(profile)), int(bool(stencil_cache)), _INTERP[interp],
                               float(tol), int(min_exp), int(max_exp), float(sink_speed),
-                              float(dwell_depth), float(maxage), int(bool(sample)))
+                              float(dwell_depth), float(maxage), int(bool(sample)),
+                              int(bool(graph)), int(sort_steps))
 
     def execute(self, runtime: float, dt: float, outputdt: float = 0.0,
                 recovery: str = "delete", Kh: float = 0.0, run_id: int = 0, seed: int = SEED,
@@ -198,13 +199,13 @@ class ParticleSet:
                 stencil_cache: bool = True, kernel: str = "rk4", interp: str = "linear",
                 tol: float = RKF_TOL, min_exp: int = RKF_MIN_EXP, max_exp: int = RKF_MAX_EXP,
                 sink_speed: float = 0.0, dwell_depth: float = 0.0, maxage: float = 0.0,
-                sample: bool = False, stream=None):
+                sample: bool = False, sort_steps: int = 0, stream=None):
         """The update loop: runtime/|dt| steps of dt (negative dt runs backward).  With
         kernel="rkf45" each particle steps adaptively by |dt| 2^e, e in
         [min_exp, max_exp], to within `tol` metres per step."""
         o = self.opts(recovery, Kh, run_id, seed, output_stride, sort_every, profile,
                       stencil_cache, kernel, interp, tol, min_exp, max_exp, sink_speed,
-                      dwell_depth, maxage, sample)
+                      dwell_depth, maxage, sample, sort_steps=sort_steps)
         L.check(L.lib.pset_execute(self._h, float(runtime), float(dt), float(outputdt),
                                    C.byref(o), _stream(stream)))
         if runtime > 0:
@@ -330,7 +331,8 @@ def autotune_batch(psets, dt: float, trial_steps: int, opts=None, cache_path=Non
     L.check(L.lib.pset_autotune_batch(hs, n, float(dt), int(trial_steps), oa,
                                       None if cache_path is None else str(cache_path).encode(),
                                       C.byref(t)))
-    return dict(block=t.block, stencil_cache=t.stencil_cache, sort_every=t.sort_every, ms=t.ms)
+    return dict(block=t.block, stencil_cache=t.stencil_cache, sort_every=t.sort_every,
+                sort_steps=t.sort_steps, ms=t.ms)
 
 
 SIZES = (64, 256, 256, 256, 256, 2)

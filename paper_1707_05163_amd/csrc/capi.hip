@@ -853,7 +853,8 @@ namespace {
 // One execute call split into its output segments.
 struct ExecPlan {
     int64_t nsteps = 0, per = 0;
-    std::vector<std::pair<int64_t, int64_t>> segs;  // (first step, steps)
+    std::vector<std::pair<int64_t, int64_t>> segs;  // launches: (first step, steps)
+    std::vector<char> seg_end;                      // the launch ends an output segment
     std::vector<char> used;                         // snapshot slots read
     lp::AdvectParams P{};                           // per-call part of the kernel arguments
     size_t toff = 0;                                // time-table offset of the next segment
@@ -896,8 +897,11 @@ int exec_prepare(lp_pset *ps, double runtime, double dt, double outputdt, const 
     const double adt = std::fabs(dt);
     if (!(runtime >= 0.0) || !std::isfinite(runtime) || !(outputdt >= 0.0))
         return fail(LP_EINVAL, "runtime and outputdt must be >= 0");
-    if (!(o->Kh >= 0.0) || o->output_stride < 0 || o->sort_every < 0)
+    if (!(o->Kh >= 0.0) || o->output_stride < 0 || o->sort_every < 0 || o->sort_steps < 0)
         return fail(LP_EINVAL, "bad options");
+    if (rkf && o->sort_steps > 0)
+        return fail(LP_EINVAL, "RKF45 runs a whole output interval per launch: sort_steps "
+                               "must be 0");
     const int64_t nsteps = (int64_t)std::llround(runtime / adt);
     if (std::fabs((double)nsteps * adt - runtime) > 1e-9 * std::max(runtime, adt))
         return fail(LP_EINVAL, "dt %g does not divide runtime %g", dt, runtime);
@@ -926,8 +930,16 @@ int exec_prepare(lp_pset *ps, double runtime, double dt, double outputdt, const 
     double t0 = ps->t0;
     if (ps->dt != 0.0 && dt != ps->dt)  // keep t = t0 + step * dt at the current step
         t0 = (ps->t0 + (double)ps->step * ps->dt) - (double)ps->step * dt;
-    for (int64_t a = 0; a < nsteps; a += per)
-        plan.segs.emplace_back(ps->step + a, std::min(per, nsteps - a));
+    // one launch per output segment, or with sort_steps = K one per K steps of it
+    const int64_t cut = o->sort_steps > 0 ? (int64_t)o->sort_steps : 0;
+    for (int64_t a = 0; a < nsteps; a += per) {
+        const int64_t len = std::min(per, nsteps - a);
+        const int64_t piece = cut > 0 ? cut : len;
+        for (int64_t c = 0; c < len; c += piece) {
+            plan.segs.emplace_back(ps->step + a + c, std::min(piece, len - c));
+            plan.seg_end.push_back(c + piece >= len ? 1 : 0);
+        }
+    }
     size_t ntab = 0;
     if (!rkf)
         for (auto &sg : plan.segs)
@@ -1021,7 +1033,10 @@ int exec_prepare(lp_pset *ps, double runtime, double dt, double outputdt, const 
     if (behave)
         ps->behave_records = true;
     if (plan.records) {
-        int rc = grow_records(ps, ps->nrec + (int64_t)plan.segs.size() + 1);
+        int64_t nout = 0;
+        for (char e : plan.seg_end)
+            nout += e ? 1 : 0;
+        int rc = grow_records(ps, ps->nrec + nout + 1);
         if (rc)
             return rc;
         if (ps->nrec == 0 && (rc = take_record(ps, stream)))
@@ -1083,7 +1098,7 @@ int exec_segment_pre(lp_pset *ps, const lp_exec_opts *o, ExecPlan &plan, size_t 
                      hipStream_t stream)
 {
     lp_fieldset *fs = ps->fs;
-    if (o->sort_every > 0 && ps->segs_since_sort >= o->sort_every) {
+    if (o->sort_steps > 0 || (o->sort_every > 0 && ps->segs_since_sort >= o->sort_every)) {
         HIPCHECK(lp::launch_sort(fs->g, ps->dx, ps->dy, ps->dz, ps->dst, ps->dorder[ps->cur],
                                  ps->dcount + ps->cur, ps->n_launch, ps->dkeys, ps->dhist,
                                  ps->nbins, ps->dblk, ps->dorder[1 - ps->cur],
@@ -1109,11 +1124,13 @@ int exec_segment_post(lp_pset *ps, ExecPlan &plan, size_t k, hipStream_t stream)
                                 ps->dorder[1 - ps->cur], ps->dcount + (1 - ps->cur),
                                 ps->n_launch, stream));
     ps->cur = 1 - ps->cur;
-    ps->segs_since_sort++;
-    if (plan.records) {
-        int rc = take_record(ps, stream);
-        if (rc)
-            return rc;
+    if (plan.seg_end[k]) {
+        ps->segs_since_sort++;
+        if (plan.records) {
+            int rc = take_record(ps, stream);
+            if (rc)
+                return rc;
+        }
     }
     plan.toff += 2 * (size_t)plan.segs[k].second + 1;
     return LP_OK;
@@ -1183,8 +1200,44 @@ struct BatchScratch {
     size_t cap_runs = 0;
     hipEvent_t done = nullptr;
     bool pending = false;
+    // graph mode: the stream segments are captured on, and the executable graph of
+    // the last captured segment (updated in place while the topology stays the same)
+    hipStream_t cap = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int64_t instantiated = 0, updated = 0;
 };
 thread_local BatchScratch g_batch;
+
+// End a capture that failed part-way, dropping what was captured.
+void abandon_capture(hipStream_t cs)
+{
+    hipGraph_t g = nullptr;
+    (void)hipStreamEndCapture(cs, &g);
+    if (g)
+        (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+}
+
+// Turn the captured graph of one segment into the executable graph: update the
+// previous one in place when the topology matches, else instantiate anew.
+int graph_from_capture(BatchScratch &b, hipGraph_t g)
+{
+    if (b.exec) {
+        hipGraphNode_t err_node = nullptr;
+        hipGraphExecUpdateResult res = hipGraphExecUpdateError;
+        if (hipGraphExecUpdate(b.exec, g, &err_node, &res) == hipSuccess &&
+            res == hipGraphExecUpdateSuccess) {
+            b.updated++;
+            return LP_OK;
+        }
+        (void)hipGetLastError();
+        (void)hipGraphExecDestroy(b.exec);
+        b.exec = nullptr;
+    }
+    HIPCHECK(hipGraphInstantiate(&b.exec, g, nullptr, nullptr, 0));
+    b.instantiated++;
+    return LP_OK;
+}
 
 int batch_reserve(size_t nruns)
 {
@@ -1240,8 +1293,10 @@ int execute_batch(lp_pset **ps, int32_t nruns, double runtime, double dt, double
             (f->npushed == 1) != (f0->npushed == 1))
             return fail(LP_EINVAL, "batched runs must be 2D with one storage type, one mesh kind "
                                    "and all steady or all time-varying (run %d differs)", r);
-        if (opts[r].stencil_cache != opts[0].stencil_cache)
-            return fail(LP_EINVAL, "batched runs share the stencil_cache setting");
+        if (opts[r].stencil_cache != opts[0].stencil_cache || opts[r].graph != opts[0].graph ||
+            opts[r].sort_steps != opts[0].sort_steps)
+            return fail(LP_EINVAL, "batched runs share the stencil_cache, graph and sort_steps "
+                                   "settings");
         if (opts[r].kernel == LP_KERNEL_RKF45)
             return fail(LP_EINVAL, "the batched launch takes RK4 or Euler, not RKF45 (run %d)", r);
         if (opts[r].interp != LP_INTERP_LINEAR)
@@ -1263,31 +1318,51 @@ int execute_batch(lp_pset **ps, int32_t nruns, double runtime, double dt, double
     if (plans[0].nsteps == 0)
         return LP_OK;
     const size_t nseg = plans[0].segs.size();
+    const bool use_graph = opts[0].graph != 0;
     for (size_t k = 0; k < nseg; ++k) {
         int rc = batch_reserve((size_t)nruns);
         if (rc)
             return rc;
         BatchScratch &b = g_batch;
+        // graph mode: the segment's launches are recorded on the capture stream and
+        // run as one graph on `stream`; otherwise they go to `stream` directly
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        const bool prof = opts[0].profile || kernel_ms;
+        if (prof) {  // graph mode times the whole segment's graph
+            HIPCHECK(hipEventCreate(&e0));
+            HIPCHECK(hipEventCreate(&e1));
+        }
+        hipStream_t cs = stream;
+        if (use_graph) {
+            if (!b.cap)
+                HIPCHECK(hipStreamCreateWithFlags(&b.cap, hipStreamNonBlocking));
+            cs = b.cap;
+            HIPCHECK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        }
+        auto bail = [&](int code) {
+            if (use_graph)
+                abandon_capture(cs);
+            return code;
+        };
         uint32_t total = 0;
         for (int r = 0; r < nruns; ++r) {
-            if ((rc = exec_segment_pre(ps[r], &opts[r], plans[r], k, stream)))
-                return rc;
+            if ((rc = exec_segment_pre(ps[r], &opts[r], plans[r], k, cs)))
+                return bail(rc);
             b.hruns[r] = plans[r].P;
             b.hcstart[r] = total;
             total += (ps[r]->n_launch + block - 1) / block;
         }
         b.hcstart[nruns] = total;
-        HIPCHECK(hipMemcpyAsync(b.druns, b.hruns, nruns * sizeof(lp::AdvectParams),
-                                hipMemcpyHostToDevice, stream));
-        HIPCHECK(hipMemcpyAsync(b.dcstart, b.hcstart, (nruns + 1) * sizeof(uint32_t),
-                                hipMemcpyHostToDevice, stream));
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-        const bool prof = opts[0].profile || kernel_ms;
-        if (prof) {
-            HIPCHECK(hipEventCreate(&e0));
-            HIPCHECK(hipEventCreate(&e1));
+        hipError_t he = hipMemcpyAsync(b.druns, b.hruns, nruns * sizeof(lp::AdvectParams),
+                                       hipMemcpyHostToDevice, cs);
+        if (he == hipSuccess)
+            he = hipMemcpyAsync(b.dcstart, b.hcstart, (nruns + 1) * sizeof(uint32_t),
+                                hipMemcpyHostToDevice, cs);
+        if (he != hipSuccess)
+            return bail(fail(LP_EDEVICE, "batch descriptor upload failed: %s",
+                             hipGetErrorString(he)));
+        if (prof && !use_graph)
             HIPCHECK(hipEventRecord(e0, stream));
-        }
         int met = 0;
         bool brown = false;
         if (f0->g.spherical) {
@@ -1303,11 +1378,36 @@ int execute_batch(lp_pset **ps, int32_t nruns, double runtime, double dt, double
         }
         for (int r = 0; r < nruns; ++r)
             brown = brown || opts[r].Kh > 0.0;
-        HIPCHECK(lp::launch_advect_batch(f0->dtype, f0->npushed == 1, met, brown, b.druns,
-                                         b.dcstart, nruns, total, b.dqueues, block, stream,
-                                         nullptr));
-        if (prof) {
+        he = lp::launch_advect_batch(f0->dtype, f0->npushed == 1, met, brown, b.druns,
+                                     b.dcstart, nruns, total, b.dqueues, block, cs, nullptr);
+        if (he != hipSuccess)
+            return bail(fail(LP_EDEVICE, "batched launch failed: %s", hipGetErrorString(he)));
+        if (prof && !use_graph)
             HIPCHECK(hipEventRecord(e1, stream));
+        if (!use_graph) {
+            HIPCHECK(hipEventRecord(b.done, stream));
+            b.pending = true;
+        }
+        for (int r = 0; r < nruns; ++r)
+            if ((rc = exec_segment_post(ps[r], plans[r], k, cs)))
+                return bail(rc);
+        if (use_graph) {
+            hipGraph_t g = nullptr;
+            HIPCHECK(hipStreamEndCapture(cs, &g));
+            rc = graph_from_capture(b, g);
+            (void)hipGraphDestroy(g);
+            if (rc)
+                return rc;
+            if (prof)
+                HIPCHECK(hipEventRecord(e0, stream));
+            HIPCHECK(hipGraphLaunch(b.exec, stream));
+            if (prof)
+                HIPCHECK(hipEventRecord(e1, stream));
+            // the descriptors in pinned memory are read when the graph runs
+            HIPCHECK(hipEventRecord(b.done, stream));
+            b.pending = true;
+        }
+        if (prof) {
             if (kernel_ms) {
                 HIPCHECK(hipEventSynchronize(e1));
                 float ms = 0.f;
@@ -1319,11 +1419,6 @@ int execute_batch(lp_pset **ps, int32_t nruns, double runtime, double dt, double
                 ps[0]->prof.emplace_back(e0, e1);
             }
         }
-        HIPCHECK(hipEventRecord(b.done, stream));
-        b.pending = true;
-        for (int r = 0; r < nruns; ++r)
-            if ((rc = exec_segment_post(ps[r], plans[r], k, stream)))
-                return rc;
     }
     for (int r = 0; r < nruns; ++r) {
         int rc = exec_finish(ps[r], plans[r], stream);
@@ -1430,7 +1525,8 @@ std::string tune_key(lp_pset **ps, int nruns)
 }
 
 // The cache is a JSON object with one entry per line:
-//   "key": {"block": B, "stencil_cache": C, "sort_every": S, "ms": T},
+//   "key": {"block": B, "stencil_cache": C, "sort_every": S, "sort_steps": K, "ms": T},
+// (entries in an older format without "sort_steps" do not parse and are tuned again)
 bool cache_lookup(const char *path, const std::string &key, lp_tune *t)
 {
     if (!path)
@@ -1447,8 +1543,8 @@ bool cache_lookup(const char *path, const std::string &key, lp_tune *t)
             continue;
         lp_tune r{};
         if (sscanf(p + pat.size(), " : {\"block\": %d, \"stencil_cache\": %d, \"sort_every\": %d, "
-                                   "\"ms\": %lf}", &r.block, &r.stencil_cache, &r.sort_every,
-                   &r.ms) == 4) {
+                                   "\"sort_steps\": %d, \"ms\": %lf}", &r.block,
+                   &r.stencil_cache, &r.sort_every, &r.sort_steps, &r.ms) == 5) {
             *t = r;
             found = true;
         }
@@ -1476,8 +1572,9 @@ void cache_store(const char *path, const std::string &key, const lp_tune &t)
     }
     char buf[512];
     snprintf(buf, sizeof buf,
-             "  \"%s\": {\"block\": %d, \"stencil_cache\": %d, \"sort_every\": %d, \"ms\": %.4f}",
-             key.c_str(), t.block, t.stencil_cache, t.sort_every, t.ms);
+             "  \"%s\": {\"block\": %d, \"stencil_cache\": %d, \"sort_every\": %d, "
+             "\"sort_steps\": %d, \"ms\": %.4f}",
+             key.c_str(), t.block, t.stencil_cache, t.sort_every, t.sort_steps, t.ms);
     lines.push_back(buf);
     const std::string tmp = std::string(path) + ".tmp";
     FILE *f = fopen(tmp.c_str(), "w");
@@ -1521,25 +1618,36 @@ extern "C" int pset_autotune_batch(lp_pset **ps, int32_t nruns, double dt, int32
         return fail(LP_EDEVICE, "event creation failed");
     }
     const int blocks[] = {128, 256, 512};
+    // sort cadence ladder: never, once per output segment, every 64, 16 and 4 steps
+    struct Cadence {
+        int every, steps;
+    };
+    const Cadence ladder[] = {{0, 0}, {1, 0}, {0, 64}, {0, 16}, {0, 4}};
+    // the trial spans at least two of the longest cadence's launches
+    const int steps = std::max(trial_steps, 128);
     for (int cache = 1; cache >= 0 && rc == LP_OK; --cache)
-        for (int sort = 0; sort <= 1 && rc == LP_OK; ++sort)
+        for (const Cadence &cad : ladder) {
+            if (rc != LP_OK)
+                break;
             for (int blk : blocks) {
                 for (auto &x : o) {
                     x.stencil_cache = cache;
-                    x.sort_every = sort;
+                    x.sort_every = cad.every;
+                    x.sort_steps = cad.steps;
                     x.output_stride = 0;
                     x.profile = 0;
+                    x.graph = 0;
                 }
-                // the trial is one segment, timed whole on the device: the sort ahead of
-                // it (sort = 1) and the per-run preparation count, not the kernel alone
+                // the trial is one output segment, timed whole on the device: the sorts
+                // in it and the per-run preparation count, not the kernel alone
                 for (int r = 0; r < nruns; ++r)
-                    ps[r]->segs_since_sort = sort ? 1 << 30 : 0;
+                    ps[r]->segs_since_sort = cad.every ? 1 << 30 : 0;
                 float fms = 0.f;
                 if (hipEventRecord(t0, nullptr) != hipSuccess) {
                     rc = fail(LP_EDEVICE, "event record failed");
                     break;
                 }
-                rc = execute_batch(ps, nruns, trial_steps * dt, dt, 0.0, o.data(), nullptr, blk,
+                rc = execute_batch(ps, nruns, steps * dt, dt, 0.0, o.data(), nullptr, blk,
                                    false, nullptr);
                 if (rc == LP_OK && (hipEventRecord(t1, nullptr) != hipSuccess ||
                                     hipEventSynchronize(t1) != hipSuccess ||
@@ -1554,9 +1662,11 @@ extern "C" int pset_autotune_batch(lp_pset **ps, int32_t nruns, double dt, int32
                     b.ms = ms;
                     b.block = blk;
                     b.stencil_cache = cache;
-                    b.sort_every = sort;
+                    b.sort_every = cad.every;
+                    b.sort_steps = cad.steps;
                 }
             }
+        }
     (void)hipEventDestroy(t0);
     (void)hipEventDestroy(t1);
     for (auto &s : saved)
