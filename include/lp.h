@@ -383,6 +383,34 @@ int pset_execute_surrogate(lp_pset *ps, lp_model *m, double runtime, double dt,
                            int32_t steps_per_segment, double residual_m,
                            lp_surrogate_stats *st, void *stream);
 
+/* The two steps of the surrogate around the network, on their own (the same kernels
+ * that pset_execute_surrogate and surrogate_train run).
+ *
+ * surrogate_features: the network's input rows for n positions (x, y) at time t on a
+ * 2D field set, as the bfloat16 values the network reads, returned as floats
+ * X[n][64]: [0..3] lon/180, lat/90, sin and cos of 2 pi (t - T0) / P (T0 the first
+ * resident snapshot, P the period, or the span of the resident snapshots); [4..53]
+ * U, V (m/s) at the 5 x 5 nodes around the nearest node (j - 2 .. j + 2 outer, i - 2
+ * .. i + 2 inner, U then V; indices clamped to the grid), each linear in time
+ * between the snapshots bracketing t; [54..55] the position's offset from that node
+ * in cell widths; [56..57] U, V bilinear at the position and linear in time;
+ * [58..59] the cell's width and height in metres / 30 km; [60..63] zero.  Positions
+ * outside the grid are clamped to it.  LP_ETIME if t is not covered.  Synchronises.
+ *
+ * surrogate_check: the residual check of the inference for n candidate segments
+ * starting at (x0, y0): the network's output Y[i][2] (east and north displacement
+ * in units of 7200 m) is accepted, accept[i] = 1 and (x1, y1) = its end point,
+ * when the coarse estimate ended in the grid (coarse_status[i] == 0), the distance
+ * in metres between the network's displacement and the coarse one (xc - x0,
+ * yc - y0; converted to metres with the metric at y0 on a spherical mesh) is at
+ * most residual_m, and the end point is inside the grid and not in a land cell;
+ * otherwise accept[i] = 0 and (x1, y1) = (x0, y0).  Synchronises. */
+int surrogate_features(lp_fieldset *fs, int64_t n, const double *x, const double *y, double t,
+                       float *X);
+int surrogate_check(lp_fieldset *fs, int64_t n, const double *x0, const double *y0,
+                    const double *xc, const double *yc, const uint8_t *coarse_status,
+                    const float *Y, double residual_m, uint8_t *accept, double *x1, double *y1);
+
 const char *lp_last_error(void);
 /* Library version string. */
 const char *lp_version(void);

@@ -5,7 +5,7 @@ ImportError if it has not been built; nothing here computes on the CPU.
 """
 
 __all__ = ["FieldSet", "ParticleSet", "SEED", "philox_normals", "execute_batch",
-           "autotune_batch", "Surrogate"]
+           "autotune_batch", "Surrogate", "surrogate_features", "surrogate_check"]
 
 
 def __getattr__(name):

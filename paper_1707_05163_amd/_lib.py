@@ -35,7 +35,7 @@ EXPORTS = (
     "pset_execute_batch", "pset_autotune_batch",
     "surrogate_param_count", "surrogate_create", "surrogate_get_params", "surrogate_set_params",
     "surrogate_forward", "surrogate_gradients", "surrogate_train_step", "surrogate_destroy",
-    "surrogate_train", "pset_execute_surrogate",
+    "surrogate_train", "pset_execute_surrogate", "surrogate_features", "surrogate_check",
 )
 
 
@@ -133,6 +133,8 @@ def _declare(L):
         "surrogate_train": ([P, P, C.POINTER(lp_surrogate_cfg), C.POINTER(lp_train_stats), P], I),
         "pset_execute_surrogate": ([P, P, C.c_double, C.c_double, C.c_int32, C.c_double,
                                     C.POINTER(lp_surrogate_stats), P], I),
+        "surrogate_features": ([P, C.c_int64, P, P, C.c_double, P], I),
+        "surrogate_check": ([P, C.c_int64, P, P, P, P, P, P, C.c_double, P, P, P], I),
         "lp_last_error": ([], C.c_char_p),
         "lp_version": ([], C.c_char_p),
     }

@@ -422,3 +422,28 @@ def _unflatten(flat):
         q += b
         out.append((W.copy(), bb.copy()))
     return out
+
+
+def surrogate_features(fieldset: FieldSet, x, y, t: float):
+    """The surrogate network's input rows [n x 64] at positions (x, y) and time t, as
+    the bfloat16 values the network reads (see surrogate_features in lp.h)."""
+    x = np.ascontiguousarray(x, np.float64)
+    y = np.ascontiguousarray(y, np.float64)
+    X = np.empty((x.size, 64), np.float32)
+    L.check(L.lib.surrogate_features(fieldset.handle, x.size, _ptr(x), _ptr(y), float(t),
+                                     _ptr(X)))
+    return X
+
+
+def surrogate_check(fieldset: FieldSet, x0, y0, xc, yc, coarse_status, Y, residual_m: float):
+    """The surrogate's residual check on n candidate segments: (accept, x1, y1)."""
+    x0, y0, xc, yc = (np.ascontiguousarray(a, np.float64) for a in (x0, y0, xc, yc))
+    st = np.ascontiguousarray(coarse_status, np.uint8)
+    Y = np.ascontiguousarray(Y, np.float32)
+    n = x0.size
+    acc = np.empty(n, np.uint8)
+    x1, y1 = np.empty(n), np.empty(n)
+    L.check(L.lib.surrogate_check(fieldset.handle, n, _ptr(x0), _ptr(y0), _ptr(xc), _ptr(yc),
+                                  _ptr(st), _ptr(Y), float(residual_m), _ptr(acc), _ptr(x1),
+                                  _ptr(y1)))
+    return acc.astype(bool), x1, y1

@@ -1029,6 +1029,128 @@ extern "C" int surrogate_train(lp_fieldset *fs, lp_model *m, const lp_surrogate_
     return LP_OK;
 }
 
+// ------------------------------------------------------------------ the two steps alone
+extern "C" int surrogate_features(lp_fieldset *fs, int64_t n, const double *x, const double *y,
+                                  double t, float *X)
+{
+    if (!fs || n < 0 || (n > 0 && (!x || !y || !X))) {
+        lp_set_error("bad surrogate_features arguments");
+        return LP_EINVAL;
+    }
+    if (fs->is3d) {
+        lp_set_error("the surrogate works on 2D field sets");
+        return LP_EINVAL;
+    }
+    if (n == 0)
+        return LP_OK;
+    TimeEntry e{};
+    int rc = lp_time_entry(fs, t, &e);
+    if (rc)
+        return rc;
+    double t_lo = 0.0;
+    const double P = field_period(fs, t_lo);
+    const double ph = P > 0.0 ? 2.0 * M_PI * std::fmod(t - t_lo, P) / P : 0.0;
+    const float phs[2] = {(float)std::sin(ph), (float)std::cos(ph)};
+    DeviceBuf mem;
+    double *dx, *dy;
+    TimeEntry *dtab;
+    float *dphase;
+    uint16_t *dX;
+    SCHECK(mem.get(&dx, (size_t)n));
+    SCHECK(mem.get(&dy, (size_t)n));
+    SCHECK(mem.get(&dtab, 1));
+    SCHECK(mem.get(&dphase, 2));
+    SCHECK(mem.get(&dX, (size_t)n * kIn));
+    SCHECK(hipMemcpy(dx, x, (size_t)n * 8, hipMemcpyHostToDevice));
+    SCHECK(hipMemcpy(dy, y, (size_t)n * 8, hipMemcpyHostToDevice));
+    SCHECK(hipMemcpy(dtab, &e, sizeof e, hipMemcpyHostToDevice));
+    SCHECK(hipMemcpy(dphase, phs, 8, hipMemcpyHostToDevice));
+    SCHECK(hipStreamSynchronize(fs->up));  // the snapshots the entry names are in place
+    FeatArgs fa{};
+    make_feat(fs, fa);
+    fa.x = dx;
+    fa.y = dy;
+    fa.tab = dtab;
+    fa.phase = dphase;
+    fa.n = n;
+    fa.npad = n;
+    fa.X = dX;
+    hipLaunchKernelGGL(k_features, dim3((uint32_t)((n + 127) / 128)), dim3(128), 0, nullptr,
+                       fa);
+    SCHECK(hipGetLastError());
+    std::vector<uint16_t> h((size_t)n * kIn);
+    SCHECK(hipDeviceSynchronize());
+    SCHECK(hipMemcpy(h.data(), dX, h.size() * 2, hipMemcpyDeviceToHost));
+    for (size_t q = 0; q < h.size(); ++q) {
+        const uint32_t b = (uint32_t)h[q] << 16;
+        std::memcpy(&X[q], &b, 4);
+    }
+    return LP_OK;
+}
+
+extern "C" int surrogate_check(lp_fieldset *fs, int64_t n, const double *x0, const double *y0,
+                               const double *xc, const double *yc, const uint8_t *coarse_status,
+                               const float *Y, double residual_m, uint8_t *accept, double *x1,
+                               double *y1)
+{
+    if (!fs || n < 0 || n > 0x7FFFFFFFll ||
+        (n > 0 && (!x0 || !y0 || !xc || !yc || !coarse_status || !Y || !accept || !x1 ||
+                   !y1)) ||
+        !(residual_m >= 0.0)) {
+        lp_set_error("bad surrogate_check arguments");
+        return LP_EINVAL;
+    }
+    if (fs->is3d) {
+        lp_set_error("the surrogate works on 2D field sets");
+        return LP_EINVAL;
+    }
+    if (n == 0)
+        return LP_OK;
+    const size_t N = (size_t)n;
+    DeviceBuf mem;
+    double *dx, *dy, *dxc, *dyc;
+    uint8_t *dst;
+    float *dY;
+    uint32_t *order, *nact, *fall, *nfall;
+    unsigned long long *acc;
+    SCHECK(mem.get(&dx, N));
+    SCHECK(mem.get(&dy, N));
+    SCHECK(mem.get(&dxc, N));
+    SCHECK(mem.get(&dyc, N));
+    SCHECK(mem.get(&dst, N));
+    SCHECK(mem.get(&dY, 2 * N));
+    SCHECK(mem.get(&order, N));
+    SCHECK(mem.get(&nact, 1));
+    SCHECK(mem.get(&fall, N));
+    SCHECK(mem.get(&nfall, 1));
+    SCHECK(mem.get(&acc, 1));
+    SCHECK(hipMemcpy(dx, x0, N * 8, hipMemcpyHostToDevice));
+    SCHECK(hipMemcpy(dy, y0, N * 8, hipMemcpyHostToDevice));
+    SCHECK(hipMemcpy(dxc, xc, N * 8, hipMemcpyHostToDevice));
+    SCHECK(hipMemcpy(dyc, yc, N * 8, hipMemcpyHostToDevice));
+    SCHECK(hipMemcpy(dst, coarse_status, N, hipMemcpyHostToDevice));
+    SCHECK(hipMemcpy(dY, Y, N * 8, hipMemcpyHostToDevice));
+    SCHECK(lp::launch_iota(order, N, nullptr));
+    SCHECK(lp::launch_fill_u32(nact, (uint32_t)n, 1, nullptr));
+    SCHECK(lp::launch_fill_u32(nfall, 0u, 1, nullptr));
+    SCHECK(hipMemset(acc, 0, 8));
+    hipLaunchKernelGGL(k_check, dim3((uint32_t)((N + 255) / 256)), dim3(256), 0, nullptr, fs->g,
+                       order, nact, dx, dy, dxc, dyc, dst, dY, residual_m, fall, nfall, acc);
+    SCHECK(hipGetLastError());
+    SCHECK(hipDeviceSynchronize());
+    uint32_t nf = 0;
+    SCHECK(hipMemcpy(&nf, nfall, 4, hipMemcpyDeviceToHost));
+    std::vector<uint32_t> hf(nf);
+    if (nf)
+        SCHECK(hipMemcpy(hf.data(), fall, (size_t)nf * 4, hipMemcpyDeviceToHost));
+    SCHECK(hipMemcpy(x1, dx, N * 8, hipMemcpyDeviceToHost));
+    SCHECK(hipMemcpy(y1, dy, N * 8, hipMemcpyDeviceToHost));
+    std::memset(accept, 1, N);
+    for (uint32_t id : hf)
+        accept[id] = 0;
+    return LP_OK;
+}
+
 // ------------------------------------------------------------------ inference
 extern "C" int pset_execute_surrogate(lp_pset *ps, lp_model *m, double runtime, double dt,
                                       int32_t steps_per_segment, double residual_m,
