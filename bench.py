@@ -310,14 +310,18 @@ def main_cfg2(a):
         ps = ParticleSet(fs, lon0, lat0, dep0, stream=stream)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        fs.push_snapshot(w.fields.times[0], *snaps[0], stream=stream)
-        fs.push_snapshot(w.fields.times[1], *snaps[1], stream=stream)
+        # the snapshots are complete before the timed region, so their pushes need no
+        # ordering after the compute stream (stream 0): the upload and conversion of day
+        # d + 2 run on the field set's side stream while day d is advected, into the
+        # ring slot day d no longer reads; the execute of day d + 1 waits for them
+        fs.push_snapshot(w.fields.times[0], *snaps[0], stream=0)
+        fs.push_snapshot(w.fields.times[1], *snaps[1], stream=0)
         for d in range(days):
             ps.execute(86400.0, w.dt, 86400.0, output_stride=stride, sort_every=a.sort_every,
                        profile=it >= a.warmup, stencil_cache=bool(a.stencil_cache),
                        stream=stream)
             if d + 2 < w.fields.nt:
-                fs.push_snapshot(w.fields.times[d + 2], *snaps[d + 2], stream=stream)
+                fs.push_snapshot(w.fields.times[d + 2], *snaps[d + 2], stream=0)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         print(f"[bench] step {it}: {el * 1e3:.1f} ms", file=sys.stderr, flush=True)

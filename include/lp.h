@@ -109,15 +109,21 @@ int fieldset_create(const lp_grid_desc *g, lp_fieldset **out);
  * upload stream, which then converts the snapshot to the storage type.  The call
  * returns once the last chunk is queued, without waiting for the device copies;
  * a later pset_execute waits for them.  The host arrays may be reused when the
- * call returns.  LP_ENOMEM if the pinned staging cannot be allocated. */
+ * call returns.  LP_ENOMEM if the pinned staging cannot be allocated.  The upload
+ * starts after the work queued on `stream` before the call; with stream NULL it
+ * waits for nothing but the readers of the slot it replaces, so it can overlap
+ * kernels already queued (the next time slice loads while the current one is
+ * advected). */
 int fieldset_push_snapshot(lp_fieldset *fs, double t, const float *U, const float *V,
                            const float *W, void *stream);
 /* Same with double host arrays (LP_F64 storage keeps them exact). */
 int fieldset_push_snapshot_f64(lp_fieldset *fs, double t, const double *U, const double *V,
                                const double *W, void *stream);
-/* Same with float arrays already in device memory (no host copy).  Work the
- * caller queues on `stream` after this call runs after the arrays have been read,
- * so they may then be freed or overwritten in stream order. */
+/* Same with float arrays already in device memory: they are converted into the
+ * slot where they are, without a copy.  Work the caller queues on `stream` after
+ * this call runs after the arrays have been read, so they may then be freed or
+ * overwritten in stream order; with stream NULL the caller keeps them until the
+ * next pset_execute that reads the slot has been queued and has completed. */
 int fieldset_push_snapshot_device(lp_fieldset *fs, double t, const float *dU, const float *dV,
                                   const float *dW, void *stream);
 /* A scalar tracer (the temperature of the worked example, Sect. 3.1 and

@@ -93,7 +93,9 @@ class FieldSet:
         return self._h
 
     def push_snapshot(self, t: float, U, V, W=None, stream=None):
-        """advancetime: upload the snapshot at time t into the next ring slot."""
+        """advancetime: upload the snapshot at time t into the next ring slot.  The
+        upload follows the work queued on `stream` (default: torch's current stream);
+        stream=0 orders it after nothing, for sources that are already complete."""
         if _is_torch(U):
             L.check(L.lib.fieldset_push_snapshot_device(self._h, float(t), _ptr(U), _ptr(V),
                                                         _ptr(W), _stream(stream)))

@@ -384,10 +384,13 @@ static int push_common(lp_fieldset *fs, double t, const void *U, const void *V, 
     const size_t nvals = fs->plane() * fs->nzl;
     const int nvar = fs->is3d ? 3 : 2;
     int rc;
+    // float arrays in device memory are converted where they are; everything else goes
+    // through the device staging buffer
+    const bool direct = device_src && !f64;
     if (f64) {
         if (!fs->dstage64 && (rc = dalloc(&fs->dstage64, nvals * 3)))
             return rc;
-    } else if (!fs->dstage && (rc = dalloc(&fs->dstage, nvals * 3))) {
+    } else if (!direct && !fs->dstage && (rc = dalloc(&fs->dstage, nvals * 3))) {
         return rc;
     }
     if (stream) {
@@ -402,21 +405,18 @@ static int push_common(lp_fieldset *fs, double t, const void *U, const void *V, 
     const void *src[3] = {U, V, W};
     const size_t esz = f64 ? sizeof(double) : sizeof(float);
     char *dst = f64 ? (char *)fs->dstage64 : (char *)fs->dstage;
-    if (device_src) {
+    if (device_src && !direct) {
         for (int q = 0; q < nvar; ++q)
             HIPCHECK(hipMemcpyAsync(dst + (size_t)q * nvals * esz, src[q], nvals * esz,
                                     hipMemcpyDeviceToDevice, fs->up));
-        if (stream) {  // work the caller queues on `stream` later may reuse the source
-            if (!fs->src_done)
-                HIPCHECK(hipEventCreateWithFlags(&fs->src_done, hipEventDisableTiming));
-            HIPCHECK(hipEventRecord(fs->src_done, fs->up));
-            HIPCHECK(hipStreamWaitEvent((hipStream_t)stream, fs->src_done, 0));
-        }
-    } else if ((rc = upload_from_host(fs, src, nvar, nvals * esz, dst))) {
+    } else if (!device_src && (rc = upload_from_host(fs, src, nvar, nvals * esz, dst))) {
         return rc;
     }
     char *slotp = fs->dslots + (size_t)slot * fs->slot_bytes;
     float *scales = fs->dscales + (size_t)slot * fs->nzl * 3;
+    const float *fsrc = direct ? (const float *)U : fs->dstage;
+    const float *fv = direct ? (const float *)V : fs->dstage + nvals;
+    const float *fw = direct ? (const float *)W : (fs->is3d ? fs->dstage + 2 * nvals : nullptr);
     hipError_t e;
     if (f64)
         e = lp::launch_convert_snapshot(fs->dtype, fs->is3d, nullptr, nullptr, nullptr,
@@ -424,12 +424,16 @@ static int push_common(lp_fieldset *fs, double t, const void *U, const void *V, 
                                         fs->is3d ? fs->dstage64 + 2 * nvals : nullptr,
                                         fs->plane(), fs->nzl, slotp, scales, fs->dtmp, fs->up);
     else
-        e = lp::launch_convert_snapshot(fs->dtype, fs->is3d, fs->dstage, fs->dstage + nvals,
-                                        fs->is3d ? fs->dstage + 2 * nvals : nullptr, nullptr,
-                                        nullptr, nullptr, fs->plane(), fs->nzl, slotp, scales,
-                                        fs->dtmp, fs->up);
+        e = lp::launch_convert_snapshot(fs->dtype, fs->is3d, fsrc, fv, fs->is3d ? fw : nullptr,
+                                        nullptr, nullptr, nullptr, fs->plane(), fs->nzl, slotp,
+                                        scales, fs->dtmp, fs->up);
     HIPCHECK(e);
     HIPCHECK(hipEventRecord(fs->ready[slot], fs->up));
+    if (device_src && stream) {
+        // work the caller queues on `stream` later may reuse the source arrays: it runs
+        // after the upload stream has read them (the copy, or the conversion itself)
+        HIPCHECK(hipStreamWaitEvent((hipStream_t)stream, fs->ready[slot], 0));
+    }
     if (fs->npushed == 0)
         fs->first_t = t;
     fs->slot_t[slot] = t;
