@@ -1095,6 +1095,22 @@ __device__ inline double metres_lon(const Cell2<R, NL> &c, const AdvectParams &P
 
 
 
+// 1 / (M cos(lat)) at a stage point inside the cached cell, for the slope of an RK4
+// stage: the short series in cells of at most 0.3 degrees, else the cell's series (or
+// the library cosine), then one Newton step on the hardware reciprocal.
+template <int MET, class CellT>
+__device__ inline double stage_metric(const CellT &c, const AdvectParams &P, double y)
+{
+    double m;
+    if constexpr (MET == kSphLib)
+        m = kMetresPerDegree * cos(y * kDegToRad);
+    else if constexpr (MET == kSphTable2)
+        m = mcos_short(c.cl, c.sl, c.y0, y);
+    else
+        m = cos_series_m<MET>(c.cl, c.sl, c.y0, y, P);
+    return recip_stage(m);
+}
+
 // 1 / (M cos(lat)) at the end point of a step, for the metric of the Brownian term: the
 // cached cell's series when the latitude is inside the cell's band (where the series
 // holds), else the turn form of the cosine.
@@ -1150,7 +1166,7 @@ __device__ inline bool stage2(const AdvectParams &P, Cell2<typename Real<ST>::T,
     R u, v;
     values_at<STEADY>(c, e.tau, xi, eta, u, v);
     if constexpr (MET != kFlat) {
-        kx = (double)u * recip(metres_lon<MET>(c, P, y));
+        kx = (double)u * stage_metric<MET>(c, P, y);
         ky = v_in_degrees<R, MET>() ? (double)v : (double)v * (1.0 / kMetresPerDegree);
     } else {
         kx = (double)u;
@@ -1185,7 +1201,7 @@ __device__ inline bool stage2_tc(const AdvectParams &P, Cell2<typename Real<ST>:
         v = poly<R>(tc + 4, xi, eta);
     }
     if constexpr (MET != kFlat) {
-        kx = (double)u * recip(metres_lon<MET>(c, P, y));
+        kx = (double)u * stage_metric<MET>(c, P, y);
         ky = v_in_degrees<R, MET>() ? (double)v : (double)v * (1.0 / kMetresPerDegree);
     } else {
         kx = (double)u;
@@ -1790,14 +1806,7 @@ __device__ inline bool stage3(const AdvectParams &P, Cell3<typename Real<ST>::T,
         }
     }
     if constexpr (MET != kFlat) {
-        double mlon;  // M cos(lat)
-        if constexpr (MET == kSphLib)
-            mlon = kMetresPerDegree * cos(y * kDegToRad);
-        else if constexpr (MET == kSphTable2)
-            mlon = mcos_short(c.cl, c.sl, c.y0, y);
-        else
-            mlon = cos_series_m<MET>(c.cl, c.sl, c.y0, y, P);
-        k[0] = (double)v[0] * recip_stage(mlon);
+        k[0] = (double)v[0] * stage_metric<MET>(c, P, y);
         k[1] = (double)v[1] * (1.0 / kMetresPerDegree);
     } else {
         k[0] = (double)v[0];
