@@ -34,14 +34,18 @@ __device__ inline uint32_t xcd_block(uint32_t b, uint32_t nb)
     return x * q + (x < r ? x : r) + local;
 }
 
-// Cell search on one axis: the largest i in [0, n-2] with c[i] <= x, or false if x
-// is NaN or outside [c0, c(n-1)].  The guess (closed form for a uniform axis, a
-// bin table otherwise) is corrected against the stored coordinates, so the index
-// follows the stored grid exactly.
-__device__ inline bool locate(const AxisDev &a, double x, int &i, double &f)
+// What a reload reads in place of an absent per-cell table (no land mask, or no latitude
+// tables on a flat mesh): a zero in device memory, so that the read needs no branch and
+// goes out with the reload's other reads instead of after them.
+__device__ double kAbsentTable = 0.0;  // never written; not const, so it sits in global memory as the tables do
+
+// The cell search of a reload, in three phases that the reload runs across all three
+// axes before moving on, so that the axes' memory reads overlap: the guess (as in
+// locate), one 16-byte read of the guessed cell's two faces c[g] and c[g + 1], and the
+// correction against them.  The result is locate's index, with the faces of its cell.
+// x must lie in [c0, c(n-1)].
+__device__ inline int axis_guess(const AxisDev &a, double x)
 {
-    if (!(x >= a.lo && x <= a.hi))
-        return false;
     int g;
     if (a.uniform) {
         g = (int)((x - a.lo) * a.ginv);
@@ -50,13 +54,76 @@ __device__ inline bool locate(const AxisDev &a, double x, int &i, double &f)
         b = b < kGuessBins - 1 ? b : kGuessBins - 1;
         g = a.guess[b];
     }
-    g = g < 0 ? 0 : (g > a.n - 2 ? a.n - 2 : g);
-    while (g > 0 && a.c[g] > x)
+    return g < 0 ? 0 : (g > a.n - 2 ? a.n - 2 : g);
+}
+
+__device__ inline void axis_faces(const AxisDev &a, int g, double &lo, double &hi)
+{
+    // 8-byte alignment suffices for a global vector load
+    typedef double FacePair __attribute__((ext_vector_type(2), aligned(8)));
+    const FacePair p = *reinterpret_cast<const FacePair *>(a.c + g);
+    lo = p.x;
+    hi = p.y;
+}
+
+__device__ inline void axis_correct(const AxisDev &a, double x, int &g, double &lo, double &hi)
+{
+    while (g > 0 && lo > x) {
         --g;
-    while (g < a.n - 2 && a.c[g + 1] <= x)
+        hi = lo;
+        lo = a.c[g];
+    }
+    while (g < a.n - 2 && hi <= x) {
         ++g;
-    i = g;
-    f = (x - a.c[g]) * a.rw[g];
+        lo = hi;
+        hi = a.c[g + 1];
+    }
+}
+
+// One axis's cell search split in two phases, so that a caller can run each phase
+// across all its axes and their reads overlap: find_start takes the guess and issues
+// the reads of the guessed cell (its faces, and its inverse width when the fraction is
+// wanted); find_finish corrects against the faces, reading the width again only if the
+// cell moved.  The result is the largest i in [0, n-2] with c[i] <= x, for x in
+// [c0, c(n-1)]; the guess (closed form for a uniform axis, a bin table otherwise) only
+// decides where the search starts, so the index follows the stored grid exactly.
+struct AxisFind {
+    int g, g0;
+    double lo, hi, rw;
+};
+
+__device__ inline bool on_axis(const AxisDev &a, double x) { return x >= a.lo && x <= a.hi; }
+
+template <bool FRAC>
+__device__ inline void find_start(const AxisDev &a, double x, AxisFind &s)
+{
+    s.g = s.g0 = axis_guess(a, x);
+    axis_faces(a, s.g, s.lo, s.hi);
+    if constexpr (FRAC)
+        s.rw = a.rw[s.g];
+}
+
+template <bool FRAC>
+__device__ inline void find_finish(const AxisDev &a, double x, AxisFind &s)
+{
+    axis_correct(a, x, s.g, s.lo, s.hi);
+    if constexpr (FRAC) {
+        if (s.g != s.g0)
+            s.rw = a.rw[s.g];
+    }
+}
+
+// Cell search on one axis: the cell index i and the fraction (x - c[i]) / (c[i+1] - c[i]),
+// or false if x is NaN or outside [c0, c(n-1)].
+__device__ inline bool locate(const AxisDev &a, double x, int &i, double &f)
+{
+    if (!on_axis(a, x))
+        return false;
+    AxisFind s;
+    find_start<true>(a, x, s);
+    find_finish<true>(a, x, s);
+    i = s.g;
+    f = (x - s.lo) * s.rw;
     return true;
 }
 
@@ -120,6 +187,40 @@ struct Cell {
     double xi, eta, zeta;
 };
 
+// The cell of a point (as locate on each axis), the axes searched together so that their
+// reads overlap; false if the point is outside the grid or NaN.  The fractions are
+// computed only if FRAC (else zero); in 2D, k and zeta are zero.
+template <bool IS3D, bool FRAC>
+__device__ inline bool locate_point(const GridDev &g, double x, double y, double z, Cell &c)
+{
+    if (!(on_axis(g.ax, x) && on_axis(g.ay, y) && (!IS3D || on_axis(g.az, z))))
+        return false;
+    AxisFind fx, fy, fz;
+    find_start<FRAC>(g.ax, x, fx);
+    find_start<FRAC>(g.ay, y, fy);
+    if constexpr (IS3D)
+        find_start<FRAC>(g.az, z, fz);
+    find_finish<FRAC>(g.ax, x, fx);
+    find_finish<FRAC>(g.ay, y, fy);
+    if constexpr (IS3D)
+        find_finish<FRAC>(g.az, z, fz);
+    c.i = fx.g;
+    c.j = fy.g;
+    c.k = IS3D ? fz.g : 0;
+    c.xi = FRAC ? (x - fx.lo) * fx.rw : 0.0;
+    c.eta = FRAC ? (y - fy.lo) * fy.rw : 0.0;
+    c.zeta = FRAC && IS3D ? (z - fz.lo) * fz.rw : 0.0;
+    return true;
+}
+
+// Whether cell (i, j) is land (false without a land mask); the read needs no branch.
+__device__ inline bool land_at(const GridDev &g, int i, int j)
+{
+    const uint8_t *p = g.landcell ? g.landcell + ((size_t)j * (size_t)(g.ax.n - 1) + (size_t)i)
+                                  : reinterpret_cast<const uint8_t *>(&kAbsentTable);
+    return *p != 0;
+}
+
 // Bilinear interpolation of level k in one slot: the four corner weights times the
 // corner values, summed in the order (0,0), (1,0), (1,1), (0,1).
 template <int ST, bool IS3D>
@@ -173,14 +274,8 @@ __device__ inline bool sample(const AdvectParams &P, const TimeEntry &te, double
 {
     using R = typename Real<ST>::T;
     Cell c;
-    if (!locate(P.g.ax, x, c.i, c.xi) || !locate(P.g.ay, y, c.j, c.eta))
+    if (!locate_point<IS3D, true>(P.g, x, y, z, c))
         return false;
-    c.k = 0;
-    c.zeta = 0.0;
-    if constexpr (IS3D) {
-        if (!locate(P.g.az, z, c.k, c.zeta))
-            return false;
-    }
     if (P.nearest) {
         c.xi = c.xi < 0.5 ? 0.0 : 1.0;
         c.eta = c.eta < 0.5 ? 0.0 : 1.0;
@@ -431,15 +526,10 @@ __device__ inline uint8_t rk4_step(const AdvectParams &P, int s, uint32_t id, do
         xs = xs + dx;
         ys = ys + dy;
     }
-    int ci, cj, ck;
-    double f;
-    if (!locate(P.g.ax, xs, ci, f) || !locate(P.g.ay, ys, cj, f))
+    Cell cs;
+    if (!locate_point<IS3D, false>(P.g, xs, ys, zs, cs))
         return ST_OOB;
-    if constexpr (IS3D) {
-        if (!locate(P.g.az, zs, ck, f))
-            return ST_OOB;
-    }
-    if (P.g.landcell && P.g.landcell[(size_t)cj * (size_t)(P.g.ax.n - 1) + (size_t)ci])
+    if (land_at(P.g, cs.i, cs.j))
         return ST_LAND;
     x = xs;
     y = ys;
@@ -454,14 +544,8 @@ __device__ inline bool sample_tracer(const AdvectParams &P, const TimeEntry &te,
                                      double y, double z, double &val)
 {
     Cell c;
-    if (!locate(P.g.ax, x, c.i, c.xi) || !locate(P.g.ay, y, c.j, c.eta))
+    if (!locate_point<IS3D, true>(P.g, x, y, z, c))
         return false;
-    c.k = 0;
-    c.zeta = 0.0;
-    if constexpr (IS3D) {
-        if (!locate(P.g.az, z, c.k, c.zeta))
-            return false;
-    }
     const size_t nx = (size_t)P.g.ax.n, plane = nx * (size_t)P.g.ay.n;
     auto level = [&](int slot, int k) {
         const float *F = P.f.tracer + ((size_t)slot * P.f.nzl + (size_t)k) * plane;
@@ -793,16 +877,12 @@ struct GatherLane {
         const double err = sqrt((ex * ex + ey * ey) + ev[2] * ev[2]);
         if (!rkf_accept(P, s, err, acc, rej))
             return false;
-        int ci, cj, ck;
-        double f;
-        bool out = !locate(P.g.ax, p4[0], ci, f) || !locate(P.g.ay, p4[1], cj, f);
-        if constexpr (IS3D)
-            out = out || !locate(P.g.az, p4[2], ck, f);
-        if (out) {
+        Cell cs;
+        if (!locate_point<IS3D, false>(P.g, p4[0], p4[1], p4[2], cs)) {
             s.st = (uint8_t)(ST_OOB | extra);
             return true;
         }
-        if (P.g.landcell && P.g.landcell[(size_t)cj * (size_t)(P.g.ax.n - 1) + (size_t)ci]) {
+        if (land_at(P.g, cs.i, cs.j)) {
             s.st = (uint8_t)(ST_LAND | extra);
             return true;
         }
@@ -936,23 +1016,20 @@ __device__ inline bool reload2(const AdvectParams &P, Cell2<typename Real<ST>::T
                                int sb, double x, double y)
 {
     using R = typename Real<ST>::T;
-    int i, j;
-    double f;
-    if (!locate(P.g.ax, x, i, f) || !locate(P.g.ay, y, j, f))
-        return false;
     const AxisDev &ax = P.g.ax, &ay = P.g.ay;
-    c.x0 = ax.c[i];
-    c.ux = (i == ax.n - 2) ? nextafter(ax.hi, __builtin_inf()) : ax.c[i + 1];
-    c.rx = ax.rw[i];
-    c.y0 = ay.c[j];
-    c.uy = (j == ay.n - 2) ? nextafter(ay.hi, __builtin_inf()) : ay.c[j + 1];
-    c.ry = ay.rw[j];
-    if (P.g.coslat) {
-        c.cl = kMetresPerDegree * P.g.coslat[j];
-        c.sl = kMetresPerDegree * P.g.sinlat[j];
-    }
+    if (!(x >= ax.lo && x <= ax.hi && y >= ay.lo && y <= ay.hi))
+        return false;
+    // the cell search of both axes in phases, then every read of the cell issued before
+    // any of its values is used (as in the 3D reload)
+    int i = axis_guess(ax, x), j = axis_guess(ay, y);
+    double xh, yh;
+    axis_faces(ax, i, c.x0, xh);
+    axis_faces(ay, j, c.y0, yh);
+    axis_correct(ax, x, i, c.x0, xh);
+    axis_correct(ay, y, j, c.y0, yh);
+    c.ux = (i == ax.n - 2) ? nextafter(ax.hi, __builtin_inf()) : xh;
+    c.uy = (j == ay.n - 2) ? nextafter(ay.hi, __builtin_inf()) : yh;
     const size_t nx = (size_t)ax.n;
-    c.land = P.g.landcell ? P.g.landcell[(size_t)j * (nx - 1) + (size_t)i] != 0 : false;
     const size_t n00 = (size_t)j * nx + (size_t)i;
     const char *base = static_cast<const char *>(P.f.slots);
     const char *A = base + (size_t)sa * P.f.slot_bytes;
@@ -962,14 +1039,22 @@ __device__ inline bool reload2(const AdvectParams &P, Cell2<typename Real<ST>::T
     load_node<ST, false>(A, n00 + 1, sca, p10);
     load_node<ST, false>(A, n00 + nx, sca, p01);
     load_node<ST, false>(A, n00 + nx + 1, sca, p11);
+    const char *B = base + (size_t)sb * P.f.slot_bytes;
+    const float *scb = ST == kF16S ? P.f.scales + (size_t)sb * P.f.nzl * 3 : nullptr;
+    R q00[3], q10[3], q01[3], q11[3];
     if constexpr (!STEADY) {
-        const char *B = base + (size_t)sb * P.f.slot_bytes;
-        const float *scb = ST == kF16S ? P.f.scales + (size_t)sb * P.f.nzl * 3 : nullptr;
-        R q00[3], q10[3], q01[3], q11[3];
         load_node<ST, false>(B, n00, scb, q00);
         load_node<ST, false>(B, n00 + 1, scb, q10);
         load_node<ST, false>(B, n00 + nx, scb, q01);
         load_node<ST, false>(B, n00 + nx + 1, scb, q11);
+    }
+    c.rx = ax.rw[i];
+    c.ry = ay.rw[j];
+    const double clat = *(P.g.coslat ? P.g.coslat + j : &kAbsentTable);
+    const double slat = *(P.g.coslat ? P.g.sinlat + j : &kAbsentTable);
+    const uint32_t land = *(P.g.landcell ? P.g.landcell + ((size_t)j * (nx - 1) + (size_t)i)
+                                         : reinterpret_cast<const uint8_t *>(&kAbsentTable));
+    if constexpr (!STEADY) {
 #pragma unroll
         for (int v = 0; v < 2; ++v) {
             R ca[4], cb[4];
@@ -994,6 +1079,9 @@ __device__ inline bool reload2(const AdvectParams &P, Cell2<typename Real<ST>::T
             }
         }
     }
+    c.cl = kMetresPerDegree * clat;
+    c.sl = kMetresPerDegree * slat;
+    c.land = land != 0;
     return true;
 }
 
@@ -1292,12 +1380,10 @@ __device__ inline long long advect_lane_2d(const AdvectParams &P, uint32_t k, ui
                     if (in_cell(c, P, xs, ys)) {
                         land = c.land;
                     } else {
-                        int ci, cj;
-                        double f;
-                        if (!locate(P.g.ax, xs, ci, f) || !locate(P.g.ay, ys, cj, f))
+                        Cell cs;
+                        if (!locate_point<false, false>(P.g, xs, ys, 0.0, cs))
                             goto fail;
-                        land = P.g.landcell &&
-                               P.g.landcell[(size_t)cj * (size_t)(P.g.ax.n - 1) + (size_t)ci];
+                        land = land_at(P.g, cs.i, cs.j);
                     }
                     if (land) {
                         err = ST_LAND;
@@ -1447,13 +1533,12 @@ struct CachedLane2 {
         if (in_cell(c, P, xs, ys)) {
             land = c.land;
         } else {
-            int ci, cj;
-            double f;
-            if (!locate(P.g.ax, xs, ci, f) || !locate(P.g.ay, ys, cj, f)) {
+            Cell cs;
+            if (!locate_point<false, false>(P.g, xs, ys, 0.0, cs)) {
                 s.st = (uint8_t)(ST_OOB | extra);
                 return true;
             }
-            land = P.g.landcell && P.g.landcell[(size_t)cj * (size_t)(P.g.ax.n - 1) + (size_t)ci];
+            land = land_at(P.g, cs.i, cs.j);
         }
         if (land) {
             s.st = (uint8_t)(ST_LAND | extra);
@@ -1711,66 +1796,83 @@ __device__ inline bool reload3(const AdvectParams &P, Cell3<typename Real<ST>::T
                                int sb, double x, double y, double z)
 {
     using R = typename Real<ST>::T;
-    int i, j, k;
-    double f;
-    if (!locate(P.g.ax, x, i, f) || !locate(P.g.ay, y, j, f) || !locate(P.g.az, z, k, f))
-        return false;
     const AxisDev &ax = P.g.ax, &ay = P.g.ay, &az = P.g.az;
-    c.x0 = ax.c[i];
-    c.ux = (i == ax.n - 2) ? nextafter(ax.hi, __builtin_inf()) : ax.c[i + 1];
-    c.rx = ax.rw[i];
-    c.y0 = ay.c[j];
-    c.uy = (j == ay.n - 2) ? nextafter(ay.hi, __builtin_inf()) : ay.c[j + 1];
-    c.ry = ay.rw[j];
-    c.z0 = az.c[k];
-    c.uz = (k == az.n - 2) ? nextafter(az.hi, __builtin_inf()) : az.c[k + 1];
-    c.rz = az.rw[k];
-    if (P.g.coslat) {
-        c.cl = kMetresPerDegree * P.g.coslat[j];
-        c.sl = kMetresPerDegree * P.g.sinlat[j];
-    }
+    if (!(x >= ax.lo && x <= ax.hi && y >= ay.lo && y <= ay.hi && z >= az.lo && z <= az.hi))
+        return false;
+    int i = axis_guess(ax, x), j = axis_guess(ay, y), k = axis_guess(az, z);
+    double xh, yh, zh;
+    axis_faces(ax, i, c.x0, xh);
+    axis_faces(ay, j, c.y0, yh);
+    axis_faces(az, k, c.z0, zh);
+    axis_correct(ax, x, i, c.x0, xh);
+    axis_correct(ay, y, j, c.y0, yh);
+    axis_correct(az, z, k, c.z0, zh);
+    c.ux = (i == ax.n - 2) ? nextafter(ax.hi, __builtin_inf()) : xh;
+    c.uy = (j == ay.n - 2) ? nextafter(ay.hi, __builtin_inf()) : yh;
+    c.uz = (k == az.n - 2) ? nextafter(az.hi, __builtin_inf()) : zh;
     const size_t nx = (size_t)ax.n, plane = nx * (size_t)ay.n;
-    c.land = P.g.landcell ? P.g.landcell[(size_t)j * (nx - 1) + (size_t)i] != 0 : false;
     const size_t n000 = (size_t)k * plane + (size_t)j * nx + (size_t)i;
     const size_t off[8] = {0, 1, nx, nx + 1, plane, plane + 1, plane + nx, plane + nx + 1};
     const char *base = static_cast<const char *>(P.f.slots);
     using W = typename NodeWord3<ST>::T;
-    // the eight nodes' raw words first, converted one variable at a time (fewer live
-    // registers than converting every node up front)
-    W w[8];
-    {
-        const W *A = reinterpret_cast<const W *>(base + (size_t)sa * P.f.slot_bytes);
-        const float *sc = ST == kF16S ? P.f.scales + ((size_t)sa * P.f.nzl + k) * 3 : nullptr;
+    // Every read of the reload is issued before any of its values is used, so that the
+    // reads overlap: the eight nodes' raw words of both snapshots, then the cell's widths,
+    // its latitude's cosine and sine and its land flag.  The words are converted one
+    // variable at a time (fewer live registers than converting every node up front).
+    const W *A = reinterpret_cast<const W *>(base + (size_t)sa * P.f.slot_bytes);
+    const W *B = reinterpret_cast<const W *>(base + (size_t)sb * P.f.slot_bytes);
+    // FP64 words (32 bytes) of both snapshots would hold 128 registers in flight: those
+    // read the second snapshot's after converting the first's
+    constexpr bool kBothAtOnce = !STEADY && sizeof(W) <= 16;
+    W wa[8], wb[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+        wa[q] = A[n000 + off[q]];
+    if constexpr (kBothAtOnce) {
 #pragma unroll
         for (int q = 0; q < 8; ++q)
-            w[q] = A[n000 + off[q]];
+            wb[q] = B[n000 + off[q]];
+    }
+    c.rx = ax.rw[i];
+    c.ry = ay.rw[j];
+    c.rz = az.rw[k];
+    const double clat = *(P.g.coslat ? P.g.coslat + j : &kAbsentTable);
+    const double slat = *(P.g.coslat ? P.g.sinlat + j : &kAbsentTable);
+    const uint32_t land = *(P.g.landcell ? P.g.landcell + ((size_t)j * (nx - 1) + (size_t)i)
+                                         : reinterpret_cast<const uint8_t *>(&kAbsentTable));
+    {
+        const float *sc = ST == kF16S ? P.f.scales + ((size_t)sa * P.f.nzl + k) * 3 : nullptr;
 #pragma unroll
         for (int v = 0; v < 3; ++v) {
             R f[8];
 #pragma unroll
             for (int q = 0; q < 8; ++q)
-                f[q] = node_var<ST>(w[q], v, sc + (q >> 2) * 3);
+                f[q] = node_var<ST>(wa[q], v, sc + (q >> 2) * 3);
             coeffs3<R>(f, c.a[v]);
         }
     }
     if constexpr (!STEADY) {
-        const W *B = reinterpret_cast<const W *>(base + (size_t)sb * P.f.slot_bytes);
-        const float *sc = ST == kF16S ? P.f.scales + ((size_t)sb * P.f.nzl + k) * 3 : nullptr;
+        if constexpr (!kBothAtOnce) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q)
-            w[q] = B[n000 + off[q]];
+            for (int q = 0; q < 8; ++q)
+                wb[q] = B[n000 + off[q]];
+        }
+        const float *sc = ST == kF16S ? P.f.scales + ((size_t)sb * P.f.nzl + k) * 3 : nullptr;
 #pragma unroll
         for (int v = 0; v < 3; ++v) {
             R f[8], cb[8];
 #pragma unroll
             for (int q = 0; q < 8; ++q)
-                f[q] = node_var<ST>(w[q], v, sc + (q >> 2) * 3);
+                f[q] = node_var<ST>(wb[q], v, sc + (q >> 2) * 3);
             coeffs3<R>(f, cb);
 #pragma unroll
             for (int q = 0; q < 8; ++q)
                 c.d(v, q) = cb[q] - c.a[v][q];
         }
     }
+    c.cl = kMetresPerDegree * clat;
+    c.sl = kMetresPerDegree * slat;
+    c.land = land != 0;
     return true;
 }
 
@@ -1909,13 +2011,10 @@ __attribute__((amdgpu_waves_per_eu(cache3_lds<ST, STEADY, MET, BROWN>() ? (sizeo
                     if (in_cell3(c, P, xs, ys, zs)) {
                         land = c.land;
                     } else {
-                        int ci, cj, ck;
-                        double f;
-                        if (!locate(P.g.ax, xs, ci, f) || !locate(P.g.ay, ys, cj, f) ||
-                            !locate(P.g.az, zs, ck, f))
+                        Cell cs;
+                        if (!locate_point<true, false>(P.g, xs, ys, zs, cs))
                             goto fail;
-                        land = P.g.landcell &&
-                               P.g.landcell[(size_t)cj * (size_t)(P.g.ax.n - 1) + (size_t)ci];
+                        land = land_at(P.g, cs.i, cs.j);
                     }
                     if (land) {
                         err = ST_LAND;
