@@ -213,12 +213,19 @@ __device__ inline bool locate_point(const GridDev &g, double x, double y, double
     return true;
 }
 
-// Whether cell (i, j) is land (false without a land mask); the read needs no branch.
-__device__ inline bool land_at(const GridDev &g, int i, int j)
+// The status a step's end point takes: ST_OOB off the grid (or NaN), ST_LAND in a land
+// cell, else 0.  Without a land mask (a branch uniform across the launch) only the
+// bounds matter and no memory is read; with one, only the horizontal cell is searched.
+template <bool IS3D>
+__device__ inline uint8_t point_status(const GridDev &g, double x, double y, double z)
 {
-    const uint8_t *p = g.landcell ? g.landcell + ((size_t)j * (size_t)(g.ax.n - 1) + (size_t)i)
-                                  : reinterpret_cast<const uint8_t *>(&kAbsentTable);
-    return *p != 0;
+    if (!(on_axis(g.ax, x) && on_axis(g.ay, y) && (!IS3D || on_axis(g.az, z))))
+        return ST_OOB;
+    if (!g.landcell)
+        return 0;
+    Cell cs;
+    locate_point<false, false>(g, x, y, 0.0, cs);
+    return g.landcell[(size_t)cs.j * (size_t)(g.ax.n - 1) + (size_t)cs.i] ? ST_LAND : 0;
 }
 
 // Bilinear interpolation of level k in one slot: the four corner weights times the
@@ -526,11 +533,8 @@ __device__ inline uint8_t rk4_step(const AdvectParams &P, int s, uint32_t id, do
         xs = xs + dx;
         ys = ys + dy;
     }
-    Cell cs;
-    if (!locate_point<IS3D, false>(P.g, xs, ys, zs, cs))
-        return ST_OOB;
-    if (land_at(P.g, cs.i, cs.j))
-        return ST_LAND;
+    if (const uint8_t e = point_status<IS3D>(P.g, xs, ys, zs))
+        return e;
     x = xs;
     y = ys;
     z = zs;
@@ -877,13 +881,8 @@ struct GatherLane {
         const double err = sqrt((ex * ex + ey * ey) + ev[2] * ev[2]);
         if (!rkf_accept(P, s, err, acc, rej))
             return false;
-        Cell cs;
-        if (!locate_point<IS3D, false>(P.g, p4[0], p4[1], p4[2], cs)) {
-            s.st = (uint8_t)(ST_OOB | extra);
-            return true;
-        }
-        if (land_at(P.g, cs.i, cs.j)) {
-            s.st = (uint8_t)(ST_LAND | extra);
+        if (const uint8_t e = point_status<IS3D>(P.g, p4[0], p4[1], p4[2])) {
+            s.st = (uint8_t)(e | extra);
             return true;
         }
         p[0] = p4[0];
@@ -1380,10 +1379,10 @@ __device__ inline long long advect_lane_2d(const AdvectParams &P, uint32_t k, ui
                     if (in_cell(c, P, xs, ys)) {
                         land = c.land;
                     } else {
-                        Cell cs;
-                        if (!locate_point<false, false>(P.g, xs, ys, 0.0, cs))
+                        const uint8_t e = point_status<false>(P.g, xs, ys, 0.0);
+                        if (e & ST_OOB)
                             goto fail;
-                        land = land_at(P.g, cs.i, cs.j);
+                        land = e != 0;
                     }
                     if (land) {
                         err = ST_LAND;
@@ -1533,12 +1532,12 @@ struct CachedLane2 {
         if (in_cell(c, P, xs, ys)) {
             land = c.land;
         } else {
-            Cell cs;
-            if (!locate_point<false, false>(P.g, xs, ys, 0.0, cs)) {
+            const uint8_t e = point_status<false>(P.g, xs, ys, 0.0);
+            if (e & ST_OOB) {
                 s.st = (uint8_t)(ST_OOB | extra);
                 return true;
             }
-            land = land_at(P.g, cs.i, cs.j);
+            land = e != 0;
         }
         if (land) {
             s.st = (uint8_t)(ST_LAND | extra);
@@ -2011,10 +2010,10 @@ __attribute__((amdgpu_waves_per_eu(cache3_lds<ST, STEADY, MET, BROWN>() ? (sizeo
                     if (in_cell3(c, P, xs, ys, zs)) {
                         land = c.land;
                     } else {
-                        Cell cs;
-                        if (!locate_point<true, false>(P.g, xs, ys, zs, cs))
+                        const uint8_t e = point_status<true>(P.g, xs, ys, zs);
+                        if (e & ST_OOB)
                             goto fail;
-                        land = land_at(P.g, cs.i, cs.j);
+                        land = e != 0;
                     }
                     if (land) {
                         err = ST_LAND;
