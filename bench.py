@@ -69,15 +69,15 @@ STATE_BYTES_RKF45_2D = STATE_BYTES_2D + 2  # plus the step exponent read and wri
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 COUNTER_SOURCE = "profiles/counters_k_advect2d_cfg1_k_advect3d_cfg2.md"
 COUNTERS = {
-    "advect_sha256": "83907a747c166e8c71995ab9c93968b11ef179a45b12a09ce68b724fd714957b",
-    "cfg1": (212773.0, 64599.4),    # (FETCH_SIZE KiB, WRITE_SIZE KiB) per launch of k_advect2d
-    "cfg2": (7853230.0, 404184.0),  # the same for k_advect3d
+    "advect_sha256": "da1c1c334bf60d756e2c758f8fdd1b91e57afd4d4605399173074784d98a887f",
+    "cfg1": (214055.0, 64593.9),    # (FETCH_SIZE KiB, WRITE_SIZE KiB) per launch of k_advect2d
+    "cfg2": (7773550.0, 247858.0),  # the same for k_advect3d
     # (TCC_HIT_sum, TCC_MISS_sum) per launch: L2 requests of the same kernels
-    "cfg1_l2": (4149550.0, 4976860.0),
-    "cfg2_l2": (80338000.0, 128049000.0),
+    "cfg1_l2": (4149150.0, 4993780.0),
+    "cfg2_l2": (78351100.0, 126534000.0),
     # (SQ_INSTS_VALU, SQ_INSTS_SALU) wave instructions per launch
-    "cfg1_sq": (8.49591e8, 5.2505e8),
-    "cfg2_sq": (9.25156e9, 6.40249e9),
+    "cfg1_sq": (8.45759e8, 4.7574e8),
+    "cfg2_sq": (9.24136e9, 6.32932e9),
 }
 
 
