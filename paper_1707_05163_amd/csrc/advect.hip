@@ -1968,10 +1968,15 @@ __attribute__((amdgpu_waves_per_eu(cache3_lds<ST, STEADY, MET, BROWN>() ? (sizeo
                 double k[3] = {0.0, 0.0, 0.0}, sm[3] = {0.0, 0.0, 0.0};
                 const int nst = P.scheme ? 1 : 4;
                 bool ok = true;  // as in 2D: a failed stage leaves its slope, the step fails
-                // FP32 coefficients leave the registers for the four stages side by side
-                // (+11% on the BF16 and FP16 forms); with FP64 ones the unrolled stages
-                // spill and lose 8-23%
-                constexpr int kUnroll = sizeof(R) == 4 ? 4 : 1;
+                // The four stages side by side: with FP32 coefficients (+11% on the BF16
+                // and FP16 forms), and with FP64 ones for FP32 fields in the 2-term and flat
+                // metric modes without the behaviour or Brownian terms (+8.7% on cfg2, no
+                // spill in the loop). The other FP64 forms spill more unrolled (the
+                // behaviour kernels lost 1.9%, the 3/4-term series spills 92 B), so they
+                // keep the rolled loop.
+                constexpr bool kUnrollF64 = ST == kF32 && !BEHAVE && !BROWN &&
+                                            (MET == kSphTable2 || MET == kFlat);
+                constexpr int kUnroll = sizeof(R) == 4 || kUnrollF64 ? 4 : 1;
 #pragma unroll kUnroll
                 for (int q = 0; q < nst; ++q) {
                     const TimeEntry e = q == 0 ? e0 : (q == 3 ? e2 : e1);
