@@ -69,15 +69,15 @@ STATE_BYTES_RKF45_2D = STATE_BYTES_2D + 2  # plus the step exponent read and wri
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 COUNTER_SOURCE = "profiles/counters_k_advect2d_cfg1_k_advect3d_cfg2.md"
 COUNTERS = {
-    "advect_sha256": "da1c1c334bf60d756e2c758f8fdd1b91e57afd4d4605399173074784d98a887f",
-    "cfg1": (214055.0, 64593.9),    # (FETCH_SIZE KiB, WRITE_SIZE KiB) per launch of k_advect2d
-    "cfg2": (7773550.0, 247858.0),  # the same for k_advect3d
+    "advect_sha256": "1feb777324ffa39c86b8a53d070739a40051dd44c5455a494f78a526acfd2e24",
+    "cfg1": (213467.0, 64592.1),    # (FETCH_SIZE KiB, WRITE_SIZE KiB) per launch of k_advect2d
+    "cfg2": (7800440.0, 287141.0),  # the same for k_advect3d
     # (TCC_HIT_sum, TCC_MISS_sum) per launch: L2 requests of the same kernels
-    "cfg1_l2": (4149150.0, 4993780.0),
-    "cfg2_l2": (78351100.0, 126534000.0),
+    "cfg1_l2": (4153630.0, 4991570.0),
+    "cfg2_l2": (77294500.0, 127025000.0),
     # (SQ_INSTS_VALU, SQ_INSTS_SALU) wave instructions per launch
-    "cfg1_sq": (8.45759e8, 4.7574e8),
-    "cfg2_sq": (9.24136e9, 6.32932e9),
+    "cfg1_sq": (8.45754e8, 4.75737e8),
+    "cfg2_sq": (8.85594e9, 3.32503e9),
 }
 
 
