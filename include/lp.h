@@ -384,7 +384,7 @@ typedef struct {
  * taking the network's displacement where it agrees with RK4 over the segment in
  * two steps to within residual_m metres and ends inside the grid off land, and
  * re-integrating every other particle with the fine RK4 steps (plain RK4 is the
- * fallback and the judge).  Synchronises. */
+ * fallback and the arbiter).  Synchronises. */
 int pset_execute_surrogate(lp_pset *ps, lp_model *m, double runtime, double dt,
                            int32_t steps_per_segment, double residual_m,
                            lp_surrogate_stats *st, void *stream);

@@ -3,7 +3,7 @@ INFRASTRUCTURE ONLY (the tests import it; the product library never does).
 
 The surrogate is not in the paper: it is a learned stand-in for a fixed number of
 RK4 steps of the method (Sect. 2.1.1, Eq. 1), with plain RK4 as the fallback and
-the judge.  This module restates, in FP64 with numpy, what its two steps around the
+the arbiter.  This module restates, in FP64 with numpy, what its two steps around the
 network compute, from their definitions:
 
 features(fs, x, y, t) -- the network's 64 input values per position (before the

@@ -1,6 +1,6 @@
 // surrogate.hip -- learned flow map: an MLP that predicts the displacement of a
 // particle over one segment of fine RK4 steps, trained on segments that the RK4
-// advection itself produces, and used with plain RK4 as the judge: a particle whose
+// advection itself produces, and used with plain RK4 as the arbiter: a particle whose
 // prediction disagrees with a coarse RK4 estimate by more than a threshold (or
 // whose predicted end point is outside the grid or on land) is re-integrated with
 // the fine RK4 steps.

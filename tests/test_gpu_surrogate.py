@@ -1,5 +1,5 @@
 """Flow-map surrogate end to end: training on RK4 segments, inference with the
-residual check and the RK4 fallback (plain RK4 stays the judge)."""
+residual check and the RK4 fallback (plain RK4 stays the arbiter)."""
 
 import numpy as np
 import pytest
