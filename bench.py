@@ -69,15 +69,15 @@ STATE_BYTES_RKF45_2D = STATE_BYTES_2D + 2  # plus the step exponent read and wri
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 COUNTER_SOURCE = "profiles/counters_k_advect2d_cfg1_k_advect3d_cfg2.md"
 COUNTERS = {
-    "advect_sha256": "1feb777324ffa39c86b8a53d070739a40051dd44c5455a494f78a526acfd2e24",
-    "cfg1": (213467.0, 64592.1),    # (FETCH_SIZE KiB, WRITE_SIZE KiB) per launch of k_advect2d
-    "cfg2": (7800440.0, 287141.0),  # the same for k_advect3d
+    "advect_sha256": "3b29ef1ce59bc5aaf5d3398153a1a7abb04fd5e9bc6767ee7fa8c058ba1eaecf",
+    "cfg1": (213566.3, 64598.0),    # (FETCH_SIZE KiB, WRITE_SIZE KiB) per launch of k_advect2d
+    "cfg2": (7800521.3, 287229.8),  # the same for k_advect3d
     # (TCC_HIT_sum, TCC_MISS_sum) per launch: L2 requests of the same kernels
-    "cfg1_l2": (4153630.0, 4991570.0),
-    "cfg2_l2": (77294500.0, 127025000.0),
+    "cfg1_l2": (4152082.1, 4983464.2),
+    "cfg2_l2": (77297680.8, 127023737.2),
     # (SQ_INSTS_VALU, SQ_INSTS_SALU) wave instructions per launch
-    "cfg1_sq": (8.45754e8, 4.75737e8),
-    "cfg2_sq": (8.85594e9, 3.32503e9),
+    "cfg1_sq": (8.45762e+08, 4.75741e+08),
+    "cfg2_sq": (8.85592e+09, 3.32502e+09),
 }
 
 
