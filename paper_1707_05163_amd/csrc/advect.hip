@@ -1813,6 +1813,8 @@ struct Cell3 {
     R *dl;                  // LDS slot (DL): variable v at [8 v .. 8 v + 7]
     bool land;
     __device__ R &d(int v, int q) { return DL ? dl[8 * v + q] : dr[DL ? 0 : v][q]; }
+    // (DL) the cell's depth index, kept in the slot's padding after the coefficients
+    __device__ int &kidx() { return *reinterpret_cast<int *>(dl + 24); }
     // as for the 2D cell: an empty x range until the next reload
     __device__ void invalidate()
     {
@@ -1898,17 +1900,31 @@ __device__ inline bool reload3(const AdvectParams &P, Cell3<typename Real<ST>::T
     const AxisDev &ax = P.g.ax, &ay = P.g.ay, &az = P.g.az;
     if (!(x >= ax.lo && x <= ax.hi && y >= ay.lo && y <= ay.hi && z >= az.lo && z <= az.hi))
         return false;
-    int i = axis_guess(ax, x), j = axis_guess(ay, y), k = axis_guess(az, z);
-    double xh, yh, zh;
+    // A point still between the cached cell's depth faces keeps its level (most cell
+    // changes are horizontal), which spares the depth axis's bin-table guess and face
+    // reads, the longest chain of the search on a non-uniform axis.  The level sits in
+    // the LDS slot, so only the LDS-cached forms keep it.
+    const bool keep_k = DL && z >= c.z0 && z < c.uz;
+    int i = axis_guess(ax, x), j = axis_guess(ay, y), k = 0;
+    double xh, yh, zh = 0.0;
+    if (keep_k)
+        k = c.kidx();
+    else
+        k = axis_guess(az, z);
     axis_faces(ax, i, c.x0, xh);
     axis_faces(ay, j, c.y0, yh);
-    axis_faces(az, k, c.z0, zh);
+    if (!keep_k)
+        axis_faces(az, k, c.z0, zh);
     axis_correct(ax, x, i, c.x0, xh);
     axis_correct(ay, y, j, c.y0, yh);
-    axis_correct(az, z, k, c.z0, zh);
+    if (!keep_k) {
+        axis_correct(az, z, k, c.z0, zh);
+        c.uz = (k == az.n - 2) ? nextafter(az.hi, __builtin_inf()) : zh;
+    }
+    if constexpr (DL)
+        c.kidx() = k;
     c.ux = (i == ax.n - 2) ? nextafter(ax.hi, __builtin_inf()) : xh;
     c.uy = (j == ay.n - 2) ? nextafter(ay.hi, __builtin_inf()) : yh;
-    c.uz = (k == az.n - 2) ? nextafter(az.hi, __builtin_inf()) : zh;
     const size_t nx = (size_t)ax.n, plane = nx * (size_t)ay.n;
     const size_t n000 = (size_t)k * plane + (size_t)j * nx + (size_t)i;
     const size_t off[8] = {0, 1, nx, nx + 1, plane, plane + 1, plane + nx, plane + nx + 1};
