@@ -69,15 +69,15 @@ STATE_BYTES_RKF45_2D = STATE_BYTES_2D + 2  # plus the step exponent read and wri
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 COUNTER_SOURCE = "profiles/counters_k_advect2d_cfg1_k_advect3d_cfg2.md"
 COUNTERS = {
-    "advect_sha256": "3b29ef1ce59bc5aaf5d3398153a1a7abb04fd5e9bc6767ee7fa8c058ba1eaecf",
-    "cfg1": (213566.3, 64598.0),    # (FETCH_SIZE KiB, WRITE_SIZE KiB) per launch of k_advect2d
-    "cfg2": (7800521.3, 287229.8),  # the same for k_advect3d
+    "advect_sha256": "4f415dfae5070fdf2f740c4723246c2f781a90c220fac555e8ff99248e601b13",
+    "cfg1": (213701.8, 64596.5),    # (FETCH_SIZE KiB, WRITE_SIZE KiB) per launch of k_advect2d
+    "cfg2": (7802155.6, 286896.6),  # the same for k_advect3d
     # (TCC_HIT_sum, TCC_MISS_sum) per launch: L2 requests of the same kernels
-    "cfg1_l2": (4152082.1, 4983464.2),
-    "cfg2_l2": (77297680.8, 127023737.2),
+    "cfg1_l2": (4139567.4, 4982832.2),
+    "cfg2_l2": (72250979.8, 127044841.7),
     # (SQ_INSTS_VALU, SQ_INSTS_SALU) wave instructions per launch
-    "cfg1_sq": (8.45762e+08, 4.75741e+08),
-    "cfg2_sq": (8.85592e+09, 3.32502e+09),
+    "cfg1_sq": (8.45753e+08, 4.75736e+08),
+    "cfg2_sq": (8.78683e+09, 3.32526e+09),
 }
 
 
