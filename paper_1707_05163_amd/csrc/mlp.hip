@@ -220,60 +220,77 @@ __device__ inline uint32_t pack_bf16(float a, float b)
     return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2_t{a, b}, bf16x2_t));
 }
 
-// one layer: K inputs (16-wide k-steps in `in`), N (padded) outputs; the accumulators
-// start from the biases of the features each lane holds
-template <int K, int N>
-__device__ inline void fused_layer(const uint16_t *wl, const float *bl, int r, int h,
-                                   const bf16x8 (&in)[16], f32x16 (&acc)[8])
+// One 32-feature output block nb of a layer with K inputs (16-wide k-steps in `in`):
+// the accumulator starts from the biases of the features the lane holds and takes the
+// K/16 products in k order.
+template <int K>
+__device__ inline f32x16 fused_block(const uint16_t *wl, const float *bl, int r, int h, int nb,
+                                     const bf16x8 (&in)[16])
 {
+    f32x16 acc;
 #pragma unroll
-    for (int nb = 0; nb < N / 32; ++nb) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const float4 b = *reinterpret_cast<const float4 *>(bl + nb * 32 + 8 * q + 4 * h);
-            acc[nb][4 * q + 0] = b.x;
-            acc[nb][4 * q + 1] = b.y;
-            acc[nb][4 * q + 2] = b.z;
-            acc[nb][4 * q + 3] = b.w;
-        }
+    for (int q = 0; q < 4; ++q) {
+        const float4 b = *reinterpret_cast<const float4 *>(bl + nb * 32 + 8 * q + 4 * h);
+        acc[4 * q + 0] = b.x;
+        acc[4 * q + 1] = b.y;
+        acc[4 * q + 2] = b.z;
+        acc[4 * q + 3] = b.w;
     }
 #pragma unroll
     for (int s = 0; s < K / 16; ++s) {
-#pragma unroll
-        for (int nb = 0; nb < N / 32; ++nb) {
-            const bf16x8 w =
-                *reinterpret_cast<const bf16x8 *>(wl + (nb * 32 + r) * kLdsStride + 16 * s + 8 * h);
-            acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, in[s], acc[nb], 0, 0, 0);
-        }
+        const bf16x8 w =
+            *reinterpret_cast<const bf16x8 *>(wl + (nb * 32 + r) * kLdsStride + 16 * s + 8 * h);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, in[s], acc, 0, 0, 0);
     }
+    return acc;
 }
 
-// GELU + bf16, then the half-wave exchange into the next layer's operands
-__device__ inline void fused_hidden_epilogue(const f32x16 (&acc)[8], bf16x8 (&in)[16])
+// GELU + bf16 of one output block, then the half-wave exchange into the next layer's
+// two operands for these 32 features
+__device__ inline void block_epilogue(const f32x16 &acc, bf16x8 &o0, bf16x8 &o1)
 {
+    float g[16];
 #pragma unroll
-    for (int nb = 0; nb < 8; ++nb) {
-        float g[16];
+    for (int v = 0; v < 16; ++v)
+        g[v] = gelu_sigmoid(acc[v]);
+    uint32_t P[8];
 #pragma unroll
-        for (int v = 0; v < 16; ++v)
-            g[v] = gelu_sigmoid(acc[nb][v]);
-        uint32_t P[8];
+    for (int j = 0; j < 8; ++j)
+        P[j] = pack_bf16(g[2 * j], g[2 * j + 1]);
+    // lanes 32-63 of the first register trade places with lanes 0-31 of the second
 #pragma unroll
-        for (int j = 0; j < 8; ++j)
-            P[j] = pack_bf16(g[2 * j], g[2 * j + 1]);
-        // lanes 32-63 of the first register trade places with lanes 0-31 of the second
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            auto lo = __builtin_amdgcn_permlane32_swap(P[j], P[j + 2], false, false);
-            P[j] = lo[0];
-            P[j + 2] = lo[1];
-            auto hi = __builtin_amdgcn_permlane32_swap(P[j + 4], P[j + 6], false, false);
-            P[j + 4] = hi[0];
-            P[j + 6] = hi[1];
-        }
-        in[2 * nb] = __builtin_bit_cast(bf16x8, u32x4_t{P[0], P[1], P[2], P[3]});
-        in[2 * nb + 1] = __builtin_bit_cast(bf16x8, u32x4_t{P[4], P[5], P[6], P[7]});
+    for (int j = 0; j < 2; ++j) {
+        auto lo = __builtin_amdgcn_permlane32_swap(P[j], P[j + 2], false, false);
+        P[j] = lo[0];
+        P[j + 2] = lo[1];
+        auto hi = __builtin_amdgcn_permlane32_swap(P[j + 4], P[j + 6], false, false);
+        P[j + 4] = hi[0];
+        P[j + 6] = hi[1];
     }
+    o0 = __builtin_bit_cast(bf16x8, u32x4_t{P[0], P[1], P[2], P[3]});
+    o1 = __builtin_bit_cast(bf16x8, u32x4_t{P[4], P[5], P[6], P[7]});
+}
+
+// A hidden layer of 256 outputs, block by block: the epilogue of one block is written
+// beside the products of the next, so that the wave's GELU arithmetic runs while the
+// matrix core works (the products of a block depend only on the layer's inputs), and
+// only two accumulators are live instead of eight.
+template <int K>
+__device__ inline void hidden_layer(const uint16_t *wl, const float *bl, int r, int h,
+                                    bf16x8 (&in)[16])
+{
+    bf16x8 out[16];
+    f32x16 cur = fused_block<K>(wl, bl, r, h, 0, in);
+#pragma unroll
+    for (int nb = 1; nb < 8; ++nb) {
+        const f32x16 next = fused_block<K>(wl, bl, r, h, nb, in);
+        block_epilogue(cur, out[2 * nb - 2], out[2 * nb - 1]);
+        cur = next;
+    }
+    block_epilogue(cur, out[14], out[15]);
+#pragma unroll
+    for (int s = 0; s < 16; ++s)
+        in[s] = out[s];
 }
 
 __device__ inline void stage_layer(uint16_t *wl, float *bl, const uint16_t *WT, const float *bias,
@@ -302,26 +319,23 @@ __global__ __launch_bounds__(kFusedThreads) void k_mlp_fused(MlpFusedArgs a)
         const int64_t row = tile * kFusedRows + wave * 32 + r;
         const bool live = row < a.rows;
         bf16x8 in[16];
-        f32x16 acc[8];
 #pragma unroll
         for (int s = 0; s < 4; ++s)
             in[s] = live ? *reinterpret_cast<const bf16x8 *>(a.X + row * 64 + 16 * s + 8 * h)
                          : bf16x8{};
         stage_layer(wl, bl, a.WT[0], a.bias[0], 256, 64);
-        fused_layer<64, 256>(wl, bl, r, h, in, acc);
-        fused_hidden_epilogue(acc, in);
+        hidden_layer<64>(wl, bl, r, h, in);
 #pragma unroll 1
         for (int l = 1; l < 4; ++l) {
             stage_layer(wl, bl, a.WT[l], a.bias[l], 256, 256);
-            fused_layer<256, 256>(wl, bl, r, h, in, acc);
-            fused_hidden_epilogue(acc, in);
+            hidden_layer<256>(wl, bl, r, h, in);
         }
         stage_layer(wl, bl, a.WT[4], a.bias[4], 32, 256);
-        fused_layer<256, 32>(wl, bl, r, h, in, acc);
+        const f32x16 y = fused_block<256>(wl, bl, r, h, 0, in);
         // outputs 0 and 1 of the row sit in values 0 and 1 of the lower half-wave
         if (live && h == 0) {
-            a.Y[row * 2 + 0] = acc[0][0];
-            a.Y[row * 2 + 1] = acc[0][1];
+            a.Y[row * 2 + 0] = y[0];
+            a.Y[row * 2 + 1] = y[1];
         }
     }
 }
