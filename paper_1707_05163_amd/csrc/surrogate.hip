@@ -157,33 +157,40 @@ __global__ void k_features(FeatArgs a)
     if (r >= a.npad)
         return;
     const int64_t n = a.n_dev ? (int64_t)*a.n_dev : a.n;
-    uint16_t *row = a.X + r * kIn;
+    // the row is assembled as 32 pairs of bfloat16 (feature 2m in the low half) and
+    // written with eight 16-byte stores
+    static_assert(kIn == 64, "a row is 32 bf16 pairs");
+    uint4 *dst = reinterpret_cast<uint4 *>(a.X + r * kIn);
     if (r >= n) {
-        for (int q = 0; q < kIn; ++q)
-            row[q] = 0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            dst[q] = uint4{0u, 0u, 0u, 0u};
         if (a.T) {
             a.T[2 * r] = 0.f;
             a.T[2 * r + 1] = 0.f;
         }
         return;
     }
+    auto pair = [](float lo, float hi) {
+        return (uint32_t)to_bf16(lo) | ((uint32_t)to_bf16(hi) << 16);
+    };
+    uint32_t P[32];
     const uint32_t s = a.sel ? a.sel[r] : (uint32_t)r;
     const uint32_t rd = a.round ? a.round[s] : 0u;
     const TimeEntry e = a.tab[rd];
     const double x = a.x[s], y = a.y[s];
     const float t = (float)e.tau;
-    row[0] = to_bf16((float)(x / 180.0));
-    row[1] = to_bf16((float)(y / 90.0));
-    row[2] = to_bf16(a.phase[2 * rd]);
-    row[3] = to_bf16(a.phase[2 * rd + 1]);
+    P[0] = pair((float)(x / 180.0), (float)(y / 90.0));
+    P[1] = pair(a.phase[2 * rd], a.phase[2 * rd + 1]);
     double fx, fy;
     const int ci = cell_frac(a.g.ax, x, fx), cj = cell_frac(a.g.ay, y, fy);
     const int i0 = fx < 0.5 ? ci : ci + 1, j0 = fy < 0.5 ? cj : cj + 1;
     const int nx = a.g.ax.n, ny = a.g.ay.n;
-    int q = 4;
+#pragma unroll
     for (int dj = -2; dj <= 2; ++dj) {
         int jj = j0 + dj;
         jj = jj < 0 ? 0 : (jj > ny - 1 ? ny - 1 : jj);
+#pragma unroll
         for (int di = -2; di <= 2; ++di) {
             int ii = i0 + di;
             ii = ii < 0 ? 0 : (ii > nx - 1 ? nx - 1 : ii);
@@ -191,17 +198,16 @@ __global__ void k_features(FeatArgs a)
             float ua, va, ub, vb;
             node_uv(a.f, e.sa, node, ua, va, a.store);
             node_uv(a.f, e.sb, node, ub, vb, a.store);
-            row[q++] = to_bf16(ua + t * (ub - ua));
-            row[q++] = to_bf16(va + t * (vb - va));
+            P[2 + 5 * (dj + 2) + (di + 2)] = pair(ua + t * (ub - ua), va + t * (vb - va));
         }
     }
-    row[54] = to_bf16((float)(fx < 0.5 ? fx : fx - 1.0));
-    row[55] = to_bf16((float)(fy < 0.5 ? fy : fy - 1.0));
+    P[27] = pair((float)(fx < 0.5 ? fx : fx - 1.0), (float)(fy < 0.5 ? fy : fy - 1.0));
     float up = 0.f, vp = 0.f;
     const float w[4] = {(float)((1 - fx) * (1 - fy)), (float)(fx * (1 - fy)),
                         (float)((1 - fx) * fy), (float)(fx * fy)};
     const size_t c00 = (size_t)cj * nx + ci;
     const size_t cn[4] = {c00, c00 + 1, c00 + nx, c00 + nx + 1};
+#pragma unroll
     for (int k = 0; k < 4; ++k) {
         float ua, va, ub, vb;
         node_uv(a.f, e.sa, cn[k], ua, va, a.store);
@@ -209,17 +215,18 @@ __global__ void k_features(FeatArgs a)
         up += w[k] * (ua + t * (ub - ua));
         vp += w[k] * (va + t * (vb - va));
     }
-    row[56] = to_bf16(up);
-    row[57] = to_bf16(vp);
+    P[28] = pair(up, vp);
     double hx = a.g.ax.c[ci + 1] - a.g.ax.c[ci], hy = a.g.ay.c[cj + 1] - a.g.ay.c[cj];
     if (a.g.spherical) {
         hx *= lp::kMetresPerDegree * cos(y * lp::kDegToRad);
         hy *= lp::kMetresPerDegree;
     }
-    row[58] = to_bf16((float)(hx / 30000.0));
-    row[59] = to_bf16((float)(hy / 30000.0));
-    for (q = 60; q < kIn; ++q)
-        row[q] = 0;
+    P[29] = pair((float)(hx / 30000.0), (float)(hy / 30000.0));
+    P[30] = 0u;
+    P[31] = 0u;
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+        dst[q] = uint4{P[4 * q], P[4 * q + 1], P[4 * q + 2], P[4 * q + 3]};
     if (a.T) {
         a.T[2 * r] = a.tgt[2 * s];
         a.T[2 * r + 1] = a.tgt[2 * s + 1];
