@@ -151,30 +151,47 @@ __device__ inline int cell_frac(const lp::AxisDev &a, double x, double &f)
 // of the particle from that node in cell widths; [56..57] U, V interpolated
 // bilinearly at the particle; [58..59] the cell width and height in units of 30 km;
 // [60..63] zero.
-__global__ void k_features(FeatArgs a)
+constexpr int kFeatBlock = 128;  // rows (threads) per block of k_features
+
+__device__ inline void feature_row(const FeatArgs &a, int64_t r, uint32_t P[32]);
+
+// Each thread assembles one row as 32 pairs of bfloat16 (feature 2m in the low half);
+// the block's 128 rows, 16 KB of consecutive memory, go out through LDS so that each
+// store instruction of a wave writes 1 KB of consecutive bytes.
+__global__ __launch_bounds__(kFeatBlock) void k_features(FeatArgs a)
 {
-    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (r >= a.npad)
-        return;
-    const int64_t n = a.n_dev ? (int64_t)*a.n_dev : a.n;
-    // the row is assembled as 32 pairs of bfloat16 (feature 2m in the low half) and
-    // written with eight 16-byte stores
     static_assert(kIn == 64, "a row is 32 bf16 pairs");
-    uint4 *dst = reinterpret_cast<uint4 *>(a.X + r * kIn);
-    if (r >= n) {
+    __shared__ uint4 stage[kFeatBlock * 9];  // 8 chunks per row + 1 of padding (no conflicts)
+    const int64_t base = blockIdx.x * (int64_t)kFeatBlock, r = base + threadIdx.x;
+    const int64_t n = a.n_dev ? (int64_t)*a.n_dev : a.n;
+    uint32_t P[32];
+    if (r < a.npad && r < n) {
+        feature_row(a, r, P);
+    } else {
 #pragma unroll
-        for (int q = 0; q < 8; ++q)
-            dst[q] = uint4{0u, 0u, 0u, 0u};
-        if (a.T) {
+        for (int q = 0; q < 32; ++q)
+            P[q] = 0u;
+        if (r < a.npad && a.T) {
             a.T[2 * r] = 0.f;
             a.T[2 * r + 1] = 0.f;
         }
-        return;
     }
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+        stage[threadIdx.x * 9 + q] = uint4{P[4 * q], P[4 * q + 1], P[4 * q + 2], P[4 * q + 3]};
+    __syncthreads();
+    for (int c = threadIdx.x; c < kFeatBlock * 8; c += kFeatBlock) {
+        const int row = c >> 3, part = c & 7;
+        if (base + row < a.npad)
+            reinterpret_cast<uint4 *>(a.X + (base + row) * kIn)[part] = stage[row * 9 + part];
+    }
+}
+
+__device__ inline void feature_row(const FeatArgs &a, int64_t r, uint32_t P[32])
+{
     auto pair = [](float lo, float hi) {
         return (uint32_t)to_bf16(lo) | ((uint32_t)to_bf16(hi) << 16);
     };
-    uint32_t P[32];
     const uint32_t s = a.sel ? a.sel[r] : (uint32_t)r;
     const uint32_t rd = a.round ? a.round[s] : 0u;
     const TimeEntry e = a.tab[rd];
@@ -224,9 +241,6 @@ __global__ void k_features(FeatArgs a)
     P[29] = pair((float)(hx / 30000.0), (float)(hy / 30000.0));
     P[30] = 0u;
     P[31] = 0u;
-#pragma unroll
-    for (int q = 0; q < 8; ++q)
-        dst[q] = uint4{P[4 * q], P[4 * q + 1], P[4 * q + 2], P[4 * q + 3]};
     if (a.T) {
         a.T[2 * r] = a.tgt[2 * s];
         a.T[2 * r + 1] = a.tgt[2 * s + 1];
@@ -1011,8 +1025,8 @@ extern "C" int surrogate_train(lp_fieldset *fs, lp_model *m, const lp_surrogate_
     for (int64_t it = 0; it < cfg->iterations; ++it) {
         hipLaunchKernelGGL(k_sample_batch, dim3((uint32_t)((B + 255) / 256)), dim3(256), 0,
                            stream, cfg->seed ^ 0xA5A5A5A5u, (uint32_t)it, kept, B, idx);
-        hipLaunchKernelGGL(k_features, dim3((uint32_t)((B + 127) / 128)), dim3(128), 0, stream,
-                           fa);
+        hipLaunchKernelGGL(k_features, dim3((uint32_t)((B + kFeatBlock - 1) / kFeatBlock)),
+                           dim3(kFeatBlock), 0, stream, fa);
         SCHECK(hipGetLastError());
         const double frac = (double)it / (double)cfg->iterations;
         const double lr = cfg->lr * (0.05 + 0.95 * 0.5 * (1.0 + std::cos(M_PI * frac)));
@@ -1082,8 +1096,8 @@ extern "C" int surrogate_features(lp_fieldset *fs, int64_t n, const double *x, c
     fa.n = n;
     fa.npad = n;
     fa.X = dX;
-    hipLaunchKernelGGL(k_features, dim3((uint32_t)((n + 127) / 128)), dim3(128), 0, nullptr,
-                       fa);
+    hipLaunchKernelGGL(k_features, dim3((uint32_t)((n + kFeatBlock - 1) / kFeatBlock)),
+                       dim3(kFeatBlock), 0, nullptr, fa);
     SCHECK(hipGetLastError());
     std::vector<uint16_t> h((size_t)n * kIn);
     SCHECK(hipDeviceSynchronize());
@@ -1236,8 +1250,8 @@ extern "C" int pset_execute_surrogate(lp_pset *ps, lp_model *m, double runtime, 
         fa.n_dev = ps->dcount + c0;
         fa.npad = rows;
         fa.X = m->X;
-        hipLaunchKernelGGL(k_features, dim3((uint32_t)((rows + 127) / 128)), dim3(128), 0,
-                           stream, fa);
+        hipLaunchKernelGGL(k_features, dim3((uint32_t)((rows + kFeatBlock - 1) / kFeatBlock)),
+                           dim3(kFeatBlock), 0, stream, fa);
         SCHECK(hipGetLastError());
         if ((rc = forward(m, rows, false, stream)))
             break;
