@@ -82,7 +82,7 @@ class lp_train_stats(C.Structure):
 class lp_surrogate_stats(C.Structure):
     _fields_ = [("segments", C.c_int64), ("evaluated", C.c_int64), ("accepted", C.c_int64),
                 ("fallback", C.c_int64), ("mlp_ms", C.c_double), ("coarse_ms", C.c_double),
-                ("fine_ms", C.c_double), ("total_ms", C.c_double)]
+                ("fine_ms", C.c_double), ("total_ms", C.c_double), ("sort_ms", C.c_double)]
 
 
 class LPError(RuntimeError):
