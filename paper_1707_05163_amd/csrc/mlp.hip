@@ -191,7 +191,7 @@ __global__ void k_to_bf16(const float *x, int64_t n, uint16_t *y)
 // ---------------------------------------------------------------- fused inference
 // The whole network on one tile of 256 rows per block, activations in registers.
 // Each layer is computed transposed, H^T = W^T A^T, so the weights are the matrix
-// core's A operand (read from LDS, where the block stages one layer at a time) and
+// core's A operand (read from LDS, where the block streams them half a layer at a time) and
 // the activations its B operand: lane l keeps 8 consecutive features of row
 // (l mod 32) for each k-step.  The accumulator of the 32x32x16 product leaves lane
 // l with features 8(v/4) + 4(l/32) + (v mod 4) of that row; two permlane32 swaps per
@@ -205,7 +205,10 @@ typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
 
 constexpr int kFusedRows = 256;      // rows per tile: 8 waves x 32
 constexpr int kFusedThreads = 512;
-constexpr int kLdsStride = 256 + 8;  // bf16 per staged weight row (padding against bank conflicts)
+constexpr int kStride256 = 256 + 8;  // bf16 per staged weight row of a 256-input layer
+constexpr int kStride64 = 64 + 8;    // the same for the 64-input first layer (the 8 bf16 of
+                                     // padding put 16 consecutive rows on distinct banks)
+constexpr int kHalfRows = 128;       // weight rows (output features) per LDS buffer
 
 __device__ inline float gelu_sigmoid(float x)
 {
@@ -220,118 +223,198 @@ __device__ inline uint32_t pack_bf16(float a, float b)
     return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2_t{a, b}, bf16x2_t));
 }
 
-// One 32-feature output block nb of a layer with K inputs (16-wide k-steps in `in`):
-// the accumulator starts from the biases of the features the lane holds and takes the
-// K/16 products in k order.
-template <int K>
-__device__ inline f32x16 fused_block(const uint16_t *wl, const float *bl, int r, int h, int nb,
-                                     const bf16x8 (&in)[16])
+// One step of the network on a wave's 32 rows: the products of one 32-feature output
+// block with K inputs (weights from LDS rows of STRIDE bf16 at w, biases at b; the
+// accumulator starts from the biases of the features the lane holds and takes the K/16
+// products in k order), written beside the epilogue of the block before (prev): GELU
+// and bf16 of its 16 values, then the half-wave exchange into the next layer's two
+// operands o0, o1 for those 32 features.  Left to itself the compiler issues all the
+// products first and the epilogue after them; here the step is cut into one piece per
+// product, fenced so that nothing moves across: the weights of the product three
+// ahead are read from LDS, the product is issued, and a share of the epilogue follows
+// while the matrix core works.  At a layer's first block the previous block is the
+// previous layer's last one (CROSS): its outputs are this layer's inputs for k-steps
+// K/16 - 2 and K/16 - 1 (o0 and o1 alias in[] there), so those two products come last.
+template <int K, int STRIDE, bool PREV, bool CROSS>
+__device__ inline f32x16 step(const uint16_t *w, const float *b, int r, int h,
+                              const bf16x8 (&in)[16], const f32x16 &prev, bf16x8 &o0,
+                              bf16x8 &o1)
 {
+    constexpr int kSteps = K / 16, kAhead = 3, kLate = CROSS ? 2 : 0, kPer = 16 / kSteps;
+    static_assert(!CROSS || PREV, "a layer's first block follows the previous layer's last");
     f32x16 acc;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const float4 b = *reinterpret_cast<const float4 *>(bl + nb * 32 + 8 * q + 4 * h);
-        acc[4 * q + 0] = b.x;
-        acc[4 * q + 1] = b.y;
-        acc[4 * q + 2] = b.z;
-        acc[4 * q + 3] = b.w;
+        const float4 v = *reinterpret_cast<const float4 *>(b + 8 * q + 4 * h);
+        acc[4 * q + 0] = v.x;
+        acc[4 * q + 1] = v.y;
+        acc[4 * q + 2] = v.z;
+        acc[4 * q + 3] = v.w;
     }
+    const uint16_t *wr = w + r * STRIDE + 8 * h;
+    bf16x8 wq[kSteps];
 #pragma unroll
-    for (int s = 0; s < K / 16; ++s) {
-        const bf16x8 w =
-            *reinterpret_cast<const bf16x8 *>(wl + (nb * 32 + r) * kLdsStride + 16 * s + 8 * h);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, in[s], acc, 0, 0, 0);
+    for (int i = 0; i < kAhead && i < kSteps; ++i)
+        wq[i] = *reinterpret_cast<const bf16x8 *>(wr + 16 * i);
+    __builtin_amdgcn_sched_barrier(0);
+    float g[16];
+    uint32_t P[8];
+#pragma unroll
+    for (int i = 0; i < kSteps; ++i) {
+        if (i + kAhead < kSteps)
+            wq[i + kAhead] = *reinterpret_cast<const bf16x8 *>(wr + 16 * (i + kAhead));
+        if (i < kSteps - kLate)
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wq[i], in[i], acc, 0, 0, 0);
+        if constexpr (PREV) {
+#pragma unroll
+            for (int v = i * kPer; v < (i + 1) * kPer; ++v) {
+                g[v] = gelu_sigmoid(prev[v]);
+                if (v & 1)
+                    P[v >> 1] = pack_bf16(g[v - 1], g[v]);
+                // lanes 32-63 of the first register trade places with lanes 0-31 of the
+                // second, once both are packed
+                if (v == 7 || v == 15) {
+                    const int j0 = v == 7 ? 0 : 4;
+#pragma unroll
+                    for (int j = j0; j < j0 + 2; ++j) {
+                        auto x = __builtin_amdgcn_permlane32_swap(P[j], P[j + 2], false, false);
+                        P[j] = x[0];
+                        P[j + 2] = x[1];
+                    }
+                }
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    if constexpr (PREV) {
+        o0 = __builtin_bit_cast(bf16x8, u32x4_t{P[0], P[1], P[2], P[3]});
+        o1 = __builtin_bit_cast(bf16x8, u32x4_t{P[4], P[5], P[6], P[7]});
+    }
+    if constexpr (CROSS) {
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wq[kSteps - 2], o0, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wq[kSteps - 1], o1, acc, 0, 0, 0);
     }
     return acc;
 }
 
-// GELU + bf16 of one output block, then the half-wave exchange into the next layer's
-// two operands for these 32 features
-__device__ inline void block_epilogue(const f32x16 &acc, bf16x8 &o0, bf16x8 &o1)
+typedef __attribute__((address_space(3))) void *lds_ptr_t;
+
+// Rows [0, R) of a row-major [R x K] bf16 matrix at src, loaded straight into LDS rows
+// of STRIDE bf16 at dst without passing through registers: K/8 lanes carry a row, 16
+// bytes each.  Such a load writes its lanes' 16-byte pieces one after the other from
+// one wave-uniform LDS address, so each row is one load with the lanes of the other
+// rows switched off.  Row n0 + q of a group of G rows starts 16 q bytes past
+// n0 STRIDE*2 + q K*2 (the padding of the rows before it); that shift goes into the
+// load's immediate offset, which the hardware adds to the global address as well (the
+// lanes' pointers are moved back by it).  The LDS address is then the same for the G
+// loads of a group, and their immediates differ, so the compiler can never fold the
+// G masked loads into one.  Wave w takes rows w R/8 .. (w + 1) R/8 - 1.  The loads
+// count as the wave's vector-memory operations until the data is in LDS.
+template <int Q, int G>
+__device__ inline void load_row_group(const uint16_t *p, lds_ptr_t d, int g)
 {
-    float g[16];
-#pragma unroll
-    for (int v = 0; v < 16; ++v)
-        g[v] = gelu_sigmoid(acc[v]);
-    uint32_t P[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j)
-        P[j] = pack_bf16(g[2 * j], g[2 * j + 1]);
-    // lanes 32-63 of the first register trade places with lanes 0-31 of the second
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        auto lo = __builtin_amdgcn_permlane32_swap(P[j], P[j + 2], false, false);
-        P[j] = lo[0];
-        P[j + 2] = lo[1];
-        auto hi = __builtin_amdgcn_permlane32_swap(P[j + 4], P[j + 6], false, false);
-        P[j + 4] = hi[0];
-        P[j + 6] = hi[1];
+    if constexpr (Q < G) {
+        if (g == Q)
+            __builtin_amdgcn_global_load_lds(p, d, 16, 16 * Q, 0);
+        load_row_group<Q + 1, G>(p, d, g);
     }
-    o0 = __builtin_bit_cast(bf16x8, u32x4_t{P[0], P[1], P[2], P[3]});
-    o1 = __builtin_bit_cast(bf16x8, u32x4_t{P[4], P[5], P[6], P[7]});
 }
 
-// A hidden layer of 256 outputs, block by block: the epilogue of one block is written
-// beside the products of the next, so that the wave's GELU arithmetic runs while the
-// matrix core works (the products of a block depend only on the layer's inputs), and
-// only two accumulators are live instead of eight.
-template <int K>
-__device__ inline void hidden_layer(const uint16_t *wl, const float *bl, int r, int h,
-                                    bf16x8 (&in)[16])
+template <int R, int K, int STRIDE>
+__device__ inline void load_rows_to_lds(uint16_t *dst, const uint16_t *src, int wave, int lane)
 {
-    bf16x8 out[16];
-    f32x16 cur = fused_block<K>(wl, bl, r, h, 0, in);
+    constexpr int L = K / 8, G = 64 / L, kPerWave = R / 8;
+    static_assert(kPerWave % G == 0, "whole groups of rows per wave");
+    static_assert(STRIDE * 2 - K * 2 == 16, "16 bytes of padding per row");
+    const int g = lane / L, c = lane % L;
 #pragma unroll
-    for (int nb = 1; nb < 8; ++nb) {
-        const f32x16 next = fused_block<K>(wl, bl, r, h, nb, in);
-        block_epilogue(cur, out[2 * nb - 2], out[2 * nb - 1]);
-        cur = next;
+    for (int i = 0; i < kPerWave; i += G) {
+        const int n0 = wave * kPerWave + i;
+        const uint16_t *p = src + (size_t)(n0 + g) * K + c * 8 - 8 * g;
+        const lds_ptr_t d = (lds_ptr_t)(reinterpret_cast<char *>(dst) + n0 * STRIDE * 2);
+        load_row_group<0, G>(p, d, g);
     }
-    block_epilogue(cur, out[14], out[15]);
-#pragma unroll
-    for (int s = 0; s < 16; ++s)
-        in[s] = out[s];
 }
 
-__device__ inline void stage_layer(uint16_t *wl, float *bl, const uint16_t *WT, const float *bias,
-                                   int N, int K)
+// The wave's own loads into LDS have landed; after the barrier every wave's have, and
+// every wave is done reading the buffer that the loads issued next overwrite.
+__device__ inline void chunk_sync()
 {
-    __syncthreads();  // every wave is done with the previous layer's weights
-    const int chunks = N * K / 8;
-    for (int c = threadIdx.x; c < chunks; c += kFusedThreads) {
-        const int n = c / (K / 8), kk = (c % (K / 8)) * 8;
-        *reinterpret_cast<u32x4_t *>(wl + n * kLdsStride + kk) =
-            *reinterpret_cast<const u32x4_t *>(WT + (size_t)n * K + kk);
-    }
-    for (int c = threadIdx.x; c < N; c += kFusedThreads)
-        bl[c] = bias[c];
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
 }
 
+// Weights stream through two LDS buffers in eight chunks per tile: the first layer
+// (buffer 0), then each 256-input layer as output features 0-127 (buffer 1) and
+// 128-255 (buffer 0), then the output layer (buffer 1).  Each chunk's loads are issued
+// one chunk ahead, right after the barrier that frees their buffer, so they run while
+// the matrix core works on the other buffer.  Eight chunks per tile keep every
+// chunk's buffer the same from tile to tile, so each access names its buffer at
+// compile time (and the compiler waits for loads into one buffer only before reading
+// that one).
 __global__ __launch_bounds__(kFusedThreads) void k_mlp_fused(MlpFusedArgs a)
 {
-    extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
-    uint16_t *wl = reinterpret_cast<uint16_t *>(lds);
-    float *bl = reinterpret_cast<float *>(lds + 256 * kLdsStride * sizeof(uint16_t));
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, r = lane & 31, h = lane >> 5;
+    __shared__ __attribute__((aligned(16))) uint16_t buf0[kHalfRows * kStride256];
+    __shared__ __attribute__((aligned(16))) uint16_t buf1[kHalfRows * kStride256];
+    __shared__ __attribute__((aligned(16))) float bl[4 * 256 + 32];
+    static_assert(256 * kStride64 <= kHalfRows * kStride256, "first layer fits one buffer");
+    const int lane = threadIdx.x & 63, r = lane & 31, h = lane >> 5;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int64_t ntile = (a.rows + kFusedRows - 1) / kFusedRows;
+    for (int c = threadIdx.x; c < 4 * 256 + 32; c += kFusedThreads)
+        bl[c] = c < 1024 ? a.bias[c >> 8][c & 255] : a.bias[4][c - 1024];
+    load_rows_to_lds<256, 64, kStride64>(buf0, a.WT[0], wave, lane);  // grid <= tiles
     for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
         const int64_t row = tile * kFusedRows + wave * 32 + r;
         const bool live = row < a.rows;
-        bf16x8 in[16];
+        bf16x8 in[16], out[16];
 #pragma unroll
         for (int s = 0; s < 4; ++s)
             in[s] = live ? *reinterpret_cast<const bf16x8 *>(a.X + row * 64 + 16 * s + 8 * h)
                          : bf16x8{};
-        stage_layer(wl, bl, a.WT[0], a.bias[0], 256, 64);
-        hidden_layer<64>(wl, bl, r, h, in);
+        chunk_sync();
+        load_rows_to_lds<128, 256, kStride256>(buf1, a.WT[1], wave, lane);
+        // first layer, 64 inputs, weights in buffer 0
+        f32x16 cur = step<64, kStride64, false, false>(buf0, bl, r, h, in, f32x16{}, out[0], out[1]);
+#pragma unroll
+        for (int nb = 1; nb < 8; ++nb)
+            cur = step<64, kStride64, true, false>(buf0 + nb * 32 * kStride64, bl + nb * 32, r, h,
+                                                   in, cur, out[2 * nb - 2], out[2 * nb - 1]);
+        // 256-input layers: output features 0-127 from buffer 1, 128-255 from buffer 0
 #pragma unroll 1
         for (int l = 1; l < 4; ++l) {
-            stage_layer(wl, bl, a.WT[l], a.bias[l], 256, 256);
-            hidden_layer<256>(wl, bl, r, h, in);
+            chunk_sync();
+            load_rows_to_lds<128, 256, kStride256>(buf0, a.WT[l] + 128 * 256, wave, lane);
+            const float *bias = bl + 256 * l;
+#pragma unroll
+            for (int s = 0; s < 14; ++s)
+                in[s] = out[s];
+            cur = step<256, kStride256, true, true>(buf1, bias, r, h, in, cur, in[14], in[15]);
+#pragma unroll
+            for (int nb = 1; nb < 4; ++nb)
+                cur = step<256, kStride256, true, false>(buf1 + nb * 32 * kStride256, bias + nb * 32,
+                                                         r, h, in, cur, out[2 * nb - 2],
+                                                         out[2 * nb - 1]);
+            chunk_sync();
+            if (l < 3)
+                load_rows_to_lds<128, 256, kStride256>(buf1, a.WT[l + 1], wave, lane);
+            else
+                load_rows_to_lds<32, 256, kStride256>(buf1, a.WT[4], wave, lane);
+#pragma unroll
+            for (int nb = 4; nb < 8; ++nb)
+                cur = step<256, kStride256, true, false>(buf0 + (nb - 4) * 32 * kStride256,
+                                                         bias + nb * 32, r, h, in, cur,
+                                                         out[2 * nb - 2], out[2 * nb - 1]);
         }
-        stage_layer(wl, bl, a.WT[4], a.bias[4], 32, 256);
-        const f32x16 y = fused_block<256>(wl, bl, r, h, 0, in);
+        // output layer, weights in buffer 1; the next tile's first layer goes to buffer 0
+        chunk_sync();
+        if (tile + gridDim.x < ntile)
+            load_rows_to_lds<256, 64, kStride64>(buf0, a.WT[0], wave, lane);
+#pragma unroll
+        for (int s = 0; s < 14; ++s)
+            in[s] = out[s];
+        const f32x16 y = step<256, kStride256, true, true>(buf1, bl + 1024, r, h, in, cur, in[14],
+                                                           in[15]);
         // outputs 0 and 1 of the row sit in values 0 and 1 of the lower half-wave
         if (live && h == 0) {
             a.Y[row * 2 + 0] = y[0];
@@ -348,15 +431,6 @@ hipError_t launch_mlp_fused(const MlpFusedArgs &a, hipStream_t s)
         return hipSuccess;
     if (a.rows % 32)
         return hipErrorInvalidValue;
-    const size_t lds = 256 * kLdsStride * sizeof(uint16_t) + 256 * sizeof(float);
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_mlp_fused,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess)
-            return e;
-        attr = true;
-    }
     int cus = 0, dev = 0;
     hipError_t e;
     if ((e = hipGetDevice(&dev)) != hipSuccess ||
@@ -364,7 +438,7 @@ hipError_t launch_mlp_fused(const MlpFusedArgs &a, hipStream_t s)
         return e;
     const int64_t ntile = (a.rows + kFusedRows - 1) / kFusedRows;
     const uint32_t grid = (uint32_t)(ntile < cus ? ntile : cus);
-    hipLaunchKernelGGL(k_mlp_fused, dim3(grid), dim3(kFusedThreads), lds, s, a);
+    hipLaunchKernelGGL(k_mlp_fused, dim3(grid), dim3(kFusedThreads), 0, s, a);
     return hipGetLastError();
 }
 
