@@ -20,6 +20,12 @@
 
 namespace lp {
 
+// The counter slot of this block (see kCountSlots).
+__device__ inline unsigned long long *count_slot(unsigned long long *c)
+{
+    return c + (blockIdx.x % kCountSlots) * kCountStride;
+}
+
 namespace {
 
 constexpr uint8_t ST_OOB = 1, ST_LAND = 2, ST_DELETED = 4, ST_AGED = 8;
@@ -748,7 +754,7 @@ __global__ __launch_bounds__(kBlock) void k_advect(AdvectParams P)
     for (int off = 32; off > 0; off >>= 1)
         steps += __shfl_xor(steps, off, 64);
     if ((threadIdx.x & 63) == 0 && steps)
-        atomicAdd(P.psteps, (unsigned long long)steps);
+        atomicAdd(count_slot(P.psteps), (unsigned long long)steps);
 }
 
 // ---------------------------------------------------------------- adaptive RKF45
@@ -1520,7 +1526,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
     for (int off = 32; off > 0; off >>= 1)
         steps += __shfl_xor(steps, off, 64);
     if ((threadIdx.x & 63) == 0 && steps)
-        atomicAdd(P.psteps, (unsigned long long)steps);
+        atomicAdd(count_slot(P.psteps), (unsigned long long)steps);
 }
 
 // ---------------------------------------------------------------- 2D RKF45 with the cache
@@ -1718,9 +1724,9 @@ __device__ inline void rkf45_refill(const AdvectParams &P)
     }
     if (lane == 0) {
         if (acc)
-            atomicAdd(P.psteps, (unsigned long long)acc);
+            atomicAdd(count_slot(P.psteps), (unsigned long long)acc);
         if (rej)
-            atomicAdd(P.prej, (unsigned long long)rej);
+            atomicAdd(count_slot(P.prej), (unsigned long long)rej);
     }
 }
 
@@ -1794,7 +1800,7 @@ __attribute__((amdgpu_waves_per_eu(BROWN || MET == kSphLib ? 3 : 4))) void k_adv
         for (int off = 32; off > 0; off >>= 1)
             steps += __shfl_xor(steps, off, 64);
         if ((threadIdx.x & 63) == 0 && steps)
-            atomicAdd(P.psteps, (unsigned long long)steps);
+            atomicAdd(count_slot(P.psteps), (unsigned long long)steps);
     }
 }
 
@@ -2167,7 +2173,7 @@ __attribute__((amdgpu_waves_per_eu(cache3_lds<ST, STEADY, MET, BROWN>() ? (sizeo
     for (int off = 32; off > 0; off >>= 1)
         steps += __shfl_xor(steps, off, 64);
     if ((threadIdx.x & 63) == 0 && steps)
-        atomicAdd(P.psteps, (unsigned long long)steps);
+        atomicAdd(count_slot(P.psteps), (unsigned long long)steps);
 }
 
 __global__ void k_philox_normals(uint32_t run_id, uint32_t seed, int64_t n, const uint32_t *pid,

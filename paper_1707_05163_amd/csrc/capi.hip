@@ -706,7 +706,7 @@ static int pset_create_common(lp_fieldset *fs, int64_t n, const double *lon, con
     if ((rc = dalloc(&ps->dx, N)) || (rc = dalloc(&ps->dy, N)) ||
         (fs->is3d && (rc = dalloc(&ps->dz, N))) || (rc = dalloc(&ps->dst, N)) ||
         (rc = dalloc(&ps->dorder[0], N)) || (rc = dalloc(&ps->dorder[1], N)) ||
-        (rc = dalloc(&ps->dcount, 2)) || (rc = dalloc(&ps->dpsteps, 2)) ||
+        (rc = dalloc(&ps->dcount, 2)) || (rc = dalloc(&ps->dpsteps, 2 * lp::kCountWords)) ||
         (rc = dalloc(&ps->dexp, N)) || (rc = dalloc(&ps->dqueues, 8)) ||
         (rc = dalloc(&ps->dtemp, N)) || (rc = dalloc(&ps->dage, N)))
         return bail(rc);
@@ -727,7 +727,8 @@ static int pset_create_common(lp_fieldset *fs, int64_t n, const double *lon, con
         (fs->is3d && cp(ps->dz, depth) != hipSuccess))
         return bail(fail(LP_EDEVICE, "particle upload failed"));
     if (hipMemsetAsync(ps->dst, 0, N, stream) != hipSuccess ||
-        hipMemsetAsync(ps->dpsteps, 0, 2 * sizeof(unsigned long long), stream) != hipSuccess ||
+        hipMemsetAsync(ps->dpsteps, 0, 2 * lp::kCountWords * sizeof(unsigned long long),
+                       stream) != hipSuccess ||
         hipMemsetAsync(ps->dexp, 0, N, stream) != hipSuccess ||
         hipMemsetAsync(ps->dtemp, 0xFF, N * sizeof(double), stream) != hipSuccess ||  // NaN
         hipMemsetAsync(ps->dage, 0, N * sizeof(double), stream) != hipSuccess ||
@@ -1068,7 +1069,7 @@ int exec_prepare(lp_pset *ps, double runtime, double dt, double outputdt, const 
     P.z = ps->dz;
     P.status = ps->dst;
     P.psteps = ps->dpsteps;
-    P.prej = ps->dpsteps + 1;
+    P.prej = ps->dpsteps + lp::kCountWords;
     P.hexp = ps->dexp;
     P.queues = ps->dqueues;
     P.f.tracer = fs->dtracer;
@@ -1444,6 +1445,18 @@ extern "C" int pset_execute_batch(lp_pset **ps, int32_t nruns, double runtime, d
 
 namespace {
 
+// The particle-step and retry counters of a set, each summed over its slots.
+int read_counters(lp_pset *ps, unsigned long long sums[2])
+{
+    std::vector<unsigned long long> c(2 * (size_t)lp::kCountWords);
+    HIPCHECK(hipMemcpy(c.data(), ps->dpsteps, c.size() * 8, hipMemcpyDeviceToHost));
+    sums[0] = sums[1] = 0;
+    for (int k = 0; k < 2; ++k)
+        for (int i = 0; i < lp::kCountSlots; ++i)
+            sums[k] += c[(size_t)k * lp::kCountWords + (size_t)i * lp::kCountStride];
+    return LP_OK;
+}
+
 // Copy of the mutable state of a particle set, for autotuning trials.
 struct Snapshot {
     double *x = nullptr, *y = nullptr, *z = nullptr;
@@ -1470,7 +1483,10 @@ int save_state(lp_pset *ps, Snapshot &s)
     HIPCHECK(hipMemcpy(s.st, ps->dst, N, hipMemcpyDeviceToDevice));
     HIPCHECK(hipMemcpy(s.order, ps->dorder[ps->cur], N * 4, hipMemcpyDeviceToDevice));
     HIPCHECK(hipMemcpy(&s.count, ps->dcount + ps->cur, 4, hipMemcpyDeviceToHost));
-    HIPCHECK(hipMemcpy(&s.psteps, ps->dpsteps, 8, hipMemcpyDeviceToHost));
+    unsigned long long sums[2];
+    if ((rc = read_counters(ps, sums)))
+        return rc;
+    s.psteps = sums[0];
     s.cur = ps->cur;
     s.segs_since_sort = ps->segs_since_sort;
     s.n_launch = ps->n_launch;
@@ -1492,7 +1508,11 @@ int restore_state(lp_pset *ps, Snapshot &s)
     HIPCHECK(hipMemcpy(ps->dst, s.st, N, hipMemcpyDeviceToDevice));
     HIPCHECK(hipMemcpy(ps->dorder[ps->cur], s.order, N * 4, hipMemcpyDeviceToDevice));
     HIPCHECK(hipMemcpy(ps->dcount + ps->cur, &s.count, 4, hipMemcpyHostToDevice));
-    HIPCHECK(hipMemcpy(ps->dpsteps, &s.psteps, 8, hipMemcpyHostToDevice));
+    {
+        std::vector<unsigned long long> c(2 * (size_t)lp::kCountWords, 0ull);
+        c[0] = s.psteps;
+        HIPCHECK(hipMemcpy(ps->dpsteps, c.data(), c.size() * 8, hipMemcpyHostToDevice));
+    }
     ps->segs_since_sort = s.segs_since_sort;
     ps->n_launch = s.n_launch;
     ps->step = s.step;
@@ -1690,7 +1710,8 @@ extern "C" int pset_status(lp_pset *ps, lp_counts *c, uint8_t *status)
     std::vector<uint8_t> st((size_t)ps->n);
     HIPCHECK(hipMemcpy(st.data(), ps->dst, st.size(), hipMemcpyDeviceToHost));
     unsigned long long steps[2] = {0, 0};
-    HIPCHECK(hipMemcpy(steps, ps->dpsteps, sizeof steps, hipMemcpyDeviceToHost));
+    if (int rc = read_counters(ps, steps))
+        return rc;
     lp_counts r{};
     r.n = ps->n;
     for (uint8_t s : st) {
@@ -1927,7 +1948,8 @@ int lp_pset_reset_device(lp_pset *ps, int64_t n, const double *x, const double *
     HIPCHECK(hipMemsetAsync(ps->dst, 0, (size_t)ps->n, stream));
     if (n < ps->n)  // the unused tail is never advanced
         HIPCHECK(hipMemsetAsync(ps->dst + n, LP_ST_DELETED, (size_t)(ps->n - n), stream));
-    HIPCHECK(hipMemsetAsync(ps->dpsteps, 0, 2 * sizeof(unsigned long long), stream));
+    HIPCHECK(hipMemsetAsync(ps->dpsteps, 0,
+                            2 * lp::kCountWords * sizeof(unsigned long long), stream));
     HIPCHECK(hipMemsetAsync(ps->dexp, 0, (size_t)ps->n, stream));
     HIPCHECK(hipMemsetAsync(ps->dtemp, 0xFF, (size_t)ps->n * sizeof(double), stream));
     HIPCHECK(hipMemsetAsync(ps->dage, 0, (size_t)ps->n * sizeof(double), stream));

@@ -12,6 +12,12 @@ constexpr double kMetresPerDegree = 111120.0;  // 1852 m per arc minute
 constexpr double kDegToRad = 0.017453292519943295;
 constexpr int kTile = 16;        // horizontal cells per tile side (sort key)
 constexpr int kGuessBins = 4096; // bins of the cell-guess table of a non-uniform axis
+// The particle-step and retry counters are spread over kCountSlots slots, one 128-byte
+// line apart (kCountWords 64-bit words per counter); a wave adds to the slot of its
+// block and readers sum the slots.  A single counter would take one device-wide atomic
+// per wave on one address, and those serialise: they alone made a launch of a few
+// steps over millions of particles last most of a millisecond.
+constexpr int kCountSlots = 64, kCountStride = 16, kCountWords = kCountSlots * kCountStride;
 constexpr int kBlock = 256;      // threads per block of the advection kernels
 
 enum Store : int { kF64 = 0, kF32 = 1, kBF16 = 2, kF16S = 3 };
@@ -78,7 +84,7 @@ struct AdvectParams {
     uint8_t *status;
     const uint32_t *order;   // active ids, processing order
     const uint32_t *n_active;// device count of `order`
-    unsigned long long *psteps;
+    unsigned long long *psteps;  // kCountWords words (see kCountSlots)
     // adaptive RKF45 (scheme 2): each lane brackets its own stage times
     const ResTime *res;      // resident snapshots by time
     int32_t nres;
@@ -90,7 +96,7 @@ struct AdvectParams {
     double tol;              // error tolerance per step, metres
     int8_t *hexp;            // per-particle step exponents, id order
     uint32_t *queues;        // 8 work-queue counters of the persistent launch
-    unsigned long long *prej;// attempts retried at half the step
+    unsigned long long *prej;// attempts retried at half the step (kCountWords words)
     // the worked example's kernels ahead of each step's advection (gather kernels)
     int32_t behave;          // 1: any of them is on
     int32_t sample;          // sample the tracer into temp

@@ -358,14 +358,24 @@ __device__ inline bool locate_in(const lp::AxisDev &a, double x, int &i)
 
 // Residual check: accept the network's displacement where it agrees with the
 // coarse RK4 displacement to within thr metres and ends in an ocean cell inside the
-// grid; otherwise queue the particle for the fine RK4 steps.
-__global__ void k_check(lp::GridDev g, const uint32_t *order, const uint32_t *n_act, double *x,
-                        double *y, const double *xc, const double *yc, const uint8_t *stc,
-                        const float *Y, double thr, uint32_t *fall, uint32_t *nfall,
-                        unsigned long long *accepted)
+// grid; otherwise queue the particle for the fine RK4 steps.  The queue is appended
+// with one atomic per block (the waves' counts summed in LDS): one per wave on the
+// single counter serialised and took most of the kernel's time.  Every active
+// particle is either accepted or queued, so the accepted count is the active count
+// less the queue's length.
+constexpr int kCheckThreads = 1024;
+
+__global__ __launch_bounds__(kCheckThreads) void k_check(lp::GridDev g, const uint32_t *order,
+                                                         const uint32_t *n_act, double *x,
+                                                         double *y, const double *xc,
+                                                         const double *yc, const uint8_t *stc,
+                                                         const float *Y, double thr,
+                                                         uint32_t *fall, uint32_t *nfall)
 {
+    __shared__ uint32_t wbase[kCheckThreads / 64];
+    __shared__ uint32_t block_base;
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    bool back = false, ok = false;
+    bool back = false;
     uint32_t id = 0;
     if (k < *n_act) {
         id = order[k];
@@ -381,8 +391,9 @@ __global__ void k_check(lp::GridDev g, const uint32_t *order, const uint32_t *n_
         }
         const double r = sqrt((mx - ex) * (mx - ex) + (my - ey) * (my - ey));
         int ci, cj;
-        ok = stc[id] == 0 && r <= thr && locate_in(g.ax, nx1, ci) && locate_in(g.ay, ny1, cj) &&
-             !(g.landcell && g.landcell[(size_t)cj * (g.ax.n - 1) + ci]);
+        const bool ok = stc[id] == 0 && r <= thr && locate_in(g.ax, nx1, ci) &&
+                        locate_in(g.ay, ny1, cj) &&
+                        !(g.landcell && g.landcell[(size_t)cj * (g.ax.n - 1) + ci]);
         if (ok) {
             x[id] = nx1;
             y[id] = ny1;
@@ -393,16 +404,22 @@ __global__ void k_check(lp::GridDev g, const uint32_t *order, const uint32_t *n_
     const uint64_t mb = __ballot(back);
     const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(mb >> 32),
                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mb, 0u));
-    uint32_t base = 0;
-    if (back && rank == 0)
-        base = atomicAdd(nfall, (uint32_t)__popcll(mb));
-    const int src = mb ? __ffsll((unsigned long long)mb) - 1 : 0;
-    base = __shfl(base, src, 64);
+    const int wid = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+        wbase[wid] = (uint32_t)__popcll(mb);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t tot = 0;
+        for (int w = 0; w < kCheckThreads / 64; ++w) {
+            const uint32_t c = wbase[w];
+            wbase[w] = tot;
+            tot += c;
+        }
+        block_base = tot ? atomicAdd(nfall, tot) : 0u;
+    }
+    __syncthreads();
     if (back)
-        fall[base + rank] = id;
-    const uint64_t ma = __ballot(ok);
-    if ((threadIdx.x & 63) == 0 && ma)
-        atomicAdd(accepted, (unsigned long long)__popcll(ma));
+        fall[block_base + wbase[wid] + rank] = id;
 }
 
 }  // namespace
@@ -1133,7 +1150,6 @@ extern "C" int surrogate_check(lp_fieldset *fs, int64_t n, const double *x0, con
     uint8_t *dst;
     float *dY;
     uint32_t *order, *nact, *fall, *nfall;
-    unsigned long long *acc;
     SCHECK(mem.get(&dx, N));
     SCHECK(mem.get(&dy, N));
     SCHECK(mem.get(&dxc, N));
@@ -1144,7 +1160,6 @@ extern "C" int surrogate_check(lp_fieldset *fs, int64_t n, const double *x0, con
     SCHECK(mem.get(&nact, 1));
     SCHECK(mem.get(&fall, N));
     SCHECK(mem.get(&nfall, 1));
-    SCHECK(mem.get(&acc, 1));
     SCHECK(hipMemcpy(dx, x0, N * 8, hipMemcpyHostToDevice));
     SCHECK(hipMemcpy(dy, y0, N * 8, hipMemcpyHostToDevice));
     SCHECK(hipMemcpy(dxc, xc, N * 8, hipMemcpyHostToDevice));
@@ -1154,9 +1169,9 @@ extern "C" int surrogate_check(lp_fieldset *fs, int64_t n, const double *x0, con
     SCHECK(lp::launch_iota(order, N, nullptr));
     SCHECK(lp::launch_fill_u32(nact, (uint32_t)n, 1, nullptr));
     SCHECK(lp::launch_fill_u32(nfall, 0u, 1, nullptr));
-    SCHECK(hipMemset(acc, 0, 8));
-    hipLaunchKernelGGL(k_check, dim3((uint32_t)((N + 255) / 256)), dim3(256), 0, nullptr, fs->g,
-                       order, nact, dx, dy, dxc, dyc, dst, dY, residual_m, fall, nfall, acc);
+    hipLaunchKernelGGL(k_check, dim3((uint32_t)((N + kCheckThreads - 1) / kCheckThreads)),
+                       dim3(kCheckThreads), 0, nullptr, fs->g, order, nact, dx, dy, dxc, dyc,
+                       dst, dY, residual_m, fall, nfall);
     SCHECK(hipGetLastError());
     SCHECK(hipDeviceSynchronize());
     uint32_t nf = 0;
@@ -1210,16 +1225,13 @@ extern "C" int pset_execute_surrogate(lp_pset *ps, lp_model *m, double runtime, 
     const int64_t n = ps->n, rows = round128(n);
     DeviceBuf mem;
     uint32_t *fall, *nfall, *saved_count;
-    unsigned long long *accepted;
     TimeEntry *dtab;
     float *dphase;
     SCHECK(mem.get(&fall, (size_t)n));
     SCHECK(mem.get(&nfall, 1));
     SCHECK(mem.get(&saved_count, 1));
-    SCHECK(mem.get(&accepted, 1));
     SCHECK(mem.get(&dtab, 1));
     SCHECK(mem.get(&dphase, 2));
-    SCHECK(hipMemsetAsync(accepted, 0, 8, stream));
     int rc = model_work(m, rows);
     if (rc)
         return rc;
@@ -1293,9 +1305,10 @@ extern "C" int pset_execute_surrogate(lp_pset *ps, lp_model *m, double runtime, 
         // residual check; the rest goes to the fine RK4 steps
         tm.start(stream);
         SCHECK(hipMemsetAsync(nfall, 0, 4, stream));
-        hipLaunchKernelGGL(k_check, dim3((ps->n_launch + 255) / 256), dim3(256), 0, stream,
+        hipLaunchKernelGGL(k_check, dim3((ps->n_launch + kCheckThreads - 1) / kCheckThreads),
+                           dim3(kCheckThreads), 0, stream,
                            fs->g, ps->dorder[c0], ps->dcount + c0, ps->dx, ps->dy, cs->dx,
-                           cs->dy, cs->dst, m->Y, residual_m, fall, nfall, accepted);
+                           cs->dy, cs->dst, m->Y, residual_m, fall, nfall);
         SCHECK(hipGetLastError());
         uint32_t *full = ps->dorder[c0];
         SCHECK(hipMemcpyAsync(saved_count, ps->dcount + c0, 4, hipMemcpyDeviceToDevice, stream));
@@ -1317,14 +1330,12 @@ extern "C" int pset_execute_surrogate(lp_pset *ps, lp_model *m, double runtime, 
         SCHECK(hipMemcpy(&na, saved_count, 4, hipMemcpyDeviceToHost));
         st->evaluated += na;
         st->fallback += nf;
+        st->accepted += (int64_t)na - (int64_t)nf;  // every active particle is one or the other
         st->segments++;
     }
     pset_destroy(cs);
     if (rc)
         return rc;
     st->total_ms = ttot.stop_ms(stream);
-    unsigned long long acc = 0;
-    SCHECK(hipMemcpy(&acc, accepted, 8, hipMemcpyDeviceToHost));
-    st->accepted = (int64_t)acc;
     return LP_OK;
 }
