@@ -378,7 +378,8 @@ int surrogate_train(lp_fieldset *fs, lp_model *m, const lp_surrogate_cfg *cfg,
 typedef struct {
     int64_t segments, evaluated, accepted, fallback;
     double mlp_ms, coarse_ms, fine_ms, total_ms;
-    double sort_ms; /* the cell sorts of the active list (one every 12 segments) */
+    double sort_ms; /* cell sorts of the active list and reordering of the state (every 12
+                       segments) */
 } lp_surrogate_stats;
 
 /* Advance a 2D particle set by runtime in segments of steps_per_segment steps of dt,

@@ -10,6 +10,7 @@
 // interpolated linearly in time, the particle's offset from that node, U and V at the
 // particle and the cell size (see k_features).  Output: the segment displacement in
 // metres (east, north) divided by kOutScale.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -420,6 +421,86 @@ __global__ __launch_bounds__(kCheckThreads) void k_check(lp::GridDev g, const ui
     __syncthreads();
     if (back)
         fall[block_base + wbase[wid] + rank] = id;
+}
+
+// The particle state in the order of the sorted active list: perm lists storage
+// positions, the sorted active ones first and the inactive ones after them; pid maps a
+// storage position to the particle's id.  With the state in this order the kernels of
+// a segment read and write it in consecutive runs instead of one 8-byte word per line.
+// k_perm_inactive appends the inactive positions after the n_act active ones (one
+// atomic per block; their order does not matter).
+__global__ __launch_bounds__(kCheckThreads) void k_perm_inactive(const uint8_t *st, uint32_t n,
+                                                                 const uint32_t *n_act,
+                                                                 uint32_t *perm, uint32_t *cnt)
+{
+    __shared__ uint32_t wbase[kCheckThreads / 64];
+    __shared__ uint32_t block_base;
+    const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool in = p < n && st[p] != 0;
+    const uint64_t mb = __ballot(in);
+    const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(mb >> 32),
+                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)mb, 0u));
+    const int wid = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+        wbase[wid] = (uint32_t)__popcll(mb);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t tot = 0;
+        for (int w = 0; w < kCheckThreads / 64; ++w) {
+            const uint32_t c = wbase[w];
+            wbase[w] = tot;
+            tot += c;
+        }
+        block_base = tot ? atomicAdd(cnt, tot) : 0u;
+    }
+    __syncthreads();
+    const uint32_t at = *n_act + block_base + wbase[wid] + rank;
+    if (in && at < n)
+        perm[at] = p;
+}
+
+// The first n_in entries of a list.
+__global__ void k_copy_list(const uint32_t *src, const uint32_t *n_in, uint32_t *dst)
+{
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < *n_in)
+        dst[k] = src[k];
+}
+
+__global__ void k_permute(const uint32_t *perm, uint32_t n, const double *x, const double *y,
+                          const uint8_t *st, const uint32_t *pid, double *x2, double *y2,
+                          uint8_t *st2, uint32_t *pid2)
+{
+    const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n) {
+        const uint32_t q = perm[p];
+        x2[p] = x[q];
+        y2[p] = y[q];
+        st2[p] = st[q];
+        pid2[p] = pid[q];
+    }
+}
+
+// Back to id order.
+__global__ void k_unpermute(const uint32_t *pid, uint32_t n, const double *x2, const double *y2,
+                            const uint8_t *st2, double *x, double *y, uint8_t *st)
+{
+    const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n) {
+        const uint32_t q = pid[p];
+        x[q] = x2[p];
+        y[q] = y2[p];
+        st[q] = st2[p];
+    }
+}
+
+// A list of storage positions as particle ids.
+__global__ void k_map_ids(const uint32_t *pid, const uint32_t *n_in, const uint32_t *order,
+                          uint32_t *out)
+{
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < *n_in)
+        out[k] = pid[order[k]];
 }
 
 }  // namespace
@@ -1232,6 +1313,19 @@ extern "C" int pset_execute_surrogate(lp_pset *ps, lp_model *m, double runtime, 
     SCHECK(mem.get(&saved_count, 1));
     SCHECK(mem.get(&dtab, 1));
     SCHECK(mem.get(&dphase, 2));
+    // the state in sorted order (see k_permute) and its position -> id map
+    uint32_t *pid, *pid2, *perm, *pcnt;
+    double *tx, *ty;
+    uint8_t *tst;
+    SCHECK(mem.get(&pid, (size_t)n));
+    SCHECK(mem.get(&pid2, (size_t)n));
+    SCHECK(mem.get(&perm, (size_t)n));
+    SCHECK(mem.get(&pcnt, 1));
+    SCHECK(mem.get(&tx, (size_t)n));
+    SCHECK(mem.get(&ty, (size_t)n));
+    SCHECK(mem.get(&tst, (size_t)n));
+    SCHECK(lp::launch_iota(pid, (size_t)n, stream));
+    const uint32_t un = (uint32_t)n, nb = std::max(1u, (un + 255) / 256);
     int rc = model_work(m, rows);
     if (rc)
         return rc;
@@ -1252,7 +1346,8 @@ extern "C" int pset_execute_surrogate(lp_pset *ps, lp_model *m, double runtime, 
         if ((rc = lp_time_entry(fs, t, &e)))
             break;
         // the active list in cell order, so that neighbouring rows gather neighbouring
-        // patches (the fine and coarse twins inherit the order)
+        // patches (the fine and coarse twins inherit the order), and the state moved
+        // into that order, so that the list becomes 0 .. active - 1
         if (q % kSortSegments == 0) {
             tm.start(stream);
             SCHECK(lp::launch_sort(fs->g, ps->dx, ps->dy, ps->dz, ps->dst, ps->dorder[ps->cur],
@@ -1260,6 +1355,21 @@ extern "C" int pset_execute_surrogate(lp_pset *ps, lp_model *m, double runtime, 
                                    ps->nbins, ps->dblk, ps->dorder[1 - ps->cur],
                                    ps->dcount + (1 - ps->cur), stream));
             ps->cur = 1 - ps->cur;
+            SCHECK(lp::launch_iota(perm, (size_t)n, stream));
+            hipLaunchKernelGGL(k_copy_list, dim3(nb), dim3(256), 0, stream, ps->dorder[ps->cur],
+                               ps->dcount + ps->cur, perm);
+            SCHECK(lp::launch_fill_u32(pcnt, 0u, 1, stream));
+            const uint32_t nbc = std::max(1u, (un + kCheckThreads - 1) / kCheckThreads);
+            hipLaunchKernelGGL(k_perm_inactive, dim3(nbc), dim3(kCheckThreads), 0, stream,
+                               ps->dst, un, ps->dcount + ps->cur, perm, pcnt);
+            hipLaunchKernelGGL(k_permute, dim3(nb), dim3(256), 0, stream, perm, un, ps->dx,
+                               ps->dy, ps->dst, pid, tx, ty, tst, pid2);
+            SCHECK(hipGetLastError());
+            std::swap(pid, pid2);
+            SCHECK(hipMemcpyAsync(ps->dx, tx, (size_t)n * 8, hipMemcpyDeviceToDevice, stream));
+            SCHECK(hipMemcpyAsync(ps->dy, ty, (size_t)n * 8, hipMemcpyDeviceToDevice, stream));
+            SCHECK(hipMemcpyAsync(ps->dst, tst, (size_t)n, hipMemcpyDeviceToDevice, stream));
+            SCHECK(lp::launch_iota(ps->dorder[ps->cur], (size_t)n, stream));
             st->sort_ms += tm.stop_ms(stream);
         }
         const double ph = 2.0 * M_PI * std::fmod(t - t_lo, P) / P;
@@ -1334,6 +1444,19 @@ extern "C" int pset_execute_surrogate(lp_pset *ps, lp_model *m, double runtime, 
         st->segments++;
     }
     pset_destroy(cs);
+    // the state back in id order, the active list as ids
+    hipLaunchKernelGGL(k_unpermute, dim3(nb), dim3(256), 0, stream, pid, un, ps->dx, ps->dy,
+                       ps->dst, tx, ty, tst);
+    SCHECK(hipGetLastError());
+    SCHECK(hipMemcpyAsync(ps->dx, tx, (size_t)n * 8, hipMemcpyDeviceToDevice, stream));
+    SCHECK(hipMemcpyAsync(ps->dy, ty, (size_t)n * 8, hipMemcpyDeviceToDevice, stream));
+    SCHECK(hipMemcpyAsync(ps->dst, tst, (size_t)n, hipMemcpyDeviceToDevice, stream));
+    hipLaunchKernelGGL(k_map_ids, dim3(nb), dim3(256), 0, stream, pid, ps->dcount + ps->cur,
+                       ps->dorder[ps->cur], ps->dorder[1 - ps->cur]);
+    SCHECK(hipGetLastError());
+    SCHECK(hipMemcpyAsync(ps->dcount + (1 - ps->cur), ps->dcount + ps->cur, 4,
+                          hipMemcpyDeviceToDevice, stream));
+    ps->cur = 1 - ps->cur;
     if (rc)
         return rc;
     st->total_ms = ttot.stop_ms(stream);
