@@ -1424,7 +1424,17 @@ extern "C" int pset_execute_surrogate(lp_pset *ps, lp_model *m, double runtime, 
         SCHECK(hipMemcpyAsync(saved_count, ps->dcount + c0, 4, hipMemcpyDeviceToDevice, stream));
         SCHECK(hipMemcpyAsync(ps->dcount + c0, nfall, 4, hipMemcpyDeviceToDevice, stream));
         ps->dorder[c0] = fall;
+        // The fine steps' launch spans the queue's own blocks (read back first): sized for the
+        // whole set, its remap onto the XCDs would give the queue, a short prefix of the
+        // grid, to the first one or two of them.  One block at least, since the call also
+        // advances the set's clock.
+        uint32_t nf = 0;
+        SCHECK(hipMemcpyAsync(&nf, nfall, 4, hipMemcpyDeviceToHost, stream));
+        SCHECK(hipStreamSynchronize(stream));
+        const uint32_t n_full = ps->n_launch;
+        ps->n_launch = std::max(nf, 1u);
         rc = pset_execute(ps, seg_t, dt, 0.0, &o, stream);
+        ps->n_launch = n_full;
         ps->dorder[c0] = full;
         ps->count_pending = false;  // its count is the fallback list's, not the set's
         if (rc)
@@ -1433,8 +1443,6 @@ extern "C" int pset_execute_surrogate(lp_pset *ps, lp_model *m, double runtime, 
         SCHECK(lp::launch_compact(full, saved_count, ps->dst, ps->dorder[1 - c0],
                                   ps->dcount + (1 - c0), ps->n_launch, stream));
         ps->cur = 1 - c0;
-        uint32_t nf = 0;
-        SCHECK(hipMemcpyAsync(&nf, nfall, 4, hipMemcpyDeviceToHost, stream));
         st->fine_ms += tm.stop_ms(stream);
         uint32_t na = 0;
         SCHECK(hipMemcpy(&na, saved_count, 4, hipMemcpyDeviceToHost));
