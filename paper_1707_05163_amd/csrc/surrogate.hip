@@ -360,11 +360,39 @@ __device__ inline bool locate_in(const lp::AxisDev &a, double x, int &i)
 // Residual check: accept the network's displacement where it agrees with the
 // coarse RK4 displacement to within thr metres and ends in an ocean cell inside the
 // grid; otherwise queue the particle for the fine RK4 steps.  The queue is appended
-// with one atomic per block (the waves' counts summed in LDS): one per wave on the
-// single counter serialised and took most of the kernel's time.  Every active
+// with one atomic per block (block_append): one per wave on the single counter
+// serialised and took most of the kernel's time.  Every active
 // particle is either accepted or queued, so the accepted count is the active count
 // less the queue's length.
 constexpr int kCheckThreads = 1024;
+
+// The slot of this thread's item (when `in`) in a list that the block of kCheckThreads
+// threads appends to with one atomic on the list's counter: the waves' ballot counts are
+// summed in LDS by the first thread.  Every thread of the block calls it; a block's items
+// land together, in thread order.
+__device__ inline uint32_t block_append(bool in, uint32_t *count)
+{
+    __shared__ uint32_t wbase[kCheckThreads / 64];
+    __shared__ uint32_t block_base;
+    const uint64_t mb = __ballot(in);
+    const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(mb >> 32),
+                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)mb, 0u));
+    const int wid = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+        wbase[wid] = (uint32_t)__popcll(mb);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t tot = 0;
+        for (int w = 0; w < kCheckThreads / 64; ++w) {
+            const uint32_t c = wbase[w];
+            wbase[w] = tot;
+            tot += c;
+        }
+        block_base = tot ? atomicAdd(count, tot) : 0u;
+    }
+    __syncthreads();
+    return block_base + wbase[wid] + rank;
+}
 
 __global__ __launch_bounds__(kCheckThreads) void k_check(lp::GridDev g, const uint32_t *order,
                                                          const uint32_t *n_act, double *x,
@@ -373,8 +401,6 @@ __global__ __launch_bounds__(kCheckThreads) void k_check(lp::GridDev g, const ui
                                                          const float *Y, double thr,
                                                          uint32_t *fall, uint32_t *nfall)
 {
-    __shared__ uint32_t wbase[kCheckThreads / 64];
-    __shared__ uint32_t block_base;
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     bool back = false;
     uint32_t id = 0;
@@ -402,59 +428,24 @@ __global__ __launch_bounds__(kCheckThreads) void k_check(lp::GridDev g, const ui
             back = true;
         }
     }
-    const uint64_t mb = __ballot(back);
-    const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(mb >> 32),
-                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)mb, 0u));
-    const int wid = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0)
-        wbase[wid] = (uint32_t)__popcll(mb);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t tot = 0;
-        for (int w = 0; w < kCheckThreads / 64; ++w) {
-            const uint32_t c = wbase[w];
-            wbase[w] = tot;
-            tot += c;
-        }
-        block_base = tot ? atomicAdd(nfall, tot) : 0u;
-    }
-    __syncthreads();
+    const uint32_t at = block_append(back, nfall);
     if (back)
-        fall[block_base + wbase[wid] + rank] = id;
+        fall[at] = id;
 }
 
 // The particle state in the order of the sorted active list: perm lists storage
 // positions, the sorted active ones first and the inactive ones after them; pid maps a
 // storage position to the particle's id.  With the state in this order the kernels of
 // a segment read and write it in consecutive runs instead of one 8-byte word per line.
-// k_perm_inactive appends the inactive positions after the n_act active ones (one
-// atomic per block; their order does not matter).
+// k_perm_inactive appends the inactive positions after the n_act active ones
+// (block_append; their order does not matter).
 __global__ __launch_bounds__(kCheckThreads) void k_perm_inactive(const uint8_t *st, uint32_t n,
                                                                  const uint32_t *n_act,
                                                                  uint32_t *perm, uint32_t *cnt)
 {
-    __shared__ uint32_t wbase[kCheckThreads / 64];
-    __shared__ uint32_t block_base;
     const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
     const bool in = p < n && st[p] != 0;
-    const uint64_t mb = __ballot(in);
-    const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(mb >> 32),
-                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)mb, 0u));
-    const int wid = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0)
-        wbase[wid] = (uint32_t)__popcll(mb);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t tot = 0;
-        for (int w = 0; w < kCheckThreads / 64; ++w) {
-            const uint32_t c = wbase[w];
-            wbase[w] = tot;
-            tot += c;
-        }
-        block_base = tot ? atomicAdd(cnt, tot) : 0u;
-    }
-    __syncthreads();
-    const uint32_t at = *n_act + block_base + wbase[wid] + rank;
+    const uint32_t at = *n_act + block_append(in, cnt);
     if (in && at < n)
         perm[at] = p;
 }
