@@ -168,8 +168,10 @@ hipError_t launch_sort(const GridDev &g, const double *x, const double *y, const
                        const uint8_t *status, const uint32_t *order_in, const uint32_t *n_in,
                        uint32_t n_launch, uint32_t *keys, uint32_t *hist, uint32_t nbins,
                        uint32_t *blocksums, uint32_t *order_out, uint32_t *n_out,
-                       hipStream_t s);
-uint32_t sort_bins(const GridDev &g);
+                       hipStream_t s, bool cells = false);
+// bins of the sort's key: tiles (times levels in 3D), or with `cells` the cells of the
+// tiles, kTile x kTile bins a tile (2D only; ignored in 3D)
+uint32_t sort_bins(const GridDev &g, bool cells = false);
 size_t sort_blocksums(uint32_t nbins);
 hipError_t launch_convert_snapshot(int store, bool is3d, const float *U, const float *V,
                                    const float *W, const double *U64, const double *V64,

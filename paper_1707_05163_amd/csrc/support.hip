@@ -115,11 +115,13 @@ __device__ inline int cell_of(const AxisDev &a, double x)
 }
 
 // Sort key: tile index (16 x 16 cells, row-major over tiles), times the level in
-// 3D.  Inactive particles get no key and are dropped by the sort.
+// 3D; with `cells` (2D) the tile index times 256 plus the cell's row-major index in its
+// tile, so that a wave's particles share cells, not only a tile.  Inactive particles get
+// no key and are dropped by the sort.
 __global__ __launch_bounds__(256) void k_sort_keys(GridDev g, const double *x, const double *y,
                                                    const double *z, const uint8_t *status,
                                                    const uint32_t *order, const uint32_t *n_in,
-                                                   uint32_t *keys, uint32_t *hist)
+                                                   uint32_t *keys, uint32_t *hist, bool cells)
 {
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t n = *n_in;
@@ -131,6 +133,8 @@ __global__ __launch_bounds__(256) void k_sort_keys(GridDev g, const double *x, c
             const int j = cell_of(g.ay, y[id]);
             const uint32_t ntx = (uint32_t)(g.ax.n - 2) / kTile + 1;
             key = (uint32_t)(j / kTile) * ntx + (uint32_t)(i / kTile);
+            if (cells)
+                key = key * (uint32_t)(kTile * kTile) + (uint32_t)((j % kTile) * kTile + i % kTile);
             if (g.az.n) {
                 const int kk = cell_of(g.az, z[id]);
                 key = key * (uint32_t)(g.az.n - 1) + (uint32_t)kk;
@@ -381,13 +385,15 @@ hipError_t launch_compact(const uint32_t *order_in, const uint32_t *n_in, const 
     return hipGetLastError();
 }
 
-uint32_t sort_bins(const GridDev &g)
+uint32_t sort_bins(const GridDev &g, bool cells)
 {
     const uint32_t ntx = (uint32_t)(g.ax.n - 2) / kTile + 1;
     const uint32_t nty = (uint32_t)(g.ay.n - 2) / kTile + 1;
     uint32_t nb = ntx * nty;
     if (g.az.n)
         nb *= (uint32_t)(g.az.n - 1);
+    else if (cells)
+        nb *= (uint32_t)(kTile * kTile);
     return nb;
 }
 
@@ -397,7 +403,7 @@ hipError_t launch_sort(const GridDev &g, const double *x, const double *y, const
                        const uint8_t *status, const uint32_t *order_in, const uint32_t *n_in,
                        uint32_t n_launch, uint32_t *keys, uint32_t *hist, uint32_t nbins,
                        uint32_t *blocksums, uint32_t *order_out, uint32_t *n_out,
-                       hipStream_t s)
+                       hipStream_t s, bool cells)
 {
     hipError_t e = launch_fill_u32(hist, 0u, nbins, s);
     if (e != hipSuccess)
@@ -405,7 +411,7 @@ hipError_t launch_sort(const GridDev &g, const double *x, const double *y, const
     const uint32_t nb = (n_launch + 255) / 256;
     if (nb)
         hipLaunchKernelGGL(k_sort_keys, dim3(nb), dim3(256), 0, s, g, x, y, z, status, order_in,
-                           n_in, keys, hist);
+                           n_in, keys, hist, cells && !g.az.n);
     const uint32_t nblk = (uint32_t)sort_blocksums(nbins);
     hipLaunchKernelGGL(k_scan_partial, dim3(nblk), dim3(kScanThreads), 0, s, hist, nbins,
                        blocksums);

@@ -1317,6 +1317,12 @@ extern "C" int pset_execute_surrogate(lp_pset *ps, lp_model *m, double runtime, 
     SCHECK(mem.get(&tst, (size_t)n));
     SCHECK(lp::launch_iota(pid, (size_t)n, stream));
     const uint32_t un = (uint32_t)n, nb = std::max(1u, (un + 255) / 256);
+    // the sorts order the list by cell within each tile (the set's own sort buffers are
+    // sized for tiles)
+    const uint32_t cbins = lp::sort_bins(fs->g, true);
+    uint32_t *chist, *cblk;
+    SCHECK(mem.get(&chist, (size_t)cbins));
+    SCHECK(mem.get(&cblk, lp::sort_blocksums(cbins)));
     int rc = model_work(m, rows);
     if (rc)
         return rc;
@@ -1336,15 +1342,15 @@ extern "C" int pset_execute_surrogate(lp_pset *ps, lp_model *m, double runtime, 
         TimeEntry e{};
         if ((rc = lp_time_entry(fs, t, &e)))
             break;
-        // the active list in cell order, so that neighbouring rows gather neighbouring
-        // patches (the fine and coarse twins inherit the order), and the state moved
-        // into that order, so that the list becomes 0 .. active - 1
+        // the active list in cell order (cells within tiles), so that neighbouring rows
+        // gather neighbouring patches (the fine and coarse twins inherit the order), and the
+        // state moved into that order, so that the list becomes 0 .. active - 1
         if (q % kSortSegments == 0) {
             tm.start(stream);
             SCHECK(lp::launch_sort(fs->g, ps->dx, ps->dy, ps->dz, ps->dst, ps->dorder[ps->cur],
-                                   ps->dcount + ps->cur, ps->n_launch, ps->dkeys, ps->dhist,
-                                   ps->nbins, ps->dblk, ps->dorder[1 - ps->cur],
-                                   ps->dcount + (1 - ps->cur), stream));
+                                   ps->dcount + ps->cur, ps->n_launch, ps->dkeys, chist, cbins,
+                                   cblk, ps->dorder[1 - ps->cur], ps->dcount + (1 - ps->cur),
+                                   stream, true));
             ps->cur = 1 - ps->cur;
             SCHECK(lp::launch_iota(perm, (size_t)n, stream));
             hipLaunchKernelGGL(k_copy_list, dim3(nb), dim3(256), 0, stream, ps->dorder[ps->cur],
