@@ -937,6 +937,36 @@ struct Timer {
     }
 };
 
+// The phase boundaries of one inference segment (sort, network, coarse steps, check and
+// fine steps) as events, read back only once the stream has passed them anyway.
+struct SegmentEvents {
+    hipEvent_t e[5] = {};
+    bool sorted = false, live = false;
+    SegmentEvents() {
+        for (auto &x : e)
+            (void)hipEventCreate(&x);
+    }
+    ~SegmentEvents() {
+        for (auto &x : e)
+            if (x)
+                (void)hipEventDestroy(x);
+    }
+    void account(lp_surrogate_stats *st) {
+        if (!live)
+            return;
+        float ms = 0.f;
+        if (sorted && hipEventElapsedTime(&ms, e[0], e[1]) == hipSuccess)
+            st->sort_ms += ms;
+        if (hipEventElapsedTime(&ms, e[1], e[2]) == hipSuccess)
+            st->mlp_ms += ms;
+        if (hipEventElapsedTime(&ms, e[2], e[3]) == hipSuccess)
+            st->coarse_ms += ms;
+        if (hipEventElapsedTime(&ms, e[3], e[4]) == hipSuccess)
+            st->fine_ms += ms;
+        live = false;
+    }
+};
+
 struct DeviceBuf {
     std::vector<void *> p;
     ~DeviceBuf() {
@@ -1335,18 +1365,27 @@ extern "C" int pset_execute_surrogate(lp_pset *ps, lp_model *m, double runtime, 
     o.recovery = LP_DELETE;
     o.stencil_cache = 1;
     o.sort_every = 0;
-    Timer ttot, tm;
+    // The stream is synchronised once a segment, to read the rejected queue's length; the
+    // phase times of a segment are read after the next segment's synchronisation (two sets
+    // of events) and the active counts once at the end.
+    uint32_t *dna;
+    SCHECK(mem.get(&dna, (size_t)std::max<int64_t>(nseg, 1)));
+    SegmentEvents ev[2];
+    uint64_t nf_sum = 0;
+    Timer ttot;
     ttot.start(stream);
     for (int64_t q = 0; q < nseg && rc == LP_OK; ++q) {
         const double t = ps->t0 + (double)ps->step * dt;
         TimeEntry e{};
         if ((rc = lp_time_entry(fs, t, &e)))
             break;
+        SegmentEvents &E = ev[q & 1];
+        E.sorted = q % kSortSegments == 0;
         // the active list in cell order (cells within tiles), so that neighbouring rows
         // gather neighbouring patches (the fine and coarse twins inherit the order), and the
         // state moved into that order, so that the list becomes 0 .. active - 1
-        if (q % kSortSegments == 0) {
-            tm.start(stream);
+        if (E.sorted) {
+            SCHECK(hipEventRecord(E.e[0], stream));
             SCHECK(lp::launch_sort(fs->g, ps->dx, ps->dy, ps->dz, ps->dst, ps->dorder[ps->cur],
                                    ps->dcount + ps->cur, ps->n_launch, ps->dkeys, chist, cbins,
                                    cblk, ps->dorder[1 - ps->cur], ps->dcount + (1 - ps->cur),
@@ -1367,7 +1406,6 @@ extern "C" int pset_execute_surrogate(lp_pset *ps, lp_model *m, double runtime, 
             SCHECK(hipMemcpyAsync(ps->dy, ty, (size_t)n * 8, hipMemcpyDeviceToDevice, stream));
             SCHECK(hipMemcpyAsync(ps->dst, tst, (size_t)n, hipMemcpyDeviceToDevice, stream));
             SCHECK(lp::launch_iota(ps->dorder[ps->cur], (size_t)n, stream));
-            st->sort_ms += tm.stop_ms(stream);
         }
         const double ph = 2.0 * M_PI * std::fmod(t - t_lo, P) / P;
         const float phs[2] = {(float)std::sin(ph), (float)std::cos(ph)};
@@ -1375,7 +1413,7 @@ extern "C" int pset_execute_surrogate(lp_pset *ps, lp_model *m, double runtime, 
         SCHECK(hipMemcpyAsync(dphase, phs, 8, hipMemcpyHostToDevice, stream));
         const int c0 = ps->cur;
         // network on every active particle
-        tm.start(stream);
+        SCHECK(hipEventRecord(E.e[1], stream));
         FeatArgs fa{};
         make_feat(fs, fa);
         fa.x = ps->dx;
@@ -1391,9 +1429,8 @@ extern "C" int pset_execute_surrogate(lp_pset *ps, lp_model *m, double runtime, 
         SCHECK(hipGetLastError());
         if ((rc = forward(m, rows, false, stream)))
             break;
-        st->mlp_ms += tm.stop_ms(stream);
+        SCHECK(hipEventRecord(E.e[2], stream));
         // coarse RK4: two steps over the segment from the same state
-        tm.start(stream);
         SCHECK(hipMemcpyAsync(cs->dx, ps->dx, (size_t)n * 8, hipMemcpyDeviceToDevice, stream));
         SCHECK(hipMemcpyAsync(cs->dy, ps->dy, (size_t)n * 8, hipMemcpyDeviceToDevice, stream));
         SCHECK(hipMemcpyAsync(cs->dst, ps->dst, (size_t)n, hipMemcpyDeviceToDevice, stream));
@@ -1408,9 +1445,8 @@ extern "C" int pset_execute_surrogate(lp_pset *ps, lp_model *m, double runtime, 
         cs->step = 0;
         if ((rc = pset_execute(cs, seg_t, seg_t / 2, 0.0, &o, stream)))
             break;
-        st->coarse_ms += tm.stop_ms(stream);
+        SCHECK(hipEventRecord(E.e[3], stream));
         // residual check; the rest goes to the fine RK4 steps
-        tm.start(stream);
         SCHECK(hipMemsetAsync(nfall, 0, 4, stream));
         hipLaunchKernelGGL(k_check, dim3((ps->n_launch + kCheckThreads - 1) / kCheckThreads),
                            dim3(kCheckThreads), 0, stream,
@@ -1428,6 +1464,7 @@ extern "C" int pset_execute_surrogate(lp_pset *ps, lp_model *m, double runtime, 
         uint32_t nf = 0;
         SCHECK(hipMemcpyAsync(&nf, nfall, 4, hipMemcpyDeviceToHost, stream));
         SCHECK(hipStreamSynchronize(stream));
+        ev[(q + 1) & 1].account(st);  // the previous segment's events have all passed
         const uint32_t n_full = ps->n_launch;
         ps->n_launch = std::max(nf, 1u);
         rc = pset_execute(ps, seg_t, dt, 0.0, &o, stream);
@@ -1440,12 +1477,10 @@ extern "C" int pset_execute_surrogate(lp_pset *ps, lp_model *m, double runtime, 
         SCHECK(lp::launch_compact(full, saved_count, ps->dst, ps->dorder[1 - c0],
                                   ps->dcount + (1 - c0), ps->n_launch, stream));
         ps->cur = 1 - c0;
-        st->fine_ms += tm.stop_ms(stream);
-        uint32_t na = 0;
-        SCHECK(hipMemcpy(&na, saved_count, 4, hipMemcpyDeviceToHost));
-        st->evaluated += na;
-        st->fallback += nf;
-        st->accepted += (int64_t)na - (int64_t)nf;  // every active particle is one or the other
+        SCHECK(hipEventRecord(E.e[4], stream));
+        E.live = true;
+        SCHECK(hipMemcpyAsync(dna + q, saved_count, 4, hipMemcpyDeviceToDevice, stream));
+        nf_sum += nf;
         st->segments++;
     }
     pset_destroy(cs);
@@ -1465,5 +1500,14 @@ extern "C" int pset_execute_surrogate(lp_pset *ps, lp_model *m, double runtime, 
     if (rc)
         return rc;
     st->total_ms = ttot.stop_ms(stream);
+    ev[0].account(st);
+    ev[1].account(st);
+    std::vector<uint32_t> na((size_t)st->segments);
+    if (!na.empty())
+        SCHECK(hipMemcpy(na.data(), dna, na.size() * 4, hipMemcpyDeviceToHost));
+    for (uint32_t v : na)
+        st->evaluated += v;
+    st->fallback = (int64_t)nf_sum;
+    st->accepted = st->evaluated - st->fallback;  // every active particle is one or the other
     return LP_OK;
 }
