@@ -190,8 +190,12 @@ __global__ __launch_bounds__(kFeatBlock) void k_features(FeatArgs a)
 
 __device__ inline void feature_row(const FeatArgs &a, int64_t r, uint32_t P[32])
 {
+    // the hardware's round-to-nearest-even convert, one instruction per pair (the
+    // features are finite, so it rounds as to_bf16 does)
     auto pair = [](float lo, float hi) {
-        return (uint32_t)to_bf16(lo) | ((uint32_t)to_bf16(hi) << 16);
+        typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+        typedef float f32x2 __attribute__((ext_vector_type(2)));
+        return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{lo, hi}, bf16x2));
     };
     const uint32_t s = a.sel ? a.sel[r] : (uint32_t)r;
     const uint32_t rd = a.round ? a.round[s] : 0u;
