@@ -70,14 +70,14 @@ FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 COUNTER_SOURCE = "profiles/counters_k_advect2d_cfg1_k_advect3d_cfg2.md"
 COUNTERS = {
     "advect_sha256": "1ea8f1c0ae4467cbe4c7e173aa56b1fac7e4e7f70e3d23c6f5ff794d5a1d22d2",
-    "cfg1": (213071.9, 64604.5),    # (FETCH_SIZE KiB, WRITE_SIZE KiB) per launch of k_advect2d
-    "cfg2": (7802080.8, 286860.0),  # the same for k_advect3d
+    "cfg1": (184886.5, 64870.7),    # (FETCH_SIZE KiB, WRITE_SIZE KiB) per launch of k_advect2d
+    "cfg2": (7795847.0, 285050.6),  # the same for k_advect3d
     # (TCC_HIT_sum, TCC_MISS_sum) per launch: L2 requests of the same kernels
-    "cfg1_l2": (4150109.9, 4999941.8),
-    "cfg2_l2": (72072032.5, 127043086.2),
+    "cfg1_l2": (3888308.9, 4498870.4),
+    "cfg2_l2": (72086374.0, 126870815.5),
     # (SQ_INSTS_VALU, SQ_INSTS_SALU) wave instructions per launch
-    "cfg1_sq": (8.4575e+08, 4.75767e+08),
-    "cfg2_sq": (8.74234e+09, 3.32557e+09),
+    "cfg1_sq": (8.45743e+08, 4.75763e+08),
+    "cfg2_sq": (8.74235e+09, 3.32557e+09),
 }
 
 
