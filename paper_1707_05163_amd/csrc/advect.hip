@@ -1898,9 +1898,11 @@ __device__ inline typename Real<ST>::T node_var(const typename NodeWord3<ST>::T 
         return (v == 0 ? f16_lo(q.x) : (v == 1 ? f16_hi(q.x) : f16_lo(q.y))) * sc[v];
 }
 
-template <int ST, bool STEADY, bool DL>
+// With CARRY the cell keeps the coefficients at the stage time tau, a + tau d, in place of
+// the earlier snapshot's a (see stage3).
+template <int ST, bool STEADY, bool DL, bool CARRY = false>
 __device__ inline bool reload3(const AdvectParams &P, Cell3<typename Real<ST>::T, DL> &c, int sa,
-                               int sb, double x, double y, double z)
+                               int sb, double x, double y, double z, double tau = 0.0)
 {
     using R = typename Real<ST>::T;
     const AxisDev &ax = P.g.ax, &ay = P.g.ay, &az = P.g.az;
@@ -1987,8 +1989,12 @@ __device__ inline bool reload3(const AdvectParams &P, Cell3<typename Real<ST>::T
                 f[q] = node_var<ST>(wb[q], v, sc + (q >> 2) * 3);
             coeffs3<R>(f, cb);
 #pragma unroll
-            for (int q = 0; q < 8; ++q)
-                c.d(v, q) = cb[q] - c.a[v][q];
+            for (int q = 0; q < 8; ++q) {
+                const R dq = cb[q] - c.a[v][q];
+                c.d(v, q) = dq;
+                if constexpr (CARRY)
+                    c.a[v][q] = fma((R)tau, dq, c.a[v][q]);
+            }
         }
     }
     c.cl = kMetresPerDegree * clat;
@@ -2004,28 +2010,54 @@ __device__ inline bool in_cell3(const Cell3<R, DL> &c, const AdvectParams &P, do
     return x >= c.x0 && x < c.ux && y >= c.y0 && y < c.uy && z >= c.z0 && z < c.uz;
 }
 
+// With FP64 coefficients the cell carries the coefficients at the last stage's time,
+// c = a + tau d, and a stage at time tau' first advances them by (tau' - tau) d, then
+// evaluates one trilinear polynomial instead of two (the polynomial is linear in its
+// coefficients, so the value is the same up to rounding).  Every lane of a launch shares
+// the stage times, so tau_prev, the previous stage's time, is one value for the wave; a
+// lane that reloads here gets its coefficients at tau' from the reload and skips the
+// advance, and stages at the previous stage's time (the first and third of RK4; the
+// last stage of a step and the first of the next share a time) skip it for the whole
+// wave: per step two advances of 24 products instead of four second polynomials.
 template <int ST, bool STEADY, int MET, bool DL>
 __device__ inline bool stage3(const AdvectParams &P, Cell3<typename Real<ST>::T, DL> &c,
                               const TimeEntry &e, bool fresh, double x, double y, double z,
-                              double k[3])
+                              double k[3], double tau_prev)
 {
     using R = typename Real<ST>::T;
-    if (!in_cell3(c, P, x, y, z) | fresh) {
-        if (!reload3<ST, STEADY, DL>(P, c, e.sa, e.sb, x, y, z))
+    constexpr bool CARRY = !STEADY && sizeof(R) == 8;
+    const bool re = !in_cell3(c, P, x, y, z) | fresh;
+    if (re) {
+        if (!reload3<ST, STEADY, DL, CARRY>(P, c, e.sa, e.sb, x, y, z, e.tau))
             return false;
     }
     const R xi = (R)((x - c.x0) * c.rx), eta = (R)((y - c.y0) * c.ry);
     const R zeta = (R)((z - c.z0) * c.rz);
     R v[3];
+    if constexpr (CARRY) {
+        const double dtau = e.tau - tau_prev;
+        if (dtau != 0.0) {
+            const R dl = re ? (R)0 : (R)dtau;
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        v[q] = poly3<R>(c.a[q], xi, eta, zeta);
-        if constexpr (!STEADY) {
-            R dq[8];
+            for (int q = 0; q < 3; ++q)
 #pragma unroll
-            for (int i = 0; i < 8; ++i)
-                dq[i] = c.d(q, i);
-            v[q] = fma((R)e.tau, poly3<R>(dq, xi, eta, zeta), v[q]);
+                for (int i = 0; i < 8; ++i)
+                    c.a[q][i] = fma(dl, c.d(q, i), c.a[q][i]);
+        }
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+            v[q] = poly3<R>(c.a[q], xi, eta, zeta);
+    } else {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            v[q] = poly3<R>(c.a[q], xi, eta, zeta);
+            if constexpr (!STEADY) {
+                R dq[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    dq[i] = c.d(q, i);
+                v[q] = fma((R)e.tau, poly3<R>(dq, xi, eta, zeta), v[q]);
+            }
         }
     }
     if constexpr (MET != kFlat) {
@@ -2069,6 +2101,7 @@ __attribute__((amdgpu_waves_per_eu(cache3_lds<ST, STEADY, MET, BROWN>() ? (sizeo
             if constexpr (DL)
                 c.dl = cache3_slot_ptr<R>();
             const double dt = P.dt, dt6 = P.dt6;
+            double tau_prev = P.tab[0].tau;  // the time of the cell's coefficients (stage3)
             for (int s = 0; s < P.nsteps; ++s) {
                 ++steps;
                 const TimeEntry e0 = P.tab[2 * s], e1 = P.tab[2 * s + 1], e2 = P.tab[2 * s + 2];
@@ -2102,7 +2135,9 @@ __attribute__((amdgpu_waves_per_eu(cache3_lds<ST, STEADY, MET, BROWN>() ? (sizeo
                     // half step comes in with the launch, as a scalar operand)
                     const double h = q == 3 ? dt : P.hdt;
                     ok = stage3<ST, STEADY, MET, DL>(P, c, e, moves.at(q), x + k[0] * h,
-                                                     y + k[1] * h, z + k[2] * h, k) & ok;
+                                                     y + k[1] * h, z + k[2] * h, k, tau_prev) &
+                         ok;
+                    tau_prev = e.tau;
                     const double wq = q == 0 ? 1.0 : (q == 3 ? 0.0 : 2.0);
 #pragma unroll
                     for (int v = 0; v < 3; ++v)
