@@ -69,15 +69,15 @@ STATE_BYTES_RKF45_2D = STATE_BYTES_2D + 2  # plus the step exponent read and wri
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 COUNTER_SOURCE = "profiles/counters_k_advect2d_cfg1_k_advect3d_cfg2.md"
 COUNTERS = {
-    "advect_sha256": "1ea8f1c0ae4467cbe4c7e173aa56b1fac7e4e7f70e3d23c6f5ff794d5a1d22d2",
-    "cfg1": (184886.5, 64870.7),    # (FETCH_SIZE KiB, WRITE_SIZE KiB) per launch of k_advect2d
-    "cfg2": (7795847.0, 285050.6),  # the same for k_advect3d
+    "advect_sha256": "07a8e58413fc66a254fc93aeedf8de7f10067d808f557bdb13fd324019b54e0c",
+    "cfg1": (185046.8, 64867.8),    # (FETCH_SIZE KiB, WRITE_SIZE KiB) per launch of k_advect2d
+    "cfg2": (7774787.2, 246243.9),  # the same for k_advect3d
     # (TCC_HIT_sum, TCC_MISS_sum) per launch: L2 requests of the same kernels
-    "cfg1_l2": (3888308.9, 4498870.4),
-    "cfg2_l2": (72086374.0, 126870815.5),
+    "cfg1_l2": (3889879.5, 4499888.4),
+    "cfg2_l2": (71593672.8, 126480295.3),
     # (SQ_INSTS_VALU, SQ_INSTS_SALU) wave instructions per launch
     "cfg1_sq": (8.45743e+08, 4.75763e+08),
-    "cfg2_sq": (8.74235e+09, 3.32557e+09),
+    "cfg2_sq": (8.06692e+09, 3.03271e+09),
 }
 
 
