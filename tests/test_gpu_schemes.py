@@ -57,6 +57,17 @@ def test_cfg1_small_schemes(kernel, interp, cache):
                        ofs=ofs)
 
 
+def test_euler_3d():
+    """Euler forward on the cached 3D kernel: one stage a step, each at a new time, so the
+    coefficients the cell carries at the last stage's time advance at every stage (RK4's
+    first and third stages skip it)."""
+    w = SC.cfg2_global_3d(nx=180, ny=90, nz=20, nt=3, n_particles=4000, nsteps=144)
+    ps, recs, orecs, ofs, st = _run_both(w, w.dt, w.nsteps * w.dt, 6 * 3600.0, kernel="euler")
+    for m, o in enumerate(orecs):
+        compare_record(slice_record(recs, m), o, w.grid, 360.0, label=f"euler3d rec {m}",
+                       ofs=ofs)
+
+
 def test_nearest_3d():
     w = SC.cfg2_global_3d(nx=180, ny=90, nz=20, nt=3, n_particles=4000, nsteps=144)
     ps, recs, orecs, ofs, st = _run_both(w, w.dt, w.nsteps * w.dt, 6 * 3600.0, interp="nearest")
